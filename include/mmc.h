@@ -1,0 +1,216 @@
+/*
+ * mmc.h -- C ABI of the MI355X (gfx950) multipath Metropolis engine for the classical
+ * O(3) Heisenberg model.
+ *
+ * Method (arXiv:1305.6758, Sec. 2): many mutually independent simulation paths on a
+ * periodic simple-cubic lattice of N = L^3 unit spins with energy eq. (ham),
+ * H = -(J/2) sum_n sum_lambda S_n . S_{n+lambda}. Each path starts from a random state,
+ * is thermalised and measured with single-spin Metropolis moves, and outputs its per-site
+ * magnetisation M and energy; the cross-path averages of eq. (MCAV) and eq. (M_and_H),
+ * the moments <|M|^k>, eq. (cv), eq. (kum), eq. (dist-coefficient) and eq. (eq:cv) are the
+ * simulation results.
+ *
+ * Engine conventions (the paper leaves these open):
+ *   - proposal: a new spin uniform on the sphere, independent of the old one
+ *     (cos(theta) = 2 u0 - 1, phi = 2 pi u1); acceptance: u2 < exp(-beta dE), beta = 1/T;
+ *   - random numbers: Philox4x32-10 (Salmon et al., SC'11) on the counter
+ *     (site id, sweep, path, tag | instance_id << 8) with key (seed_lo, seed_hi); tag 0 for
+ *     the initial state (sweep word 0), tag 1 for the Metropolis move; site id
+ *     i = x + L (y + L z);
+ *   - sweep: checkerboard, sites with (x + y + z) even first, then the odd ones;
+ *   - FP32 mode: spins, fields and the acceptance exponential in FP32 (uniforms with 23
+ *     random bits, ((w >> 8) | 1) 2^-24), spins renormalised every renorm_every sweeps;
+ *     FP64 mode: uniforms (w + 1/2) 2^-32 and IEEE FP64 arithmetic without contraction,
+ *     the form that reproduces an FP64 reference trajectory; all per-path accumulators and
+ *     cross-path statistics are FP64 in both modes;
+ *   - measurements after every sweep k >= n_therm: e = E/N, m = |M| (M per site), and the
+ *     time means of e, e^2, m, m^2, m^4; the final state's {M^x, M^y, M^z, E/N}, which is
+ *     the per-path output of Sec. 2.2.
+ *
+ * Errors: every call returns a status (mmc_status) or NULL and never aborts; the reason of
+ * the last failure on the calling thread is in mmc_last_error(). Contexts are
+ * thread-compatible: one context must not be used by two threads at once.
+ * Ownership: the caller owns every host buffer it passes in; the library owns its contexts
+ * and, unless mmc_bind() supplies memory, the device memory they use.
+ */
+#ifndef MMC_H
+#define MMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mmc_ctx mmc_ctx;
+
+typedef enum {
+    MMC_OK = 0,
+    MMC_EINVAL = -1,       /* an argument is out of range */
+    MMC_ENOMEM = -2,       /* device or host allocation failed, or a bound buffer is too small */
+    MMC_EHIP = -3,         /* a HIP runtime call failed (no GPU, launch failure, ...) */
+    MMC_ESTATE = -4,       /* call not valid in the context's current state */
+    MMC_EUNSUPPORTED = -5, /* valid request the engine does not implement */
+    MMC_EIO = -6           /* file read/write failed or the file is not a checkpoint */
+} mmc_status;
+
+typedef enum { MMC_FP32 = 0, MMC_FP64 = 1 } mmc_precision;
+
+/* Initial state (Sec. 2.2): SPHERE draws each spin uniformly on the sphere; ANGLES draws
+ * both spherical angles uniformly (the paper's literal "random values of both angles");
+ * ORDERED starts with every spin along +z. */
+typedef enum { MMC_INIT_SPHERE = 0, MMC_INIT_ANGLES = 1, MMC_INIT_ORDERED = 2 } mmc_init;
+
+/* Where a path's spins live during a sweep. LDS: the whole lattice of one path in the
+ * workgroup's LDS. HBM: spins in device memory, one workgroup per path, sweeps inside
+ * one launch. PLAIN: the plain FP64 engine, one launch per half-sweep and one thread per
+ * site (FP64 only). AUTO: the tuner decides. */
+typedef enum { MMC_PLACE_AUTO = 0, MMC_PLACE_LDS = 1, MMC_PLACE_HBM = 2, MMC_PLACE_PLAIN = 3 } mmc_placement;
+
+/* Zero-initialised = defaults. */
+typedef struct {
+    int precision;      /* mmc_precision, default MMC_FP32 */
+    int init;           /* mmc_init, default MMC_INIT_SPHERE */
+    int placement;      /* mmc_placement, default MMC_PLACE_AUTO */
+    int block;          /* threads per workgroup; 0 lets the tuner choose */
+    int lanes_per_path; /* threads working on one path; 0 lets the tuner choose */
+    int renorm_every;   /* FP32: renormalise every k sweeps; 0 means 64; < 0 never */
+    uint32_t instance_id; /* enters Philox counter word 3 (bits 8..31); < 2^24 */
+    int trace_sweeps;   /* record (e_k, M_k) for sweeps k < trace_sweeps */
+    int async;          /* nonzero: mmc_run/mmc_batch_run return without waiting */
+} mmc_config;
+
+/* Per-path output. Means over the n_meas measured sweeps (NaN when n_meas = 0), per site:
+ * e = E/N, m = |M|. final_* is the state after the last sweep run so far. */
+typedef struct {
+    double e_mean, e2_mean, absm_mean, m2_mean, m4_mean;
+    double final_m[3], final_e;
+    uint64_t n_accept;  /* accepted moves over all sweeps run */
+} mmc_path_result;
+
+/* Cross-path statistics (FP64, host). With <.> the mean over paths of the per-path time
+ * means: mean_e = <e>, mean_absm = <m> (standard errors over paths, n - 1),
+ * e2 = <e^2>, m2 = <m^2>, m4 = <m^4>, chi = (N/T)(m2 - mean_absm^2) and
+ * cv_heat = (N/T^2)(e2 - mean_e^2) per eq. (cv), binder = 1 - m4/(3 m2^2) per eq. (kum),
+ * cv_absm = coefficient of variation of the mean of m per eq. (eq:cv), r_* = distribution
+ * coefficient of eq. (dist-coefficient) of the per-path means (Q-Q least-squares line at
+ * Filliben plotting positions), p_norm_* = D'Agostino-Pearson K^2 p-value (NaN when
+ * n < 20), accept_rate = accepted / attempted moves. */
+typedef struct {
+    int64_t n;
+    double mean_e, se_e, mean_absm, se_absm;
+    double e2, m2, m4;
+    double chi, cv_heat, binder, cv_absm;
+    double r_e, r_absm, p_norm_e, p_norm_absm;
+    double accept_rate;
+} mmc_stats_t;
+
+/* One instance of a batch. */
+typedef struct {
+    int L;
+    double T, J;
+    int n_paths, n_therm, n_meas;
+} mmc_instance;
+
+/* Creates a single-instance context: L even and >= 2 (the checkerboard needs a bipartite
+ * periodic lattice), T > 0 (T = +inf allowed: beta = 0), J finite, n_paths >= 1,
+ * n_therm >= 0, n_meas >= 0, n_therm + n_meas < 2^31. Nothing runs on the GPU until
+ * mmc_run. Returns NULL on error (see mmc_last_error). Defaults as documented in
+ * mmc_config. */
+mmc_ctx *mmc_create(int L, double T, double J, int n_paths, int n_therm, int n_meas, uint64_t seed);
+
+/* As mmc_create with a configuration (cfg may be NULL). */
+mmc_ctx *mmc_create_ex(int L, double T, double J, int n_paths, int n_therm, int n_meas,
+                       uint64_t seed, const mmc_config *cfg);
+
+/* Message of the last failed call on this thread ("" if none). Owned by the library. */
+const char *mmc_last_error(void);
+
+/* Device bytes the context needs (spin state, accumulators, trace, queue). */
+size_t mmc_workspace_bytes(const mmc_ctx *ctx);
+
+/* Hands the context caller-owned device memory of at least mmc_workspace_bytes() bytes,
+ * 256-byte aligned, and a HIP stream (NULL: the null stream). The memory must outlive
+ * the context and must not be used by anyone else meanwhile. Without this call the first
+ * run allocates its own memory with hipMalloc and uses the null stream. Only valid before
+ * the first run. */
+int mmc_bind(mmc_ctx *ctx, void *dev_ptr, size_t bytes, void *hip_stream);
+
+/* Chooses the kernel variant (placement, block, lanes per path) by timing every candidate
+ * on a short run, unless the configuration fixed it or the tuning cache (in memory, and in
+ * the JSON file named by the environment variable MMC_TUNE_CACHE if set) has an entry.
+ * Called by the first run when needed; leaves the context in its initial state. */
+int mmc_tune(mmc_ctx *ctx);
+
+/* Runs all remaining sweeps (from the initial random state on the first call). The HIP
+ * work of one run is one captured hipGraph launch. Blocks until done unless cfg.async. */
+int mmc_run(mmc_ctx *ctx);
+
+/* Advances every path by k more sweeps (k >= 1, not past n_therm + n_meas). */
+int mmc_run_sweeps(mmc_ctx *ctx, int k);
+
+/* Waits for the context's outstanding work (for cfg.async). */
+int mmc_sync(mmc_ctx *ctx);
+
+/* Returns the context to its initial state (no sweep run), keeping memory and plan. */
+int mmc_reset(mmc_ctx *ctx);
+
+/* Sweeps completed so far, or a negative status. */
+int mmc_sweeps_done(const mmc_ctx *ctx);
+
+/* Copies the per-path results of all n_paths paths to out (caller-owned, n_out >= n_paths). */
+int mmc_results(const mmc_ctx *ctx, mmc_path_result *out, int n_out);
+
+/* Copies the trace: out[path][k][4] = (e_k, Mx_k, My_k, Mz_k), per site, for
+ * k < trace_sweeps; rows of sweeps not run yet are NaN. n_out = number of doubles in out,
+ * at least n_paths * trace_sweeps * 4. */
+int mmc_trace(const mmc_ctx *ctx, double *out, size_t n_out);
+
+/* Copies the current spins of one path as FP64, xyz[3*i + a] for site id i (x fastest). */
+int mmc_get_spins(const mmc_ctx *ctx, int path, double *xyz, size_t n_out);
+
+/* Cross-path statistics of the current results. */
+int mmc_stats(const mmc_ctx *ctx, mmc_stats_t *out);
+
+/* Statistics of any result array (host only, no GPU needed); N = L^3. */
+int mmc_stats_from_results(const mmc_path_result *res, int n, int L, double T, mmc_stats_t *out);
+
+/* Writes a checkpoint (configuration, plan, sweeps done, spins, accumulators, trace). */
+int mmc_save(const mmc_ctx *ctx, const char *file);
+
+/* Creates a context from a checkpoint; a later run continues bit-identically to a run
+ * that was never interrupted (the random numbers are counter-based: no RNG state). */
+mmc_ctx *mmc_load(const char *file);
+
+/* Wall time of the last run's GPU work in milliseconds (hipEvents on the context's stream). */
+double mmc_last_timing_ms(const mmc_ctx *ctx);
+
+/* Human-readable description of the chosen kernel variant(s), NUL-terminated. */
+int mmc_plan(const mmc_ctx *ctx, char *buf, size_t n);
+
+/* Frees the context and the device memory it allocated. NULL is ignored. */
+void mmc_destroy(mmc_ctx *ctx);
+
+/* Batch of n_inst independent instances (uneven L, T, path counts) run by one persistent,
+ * hipGraph-captured launch: workgroups take (instance, path group) items, largest first,
+ * from a device work queue. Each instance uses Philox instance word = its index in inst[]
+ * (cfg->instance_id is ignored). Precision from cfg (FP32 default). Spin state exists only
+ * for items in flight, so mmc_get_spins, mmc_trace, mmc_run_sweeps and mmc_save are not
+ * available on a batch. */
+mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, const mmc_config *cfg);
+
+/* Runs the whole batch (all sweeps of all instances). */
+int mmc_batch_run(mmc_ctx *ctx);
+
+/* Per-path results of instance inst (n_out >= its n_paths). */
+int mmc_batch_results(const mmc_ctx *ctx, int inst, mmc_path_result *out, int n_out);
+
+/* Statistics of instance inst. */
+int mmc_batch_stats(const mmc_ctx *ctx, int inst, mmc_stats_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMC_H */

@@ -1,0 +1,53 @@
+"""Seeded synthetic workloads of the benchmark and the parity tests.
+
+Input recipes only -- no simulation arithmetic. The paper uses no dataset: every input is a
+lattice size, temperatures, path and sweep counts, a seed and an instance id; the random
+starts and moves come from the counter-based generator inside the engine and inside the
+oracle. All use J = 1 (the paper's energy scale, Sec. 2.1) and seed 1234.
+
+Instance ids: a workload with several (L, T) instances numbers them 0, 1, ... in the order
+listed here; the id enters the random-number counter, so instance i of a batch and a
+single-instance run with instance_id = i draw the same numbers.
+"""
+import numpy as np
+
+SEED = 1234
+J = 1.0
+
+# One-GPU workloads. "instances": list of (L, T, n_paths, n_therm, n_meas).
+WORKLOADS = {
+    # L = 8, FP64, the trajectory-parity case.
+    "L8-T1.5-p64-fp64": dict(precision="fp64", instances=[(8, 1.5, 64, 1000, 1000)]),
+    # L = 16 at three temperatures around T_c, 4096 paths each, FP32 spins in LDS.
+    "L16-T3-p4096-fp32": dict(precision="fp32", instances=[(16, T, 4096, 2000, 8000) for T in (1.2, 1.443, 1.7)]),
+    # L = 32 at T = 1.443, 1024 paths, device-memory spins, run in FP32 and in FP64.
+    "L32-T1.443-p1024": dict(precision="both", instances=[(32, 1.443, 1024, 5000, 5000)]),
+    # L = 64 at T = 1.443, 256 paths, device-memory spins, FP32.
+    "L64-T1.443-p256-fp32": dict(precision="fp32", instances=[(64, 1.443, 256, 10000, 10000)]),
+}
+
+BATCH_LS = (8, 12, 16, 24, 32, 48)
+BATCH_TS = tuple(float(t) for t in np.linspace(1.0, 2.0, 16))
+
+
+def uneven_batch():
+    """The uneven batch: L in {8, 12, 16, 24, 32, 48} x 16 temperatures evenly spaced on
+    [1, 2] (both ends included), paths per instance drawn uniformly from [64, 2048] with
+    numpy's default_rng(1234) in (L, T) order, 2000 thermalisation + 2000 measured sweeps."""
+    rng = np.random.default_rng(SEED)
+    paths = rng.integers(64, 2049, size=len(BATCH_LS) * len(BATCH_TS))
+    out = []
+    k = 0
+    for L in BATCH_LS:
+        for T in BATCH_TS:
+            out.append((L, T, int(paths[k]), 2000, 2000))
+            k += 1
+    return out
+
+
+WORKLOADS["uneven-batch-96-fp32"] = dict(precision="fp32", instances=uneven_batch())
+
+
+def updates(instances):
+    """Metropolis attempts of a workload: sum over instances of paths * L^3 * sweeps."""
+    return sum(p * L ** 3 * (nt + nm) for (L, T, p, nt, nm) in instances)
