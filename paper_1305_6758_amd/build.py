@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmmc.so")
+OPBENCH_LIB = os.path.join(HERE, "libmmc_opbench.so")
 ARCH = "gfx950"
 
 # No fused multiply-add unless written (the FP64 path must reproduce an FP64 reference
@@ -40,6 +41,12 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    # instruction-rate microbenchmark (measurement tool, separate from the engine)
+    cmd = ["hipcc", *FLAGS, "-shared", os.path.join(CSRC, "opbench.hip"), "-o", OPBENCH_LIB + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed on opbench.hip:\n" + r.stderr)
+    os.replace(OPBENCH_LIB + ".tmp", OPBENCH_LIB)
     return LIB
 
 

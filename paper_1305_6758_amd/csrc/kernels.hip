@@ -28,24 +28,53 @@ constexpr uint32_t PHI_W0 = 0x9E3779B9u, PHI_W1 = 0xBB67AE85u;
 
 struct Words { uint32_t w0, w1, w2, w3; };
 
-// Ten rounds; each round takes the two 64-bit products apart and xors in the key, then the
-// key moves along the Weyl sequence. With counter words 1-3 and the key wave-uniform, the
-// compiler keeps their part of the first two rounds on the scalar unit.
-__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1)
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+
+// a ^ b ^ c in one VALU instruction (gfx950 v_bitop3_b32, truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
+
+// Philox4x32-10. One round maps (w0, w1, w2, w3) to
+// (hi(M1 w2) ^ w1 ^ k0, lo(M1 w2), hi(M0 w0) ^ w3 ^ k1, lo(M0 w0)); the key then moves along
+// the Weyl sequence (k0, k1) += (W0, W1). Only c0 (the site) differs between the lanes of a
+// wave, so the first two rounds are spelled out to keep their wave-uniform half (c1, c2, c3,
+// key) on the scalar unit; later rounds use one three-way xor per output word.
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                               uint32_t k1)
 {
+    uint64_t p0 = (uint64_t)PHI_M0 * c0;
+    uint64_t p1 = (uint64_t)PHI_M1 * c2;  // uniform
+    const uint32_t a0 = hi32(p1) ^ c1 ^ k0;  // uniform
+    const uint32_t a1 = (uint32_t)p1;        // uniform
+    const uint32_t a2 = hi32(p0) ^ (c3 ^ k1);
+    const uint32_t a3 = (uint32_t)p0;
+    k0 += PHI_W0;
+    k1 += PHI_W1;
+    p0 = (uint64_t)PHI_M0 * a0;  // uniform
+    p1 = (uint64_t)PHI_M1 * a2;
+    const uint32_t b0 = hi32(p1) ^ (a1 ^ k0);
+    const uint32_t b1 = (uint32_t)p1;
+    const uint32_t b2 = a3 ^ (hi32(p0) ^ k1);
+    const uint32_t b3 = (uint32_t)p0;  // uniform
+    k0 += PHI_W0;
+    k1 += PHI_W1;
+    p0 = (uint64_t)PHI_M0 * b0;
+    p1 = (uint64_t)PHI_M1 * b2;
+    c0 = xor3(hi32(p1), b1, k0);
+    c1 = (uint32_t)p1;
+    c2 = hi32(p0) ^ (b3 ^ k1);
+    c3 = (uint32_t)p0;
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)PHI_M0 * c0;
-        const uint64_t p1 = (uint64_t)PHI_M1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    for (int r = 3; r < 10; ++r) {
+        k0 += PHI_W0;
+        k1 += PHI_W1;
+        p0 = (uint64_t)PHI_M0 * c0;
+        p1 = (uint64_t)PHI_M1 * c2;
+        const uint32_t n0 = xor3(hi32(p1), c1, k0);
+        const uint32_t n2 = xor3(hi32(p0), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
         c2 = n2;
-        k0 += PHI_W0;
-        k1 += PHI_W1;
     }
     return {c0, c1, c2, c3};
 }
@@ -53,20 +82,20 @@ __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 // ------------------------------------------------------------------ precision policies
 template <typename T> struct Arith;
 
-// FP32: uniforms with 23 random bits, ((w >> 8) | 1) 2^-24, exact in FP32 and never 0 or 1;
-// transcendental unit for sqrt, sin, cos (argument in revolutions) and exp2.
+// FP32: uniforms with 23 random bits, u = ((w >> 8) | 1) 2^-24, exact and never 0 or 1: the
+// bit pattern 0x3F800000 | (w >> 9) (one alignbit) is 1 + (w >> 9) 2^-23, and subtracting
+// 1 - 2^-24 from it is exact. Transcendental unit for sqrt, sin and cos (argument in
+// revolutions, so phi / (2 pi) = u1 goes in directly) and exp2.
 template <> struct Arith<float> {
-    static __device__ __forceinline__ float uni(uint32_t w) { return (float)((w >> 8) | 1u) * 0x1p-24f; }
-    // 2u - 1 for the same u, exact: ((w >> 8) | 1) - 2^23 as a signed integer, times 2^-23.
-    static __device__ __forceinline__ float sym(uint32_t w)
+    static __device__ __forceinline__ float uni(uint32_t w)
     {
-        return (float)(((int32_t)(w ^ 0x80000000u) >> 8) | 1) * 0x1p-23f;
+        return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9)) - 0x1.fffffep-1f;
     }
     static __device__ __forceinline__ void sphere(uint32_t w0, uint32_t w1, float &x, float &y, float &z)
     {
-        const float zz = sym(w0);
+        const float zz = fmaf(2.0f, uni(w0), -1.0f);  // 2 u0 - 1, exact
         const float r = __builtin_amdgcn_sqrtf(fmaf(-zz, zz, 1.0f));
-        const float rev = uni(w1);  // phi / (2 pi)
+        const float rev = uni(w1);
         x = r * __builtin_amdgcn_cosf(rev);
         y = r * __builtin_amdgcn_sinf(rev);
         z = zz;
@@ -79,11 +108,6 @@ template <> struct Arith<float> {
         x = st * __builtin_amdgcn_cosf(ph);
         y = st * __builtin_amdgcn_sinf(ph);
         z = __builtin_amdgcn_cosf(th);
-    }
-    // accept iff u < exp(beta J dot), dot = (S' - S) . h; q = beta J log2(e) precomputed.
-    static __device__ __forceinline__ bool accept(uint32_t w2, float dot, float q)
-    {
-        return uni(w2) < __builtin_amdgcn_exp2f(q * dot);
     }
 };
 
@@ -112,26 +136,65 @@ template <> struct Arith<double> {
     }
 };
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
+// ------------------------------------------------------------------ wave reductions
+template <int CTRL>
+__device__ __forceinline__ float dpp_plus(float v)
+{
+    const int s = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false);
+    return v + __int_as_float(s);
+}
+
+// Sum over the 16 lanes of each DPP row, left in every lane of the row.
+__device__ __forceinline__ float row_sum(float v)
+{
+    v = dpp_plus<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_plus<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_plus<0x141>(v);  // row_half_mirror
+    v = dpp_plus<0x140>(v);  // row_mirror
+    return v;
+}
+
+// Sum over the 64 lanes of the wave (wave-uniform result).
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v = row_sum(v);
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
+// Sum over the first 16 lanes (lanes >= n contribute 0): result valid in lane 0.
+__device__ __forceinline__ float first_lanes_sum(float v) { return row_sum(v); }
+
+__device__ __forceinline__ double first_lanes_sum(double v)
+{
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 enum Map { COLZ = 0, FLAT = 1 };
 
-// Everything a path group needs during its sweeps.
+// Everything a path group needs during its sweeps; path, key and counter word are
+// wave-uniform (each wave belongs to one path group).
 template <typename T>
 struct GroupCtx {
-    const InstDev *in;
-    int path;
-    bool active;       // path < n_paths
-    int lane;          // 0 .. G-1
-    T *sp;             // spins of this path while sweeping (LDS or device memory)
-    double *shacc;     // 16 doubles in LDS: the path's PathAcc while sweeping
-    T *red;            // LDS [waves of the group][4] measurement partials
+    int L;                            // side (runtime copy; kernels with a compile-time L use that)
+    uint32_t path, key0, key1, ctr3;  // ctr3 = instance << 8 (tag added per use)
+    bool active;                      // path < n_paths
+    int lane;                         // 0 .. G-1
+    T *sp;                            // spins of this path while sweeping (LDS or device memory)
+    double *shacc;                    // 16 doubles in LDS: the path's PathAcc while sweeping
+    T *red;                           // LDS [waves of the group][4] measurement partials
 };
 
 // Site geometry of one update: half-index h, site id, and the six neighbour half-indices
@@ -164,16 +227,29 @@ __device__ __forceinline__ Site make_site(int L, int j, int y, int z, int c)
     return s;
 }
 
-// One Metropolis attempt at site s of colour c, sweep k. Returns whether it was accepted
-// and adds the new spin (and, for the odd colour, S . h) to the measurement partials.
-template <typename T>
-__device__ __forceinline__ bool update_site(const GroupCtx<T> &g, int HALF, int c, const Site &s, uint32_t k,
-                                            T beta, T J, T q, T &pe, T &pmx, T &pmy, T &pmz)
+__device__ __forceinline__ Site flat_site(int L, int h, int c)
 {
-    T *own = g.sp + (c ? 3 * HALF : 0);
-    const T *oth = g.sp + (c ? 0 : 3 * HALF);
-    const InstDev &in = *g.in;
-    const Words w = philox4x32_10((uint32_t)s.id, k, (uint32_t)g.path, TAG_MET | in.ctr3, in.key0, in.key1);
+    const int HL = L >> 1, PLANE = HL * L;
+    const int col = h % PLANE;
+    return make_site(L, col % HL, col / HL, h / PLANE, c);
+}
+
+// Coefficients of the acceptance test.
+template <typename T>
+struct Coef {
+    T beta, J;  // FP64 path
+    float q;    // FP32 path: beta J log2(e)
+};
+
+// One Metropolis attempt at site s of colour c (own = this colour's spins, oth = the other
+// colour's), sweep k. Adds the resulting spin (and for the odd colour S . h) to the
+// measurement partials and the accepted count of the wave to nacc.
+template <typename T>
+__device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const T *oth, int HALF, bool odd,
+                                            const Site &s, uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy,
+                                            T &pmz, unsigned long long &nacc)
+{
+    const Words w = philox4x32_10((uint32_t)s.id, k, g.path, TAG_MET | g.ctr3, g.key0, g.key1);
     const T sx = own[s.h], sy = own[HALF + s.h], sz = own[2 * HALF + s.h];
     T hx, hy, hz;
     if constexpr (std::is_same<T, double>::value) {
@@ -206,61 +282,124 @@ __device__ __forceinline__ bool update_site(const GroupCtx<T> &g, int HALF, int 
     bool acc;
     if constexpr (std::is_same<T, double>::value) {
         // dE = -J ((dx hx + dy hy) + dz hz); accept iff u < exp(-beta dE).
-        const double dE = -J * ((dx * hx + dy * hy) + dz * hz);
-        acc = Arith<double>::uni(w.w2) < exp(-beta * dE);
+        const double dE = -cf.J * ((dx * hx + dy * hy) + dz * hz);
+        acc = Arith<double>::uni(w.w2) < exp(-cf.beta * dE);
     } else {
+        // -beta dE = beta J (S' - S) . h; accept iff u < 2^(beta J log2(e) (S' - S) . h).
         const float dot = fmaf(dz, hz, fmaf(dy, hy, dx * hx));
-        acc = Arith<float>::accept(w.w2, dot, q);
+        acc = Arith<float>::uni(w.w2) < __builtin_amdgcn_exp2f(cf.q * dot);
     }
-    T fx = sx, fy = sy, fz = sz;
     if (acc) {
         own[s.h] = nx;
         own[HALF + s.h] = ny;
         own[2 * HALF + s.h] = nz;
-        fx = nx;
-        fy = ny;
-        fz = nz;
     }
+    const T fx = acc ? nx : sx, fy = acc ? ny : sy, fz = acc ? nz : sz;
     pmx += fx;
     pmy += fy;
     pmz += fz;
-    if (c) {
+    if (odd) {
         if constexpr (std::is_same<T, double>::value) pe = pe + ((fx * hx + fy * hy) + fz * hz);
         else pe = fmaf(fz, hz, fmaf(fy, hy, fmaf(fx, hx, pe)));
     }
-    return acc;
+    nacc += (unsigned long long)__popcll(__ballot(acc));
 }
 
-// Calls f(Site) for every site of colour c owned by this lane.
-//   COLZ: a lane owns whole columns (fixed x, y) and a stride of z: for G >= plane
-//   (plane = L^2/2 sites of one colour), lane = column + plane * z0 and z = z0 + DZ t with
-//   DZ = G / plane; for G < plane the lane owns columns lane + G t and every z.
-//   FLAT: lane owns half-indices lane + G s (any L, ragged tail allowed).
-template <int LC, int G, int MAP, typename F>
-__device__ __forceinline__ void for_own_sites(int Lrt, int lane, int c, F &&f)
+// Geometry of one column (fixed j and y) of colour c: everything but z.
+struct Column {
+    int hcol;    // j + (L/2) y
+    int idcol;   // 2 j + L y
+    int par;     // (y + c) & 1: x-parity is (par + z) & 1
+    int dxm0;    // x-1 neighbour minus h when the x-parity is 0 (else 0)
+    int dxp1;    // x+1 neighbour minus h when the x-parity is 1 (else 0)
+    int dym, dyp;
+};
+
+__device__ __forceinline__ Column make_column(int L, int col, int c)
 {
-    const int L = LC ? LC : Lrt;
-    const int HL = L >> 1, PLANE = HL * L, HALF = PLANE * L;
-    if constexpr (MAP == COLZ) {
-        if (G >= PLANE) {
-            const int DZ = G / PLANE;
+    const int HL = L >> 1;
+    const int j = col % HL, y = col / HL;
+    Column k;
+    k.hcol = col;
+    k.idcol = 2 * j + L * y;
+    k.par = (y + c) & 1;
+    k.dxm0 = (j == 0) ? HL - 1 : -1;
+    k.dxp1 = (j == HL - 1) ? -(HL - 1) : 1;
+    k.dym = (y == 0) ? (L - 1) * HL : -HL;
+    k.dyp = (y == L - 1) ? -(L - 1) * HL : HL;
+    return k;
+}
+
+// Site z of a column; dzm / dzp: half-index offsets of the z-1 / z+1 neighbours (they differ
+// from -plane / +plane only on the wrap-around planes).
+template <int L>
+__device__ __forceinline__ Site column_site(const Column &k, int z, int dzm, int dzp)
+{
+    constexpr int PLANE = L * L / 2;
+    Site s;
+    const int p = (k.par + z) & 1;
+    s.h = k.hcol + PLANE * z;
+    s.id = k.idcol + p + L * L * z;
+    s.nb[0] = s.h + (p ? 0 : k.dxm0);
+    s.nb[1] = s.h + (p ? k.dxp1 : 0);
+    s.nb[2] = s.h + k.dym;
+    s.nb[3] = s.h + k.dyp;
+    s.nb[4] = s.h + dzm;
+    s.nb[5] = s.h + dzp;
+    return s;
+}
+
+// One half-sweep (colour c) of this lane's sites.
+//   COLZ (compile-time L): a lane owns whole columns (fixed x-pair and y) and a stride of z;
+//   for G >= plane (plane = L^2/2 sites of a colour) lane = column + plane z0 and
+//   z = z0 + DZ t with DZ = G / plane, else the lane owns columns lane + G t and every z
+//   (the wrap-around planes z = 0 and L-1 peeled off).
+//   FLAT (any L): lane owns half-indices lane + G s.
+template <typename T, int LC, int G, int MAP>
+__device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, int c, uint32_t k, const Coef<T> &cf, T &pe,
+                                           T &pmx, T &pmy, T &pmz, unsigned long long &nacc)
+{
+    const int L = LC ? LC : g.L;
+    const int HALF = L * L * L / 2;
+    T *own = g.sp + (c ? 3 * HALF : 0);
+    const T *oth = g.sp + (c ? 0 : 3 * HALF);
+    const bool odd = c != 0;
+    // The lane's site geometry and the sweep-independent part of its counters are cheap to
+    // recompute here; an opaque lane index keeps the compiler from hoisting them for all of
+    // the lane's sites out of the sweep loop, which would cost more registers (occupancy,
+    // spills) than it saves.
+    int lane = g.lane;
+    asm volatile("" : "+v"(lane));
+    auto up = [&](const Site &s) { update_site<T>(g, own, oth, HALF, odd, s, k, cf, pe, pmx, pmy, pmz, nacc); };
+    if constexpr (MAP == COLZ && LC != 0) {
+        constexpr int PLANE = LC * LC / 2;
+        if constexpr (G >= PLANE) {
+            constexpr int DZ = G / PLANE;
+            constexpr int NZ = (LC + DZ - 1) / DZ;
             if (lane >= DZ * PLANE) return;
-            const int col = lane % PLANE, z0 = lane / PLANE;
-            const int j = col % HL, y = col / HL;
-            const int NZ = (L + DZ - 1) / DZ;
-#pragma unroll 4
-            for (int t = 0; t < NZ; ++t) {
-                const int z = z0 + DZ * t;
-                if (z < L) f(make_site(L, j, y, z, c));
+            const int z0 = lane / PLANE;
+            const Column col = make_column(LC, lane % PLANE, c);
+            // wrap offsets: only the first z of a lane can be 0 and only its last L-1
+            const int zlast = z0 + DZ * (NZ - 1);
+            const int dzm0 = (z0 == 0) ? (LC - 1) * PLANE : -PLANE;
+            const int dzpl = (zlast == LC - 1) ? -(LC - 1) * PLANE : PLANE;
+            up(column_site<LC>(col, z0, dzm0, NZ == 1 ? dzpl : PLANE));
+#pragma unroll 2
+            for (int t = 1; t < NZ - 1; ++t) up(column_site<LC>(col, z0 + DZ * t, -PLANE, PLANE));
+            if constexpr (NZ > 1) {
+                if ((LC % DZ) == 0 || zlast < LC) up(column_site<LC>(col, zlast, -PLANE, dzpl));
             }
         } else {
-            const int NCOL = (PLANE + G - 1) / G;
-            for (int ct = 0; ct < NCOL; ++ct) {
-                const int col = lane + G * ct;
-                if (col >= PLANE) break;
-                const int j = col % HL, y = col / HL;
-#pragma unroll 4
-                for (int z = 0; z < L; ++z) f(make_site(L, j, y, z, c));
+            constexpr int NCOL = (PLANE + G - 1) / G;
+#pragma unroll 1
+            for (int cc = 0; cc < NCOL; ++cc) {
+                const int ci = lane + G * cc;
+                if ((PLANE % G) != 0 && ci >= PLANE) break;
+                const Column col = make_column(LC, ci, c);
+                up(column_site<LC>(col, 0, (LC - 1) * PLANE, PLANE));
+#pragma unroll 2
+                for (int z = 1; z < LC - 1; ++z) up(column_site<LC>(col, z, -PLANE, PLANE));
+                up(column_site<LC>(col, LC - 1, -PLANE, -(LC - 1) * PLANE));
             }
         }
     } else {
@@ -268,55 +407,54 @@ __device__ __forceinline__ void for_own_sites(int Lrt, int lane, int c, F &&f)
 #pragma unroll 4
         for (int s = 0; s < SPL; ++s) {
             const int h = lane + G * s;
-            if (h < HALF) {
-                const int col = h % PLANE, z = h / PLANE;
-                f(make_site(L, col % HL, col / HL, z, c));
-            }
+            if (h < HALF) up(flat_site(L, h, c));
         }
     }
 }
 
-// Initial state of Sec. 2.2 for this lane's sites (Philox counter (id, 0, path, TAG_INIT)).
-// Out of line (runs once): inlined, it crashes the ROCm 7.2 optimizer (SimplifyCFG).
-template <typename T, int LC, int G, int MAP>
-__device__ __attribute__((noinline)) void init_own(const GroupCtx<T> &g)
+// Initial state of Sec. 2.2 (Philox counter (id, 0, path, TAG_INIT)): the group's lanes take
+// the path's sites in a flat stride. Out of line (runs once): inlined, it crashes the
+// ROCm 7.2 optimizer (SimplifyCFG).
+template <typename T, int G>
+__device__ __attribute__((noinline)) void init_path(T *sp, int L, int lane, uint32_t path, uint32_t key0,
+                                                    uint32_t key1, uint32_t ctr3, int init)
 {
-    const InstDev &in = *g.in;
-    const int L = LC ? LC : in.L;
     const int HALF = L * L * L / 2;
-    for (int c = 0; c < 2; ++c) {
-        T *own = g.sp + (c ? 3 * HALF : 0);
-        for_own_sites<LC, G, MAP>(in.L, g.lane, c, [&](const Site &s) {
-            T x, y, z;
-            if (in.init == INIT_ORDERED) {
-                x = T(0); y = T(0); z = T(1);
-            } else {
-                const Words w = philox4x32_10((uint32_t)s.id, 0u, (uint32_t)g.path, TAG_INIT | in.ctr3, in.key0, in.key1);
-                if (in.init == INIT_ANGLES) Arith<T>::angles(w.w0, w.w1, x, y, z);
-                else Arith<T>::sphere(w.w0, w.w1, x, y, z);
-            }
-            own[s.h] = x;
-            own[HALF + s.h] = y;
-            own[2 * HALF + s.h] = z;
-        });
+    for (int t = lane; t < 2 * HALF; t += G) {
+        const int c = t >= HALF, h = t - c * HALF;
+        const Site s = flat_site(L, h, c);
+        T x, y, z;
+        if (init == INIT_ORDERED) {
+            x = T(0);
+            y = T(0);
+            z = T(1);
+        } else {
+            const Words w = philox4x32_10((uint32_t)s.id, 0u, path, TAG_INIT | ctr3, key0, key1);
+            if (init == INIT_ANGLES) Arith<T>::angles(w.w0, w.w1, x, y, z);
+            else Arith<T>::sphere(w.w0, w.w1, x, y, z);
+        }
+        T *own = sp + c * 3 * HALF;
+        own[h] = x;
+        own[HALF + h] = y;
+        own[2 * HALF + h] = z;
     }
 }
 
-// FP32 only: S <- S / |S| for this lane's sites.
-template <typename T, int LC, int G, int MAP>
-__device__ __attribute__((noinline)) void renorm_own(const GroupCtx<T> &g)
+// FP32 only: S <- S / |S| for every site of the path (each site touched by one lane). Out of
+// line (runs every renorm_every sweeps): inlined, it crashes the ROCm 7.2 optimizer
+// (SimplifyCFG).
+template <int G>
+__device__ __attribute__((noinline)) void renorm_path(float *sp, int L, int lane)
 {
-    const int L = LC ? LC : g.in->L;
     const int HALF = L * L * L / 2;
-    for (int c = 0; c < 2; ++c) {
-        T *own = g.sp + (c ? 3 * HALF : 0);
-        for_own_sites<LC, G, MAP>(g.in->L, g.lane, c, [&](const Site &s) {
-            const T x = own[s.h], y = own[HALF + s.h], z = own[2 * HALF + s.h];
-            const T r = __builtin_amdgcn_rsqf(fmaf(z, z, fmaf(y, y, x * x)));
-            own[s.h] = x * r;
-            own[HALF + s.h] = y * r;
-            own[2 * HALF + s.h] = z * r;
-        });
+    for (int t = lane; t < 2 * HALF; t += G) {
+        const int c = t >= HALF, h = t - c * HALF;
+        float *own = sp + c * 3 * HALF;
+        const float x = own[h], y = own[HALF + h], z = own[2 * HALF + h];
+        const float r = __builtin_amdgcn_rsqf(fmaf(z, z, fmaf(y, y, x * x)));
+        own[h] = x * r;
+        own[HALF + h] = y * r;
+        own[2 * HALF + h] = z * r;
     }
 }
 
@@ -324,39 +462,36 @@ __device__ __attribute__((noinline)) void renorm_own(const GroupCtx<T> &g)
 // instance and sweep range), so __syncthreads() separates the half-sweeps of all of them.
 // Idle groups (path >= n_paths) and idle lanes still take every barrier.
 template <typename T, int LC, int G, int MAP>
-__device__ void path_sweeps(const GroupCtx<T> &g, int k0, int k1, bool fresh)
+__device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev &in, int k0, int k1, bool fresh)
 {
-    const InstDev &in = *g.in;
-    const int L = LC ? LC : in.L;
-    const int HALF = L * L * L / 2;
-    const double Nd = 2.0 * (double)HALF;
-    const T beta = (T)in.beta, J = (T)in.J;
-    const T q = (T)(in.beta * in.J * 1.4426950408889634);  // beta J log2(e)
+    const int L = LC ? LC : g.L;
+    const double Nd = (double)L * L * L;
+    const int n_therm = in.n_therm, trace_sweeps = in.trace_sweeps, renorm_every = in.renorm_every;
+    const double J = in.J;
+    double *const trace = in.trace;
+    Coef<T> cf;
+    cf.beta = (T)in.beta;
+    cf.J = (T)in.J;
+    cf.q = (float)(in.beta * in.J * 1.4426950408889634);  // beta J log2(e)
     const int wave = g.lane >> 6;
-    const bool lead = g.active && g.lane == 0;
-    unsigned long long n_acc = 0;  // this wave's accepted moves
+    constexpr int W = G / 64;  // waves per path group
+    unsigned long long nacc = 0;  // this wave's accepted moves
 
-    if (g.active && fresh) init_own<T, LC, G, MAP>(g);
+    if (g.active && fresh) init_path<T, G>(g.sp, L, g.lane, g.path, g.key0, g.key1, g.ctr3, in.init);
     __syncthreads();
 
     for (int k = k0; k < k1; ++k) {
         if constexpr (std::is_same<T, float>::value) {
-            if (in.renorm_every > 0 && k > 0 && k % in.renorm_every == 0) {
-                if (g.active) renorm_own<T, LC, G, MAP>(g);
+            if (renorm_every > 0 && k > 0 && k % renorm_every == 0) {
+                if (g.active) renorm_path<G>(g.sp, L, g.lane);
                 __syncthreads();
             }
         }
         T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);
-        for (int c = 0; c < 2; ++c) {
-            if (g.active) {
-                for_own_sites<LC, G, MAP>(in.L, g.lane, c, [&](const Site &s) {
-                    const bool a = update_site<T>(g, HALF, c, s, (uint32_t)k, beta, J, q, pe, pmx, pmy, pmz);
-                    n_acc += (unsigned long long)__popcll(__ballot(a));
-                });
-            }
-            if (c == 0) __syncthreads();
-        }
-        const bool meas = k >= in.n_therm || k < in.trace_sweeps || k == k1 - 1;
+        if (g.active) half_sweep<T, LC, G, MAP>(g, 0, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+        __syncthreads();
+        if (g.active) half_sweep<T, LC, G, MAP>(g, 1, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+        const bool meas = k >= n_therm || k < trace_sweeps || k == k1 - 1;
         if (meas) {
             pe = wave_sum(pe);
             pmx = wave_sum(pmx);
@@ -370,42 +505,50 @@ __device__ void path_sweeps(const GroupCtx<T> &g, int k0, int k1, bool fresh)
             }
         }
         __syncthreads();
-        if (meas && lead) {
-            double se = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-            for (int w = 0; w < G / 64; ++w) {
-                se += (double)g.red[4 * w + 0];
-                sx += (double)g.red[4 * w + 1];
-                sy += (double)g.red[4 * w + 2];
-                sz += (double)g.red[4 * w + 3];
+        if (meas && g.active && wave == 0) {
+            // the group's first wave adds up the wave partials (one wave per lane)
+            T se = T(0), sx = T(0), sy = T(0), sz = T(0);
+            if (g.lane < W) {
+                se = g.red[4 * g.lane + 0];
+                sx = g.red[4 * g.lane + 1];
+                sy = g.red[4 * g.lane + 2];
+                sz = g.red[4 * g.lane + 3];
             }
-            // Every bond joins an even and an odd site: E = -J sum_odd S_i . h_i.
-            const double e = -in.J * se / Nd;
-            const double mx = sx / Nd, my = sy / Nd, mz = sz / Nd;
-            if (k >= in.n_therm) {
-                const double m = sqrt(mx * mx + my * my + mz * mz);
-                g.shacc[0] += e;
-                g.shacc[1] += e * e;
-                g.shacc[2] += m;
-                g.shacc[3] += m * m;
-                g.shacc[4] += (m * m) * (m * m);
+            if constexpr (W > 1) {
+                se = first_lanes_sum(se);
+                sx = first_lanes_sum(sx);
+                sy = first_lanes_sum(sy);
+                sz = first_lanes_sum(sz);
             }
-            if (k < in.trace_sweeps) {
-                double *tr = in.trace + ((size_t)g.path * in.trace_sweeps + k) * 4;
-                tr[0] = e;
-                tr[1] = mx;
-                tr[2] = my;
-                tr[3] = mz;
-            }
-            if (k == k1 - 1) {
-                g.shacc[5] = e;
-                g.shacc[6] = mx;
-                g.shacc[7] = my;
-                g.shacc[8] = mz;
+            if (g.lane == 0) {
+                // Every bond joins an even and an odd site: E = -J sum_odd S_i . h_i.
+                const double e = -J * (double)se / Nd;
+                const double mx = (double)sx / Nd, my = (double)sy / Nd, mz = (double)sz / Nd;
+                if (k >= n_therm) {
+                    const double m = sqrt(mx * mx + my * my + mz * mz);
+                    g.shacc[0] += e;
+                    g.shacc[1] += e * e;
+                    g.shacc[2] += m;
+                    g.shacc[3] += m * m;
+                    g.shacc[4] += (m * m) * (m * m);
+                }
+                if (k < trace_sweeps) {
+                    double *tr = trace + ((size_t)g.path * trace_sweeps + k) * 4;
+                    tr[0] = e;
+                    tr[1] = mx;
+                    tr[2] = my;
+                    tr[3] = mz;
+                }
+                if (k == k1 - 1) {
+                    g.shacc[5] = e;
+                    g.shacc[6] = mx;
+                    g.shacc[7] = my;
+                    g.shacc[8] = mz;
+                }
             }
         }
     }
-    if (g.active && (g.lane & 63) == 0)
-        atomicAdd((unsigned long long *)&g.shacc[9], n_acc);
+    if (g.active && (g.lane & 63) == 0) atomicAdd((unsigned long long *)&g.shacc[9], nacc);
     __syncthreads();
 }
 
@@ -437,42 +580,66 @@ __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, bool 
 }
 
 // Sets up the group views of one workgroup and runs sweeps [k0, k1) for paths
-// path0 + group. gspins: the instance's resident spin array (or nullptr in a batch);
-// slot: device memory for an HBM path when gspins is nullptr.
+// path0 + group. gbase: device memory of path path0's spins (group g at gbase + g * 3 L^3):
+// the instance's resident array (resident = true: LDS spins are loaded from and stored back
+// to it) or a batch slot. The caller passes the base explicitly: a select between the two
+// crashes the ROCm 7.2 optimizer (SimplifyCFG).
 template <typename T, int LC, int G, int B, int MAP, bool IN_LDS>
-__device__ void wg_run(const InstDev &in, int path0, int k0, int k1, bool fresh, char *smem, T *slot)
+__device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int k1, bool fresh, char *smem, T *gbase,
+                                       bool resident)
 {
     constexpr int P = B / G;
     const int L = LC ? LC : in.L;
     const size_t NS = 3 * (size_t)L * L * L;  // spin words per path
     const int group = threadIdx.x / G;
     GroupCtx<T> g;
-    g.in = &in;
+    g.L = in.L;
     g.lane = threadIdx.x % G;
-    g.path = path0 + group;
-    g.active = g.path < in.n_paths;
+    // wave-uniform by construction (G is a multiple of 64): keep in scalar registers
+    g.path = (uint32_t)__builtin_amdgcn_readfirstlane(path0 + group);
+    g.key0 = in.key0;
+    g.key1 = in.key1;
+    g.ctr3 = in.ctr3;
+    g.active = (int)g.path < in.n_paths;
     char *p = smem;
     T *lds_spins = reinterpret_cast<T *>(p);
     if (IN_LDS) p += P * NS * sizeof(T);
     g.shacc = reinterpret_cast<double *>(p) + 16 * group;
     p += P * 128;
     g.red = reinterpret_cast<T *>(p) + 4 * (group * (G / 64));
-    T *gsp = in.spins ? reinterpret_cast<T *>(in.spins) + (size_t)g.path * NS : slot + (size_t)group * NS;
+    T *gsp = gbase + (size_t)group * NS;
     g.sp = IN_LDS ? lds_spins + (size_t)group * NS : gsp;
 
     load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
     if (IN_LDS && !fresh && g.active) copy_spins<G>(g.sp, gsp, (int)NS, g.lane);
     // (path_sweeps begins with a barrier)
-    path_sweeps<T, LC, G, MAP>(g, k0, k1, fresh);
-    if (IN_LDS && in.spins && g.active) copy_spins<G>(gsp, g.sp, (int)NS, g.lane);
+    path_sweeps<T, LC, G, MAP>(g, in, k0, k1, fresh);
+    if (IN_LDS && resident && g.active) copy_spins<G>(gsp, g.sp, (int)NS, g.lane);
     store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
 }
 
+// Waves per SIMD a kernel variant aims for (the compiler sizes its registers to fit): as
+// many workgroups as the 160 KiB of LDS per CU holds, 4 SIMDs per CU, at most 8 waves per
+// SIMD (4 in FP64); 4 (FP64: 2) for spins in device memory.
+template <typename T>
+constexpr int target_waves(int L, int B, int G, bool in_lds)
+{
+    const int fp64 = sizeof(T) == 8;  // FP64 values take register pairs
+    if (!in_lds || L == 0) return fp64 ? 2 : 4;
+    const int wgs = (int)((size_t)160 * 1024 / lds_layout_bytes<T>(L, B, G, true));
+    const int w = wgs * (B / 64) / 4, cap = fp64 ? 4 : 8;
+    return w < 1 ? 1 : (w > cap ? cap : w);
+}
+
 template <typename T, int LC, int G, int B, int MAP, bool IN_LDS>
-__global__ __launch_bounds__(B) void k_resident(InstDev in, int k0, int k1, int fresh)
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(target_waves<T>(LC, B, G, IN_LDS))))
+void k_resident(InstDev in, int k0, int k1, int fresh)
 {
     extern __shared__ __align__(16) char smem[];
-    wg_run<T, LC, G, B, MAP, IN_LDS>(in, blockIdx.x * (B / G), k0, k1, fresh != 0, smem, nullptr);
+    const int L = LC ? LC : in.L;
+    const int path0 = blockIdx.x * (B / G);
+    wg_run<T, LC, G, B, MAP, IN_LDS>(in, path0, k0, k1, fresh != 0, smem,
+                                     reinterpret_cast<T *>(in.spins) + (size_t)path0 * 3 * L * L * L, true);
 }
 
 template <typename T, int LC, int G, int B, int MAP, bool IN_LDS>
@@ -511,7 +678,7 @@ constexpr int BATCH_B = 512;
     X(double, 0, 512, FLAT, false, "f64-hbm-any-g512")
 
 template <typename T>
-__global__ __launch_bounds__(BATCH_B) void k_batch(BatchDev bd)
+__global__ __launch_bounds__(BATCH_B) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchDev bd)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int item_sh;
@@ -529,7 +696,7 @@ __global__ __launch_bounds__(BATCH_B) void k_batch(BatchDev bd)
         int idx = 0;
 #define MMC_BATCH_CASE(TT, LC, G, MAP, LDS, NAME) \
     if constexpr (std::is_same<T, TT>::value) {   \
-        if (v == idx) wg_run<TT, LC, G, BATCH_B, MAP, LDS>(in, item.path0, 0, total, true, smem, slot); \
+        if (v == idx) wg_run<TT, LC, G, BATCH_B, MAP, LDS>(in, item.path0, 0, total, true, smem, slot, false); \
         ++idx;                                    \
     }
         MMC_BATCH_VARIANTS_F32(MMC_BATCH_CASE)
@@ -543,15 +710,14 @@ __global__ __launch_bounds__(BATCH_B) void k_batch(BatchDev bd)
 // the sweep index lives in device memory so one captured sweep can be replayed.
 __global__ __launch_bounds__(256) void k_plain_init(InstDev in)
 {
-    const int L = in.L, HALF = L * L * L / 2, HL = L / 2, PLANE = HL * L;
+    const int L = in.L, HALF = L * L * L / 2;
     const int h = blockIdx.x * 256 + threadIdx.x;
     const int path = blockIdx.y;
     if (blockIdx.x == 0 && threadIdx.x < 16) reinterpret_cast<double *>(in.acc + path)[threadIdx.x] = 0.0;
     if (h >= HALF) return;
     double *sp = reinterpret_cast<double *>(in.spins) + (size_t)path * 6 * HALF;
     for (int c = 0; c < 2; ++c) {
-        const int col = h % PLANE;
-        const Site s = make_site(L, col % HL, col / HL, h / PLANE, c);
+        const Site s = flat_site(L, h, c);
         double x, y, z;
         if (in.init == INIT_ORDERED) {
             x = 0.0; y = 0.0; z = 1.0;
@@ -569,24 +735,29 @@ __global__ __launch_bounds__(256) void k_plain_init(InstDev in)
 
 __global__ __launch_bounds__(256) void k_plain_half(InstDev in, const int *k_dev, int c)
 {
-    const int L = in.L, HALF = L * L * L / 2, HL = L / 2, PLANE = HL * L;
+    const int L = in.L, HALF = L * L * L / 2;
     const int h = blockIdx.x * 256 + threadIdx.x;
     const int path = blockIdx.y;
-    bool a = false;
+    unsigned long long nacc = 0;
     if (h < HALF) {
         GroupCtx<double> g;
-        g.in = &in;
-        g.path = path;
+        g.L = L;
+        g.path = (uint32_t)path;
+        g.key0 = in.key0;
+        g.key1 = in.key1;
+        g.ctr3 = in.ctr3;
         g.active = true;
         g.lane = h;
         g.sp = reinterpret_cast<double *>(in.spins) + (size_t)path * 6 * HALF;
-        const int col = h % PLANE;
-        const Site s = make_site(L, col % HL, col / HL, h / PLANE, c);
+        Coef<double> cf;
+        cf.beta = in.beta;
+        cf.J = in.J;
+        cf.q = 0.0f;
         double pe = 0.0, px = 0.0, py = 0.0, pz = 0.0;
-        a = update_site<double>(g, HALF, c, s, (uint32_t)*k_dev, in.beta, in.J, 0.0, pe, px, py, pz);
+        update_site<double>(g, g.sp + (c ? 3 * HALF : 0), g.sp + (c ? 0 : 3 * HALF), HALF, c != 0, flat_site(L, h, c),
+                            (uint32_t)*k_dev, cf, pe, px, py, pz, nacc);
     }
-    const unsigned long long cnt = (unsigned long long)__popcll(__ballot(a));
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&in.acc[path].n_accept, cnt);
+    if ((threadIdx.x & 63) == 0 && nacc) atomicAdd(&in.acc[path].n_accept, nacc);
 }
 
 // One workgroup per path: measures the state after the sweep, accumulates, then (thread 0)
@@ -594,7 +765,7 @@ __global__ __launch_bounds__(256) void k_plain_half(InstDev in, const int *k_dev
 __global__ __launch_bounds__(256) void k_plain_measure(InstDev in, int *k_dev, int k_last)
 {
     __shared__ double part[4][4];
-    const int L = in.L, HALF = L * L * L / 2, HL = L / 2, PLANE = HL * L;
+    const int L = in.L, HALF = L * L * L / 2;
     const int path = blockIdx.x;
     const double *sp = reinterpret_cast<const double *>(in.spins) + (size_t)path * 6 * HALF;
     const int k = *k_dev;
@@ -602,8 +773,7 @@ __global__ __launch_bounds__(256) void k_plain_measure(InstDev in, int *k_dev, i
     if (meas) {
         double se = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
         for (int h = threadIdx.x; h < HALF; h += 256) {
-            const int col = h % PLANE;
-            const Site s = make_site(L, col % HL, col / HL, h / PLANE, 1);
+            const Site s = flat_site(L, h, 1);
             const double *odd = sp + 3 * HALF, *even = sp;
             double hx = even[s.nb[0]], hy = even[HALF + s.nb[0]], hz = even[2 * HALF + s.nb[0]];
             for (int n = 1; n < 6; ++n) {

@@ -1,0 +1,52 @@
+"""Measures gfx950 VALU instruction throughput (libmmc_opbench.so) and prints the issue cost
+of each instruction class in full-rate lane slots (v_add_f32 = 1), the unit of the engine's
+VALU roofline. With --copy-bytes B it instead runs one plain device-to-device copy of B bytes
+(torch), the calibration kernel for the HBM byte counters.
+
+Usage: python -m paper_1305_6758_amd.opbench [--iters N] [--copy-bytes B]
+"""
+import argparse
+import ctypes as C
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--iters", type=int, default=4096)
+    ap.add_argument("--copy-bytes", type=int, default=0)
+    a = ap.parse_args()
+    import torch
+    if a.copy_bytes:
+        x = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.copy_bytes}))
+        return
+    lib = C.CDLL(os.path.join(HERE, "libmmc_opbench.so"))
+    lib.mmc_opbench_name.restype = C.c_char_p
+    lib.mmc_opbench_run.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    rows = {}
+    for i in range(lib.mmc_opbench_count()):
+        rate, ms = C.c_double(), C.c_double()
+        rc = lib.mmc_opbench_run(i, a.iters, C.byref(rate), C.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"opbench op {i} failed ({rc})")
+        rows[lib.mmc_opbench_name(i).decode()] = (rate.value, ms.value)
+    base = rows["v_add_f32"][0]
+    props = torch.cuda.get_device_properties(0)
+    print(f"device: {props.name} {props.gcnArchName}, {props.multi_processor_count} CUs")
+    print(f"v_add_f32: {base:.4e} lane-ops/s = {base / (props.multi_processor_count * 64) / 1e9:.3f} G issue/s per lane-slot "
+          "(effective VALU clock, 64 lanes per CU per clock)")
+    print(f"{'instruction':16s} {'lane-ops/s':>12s} {'slots':>7s} {'ms':>8s}")
+    for k, (r, ms) in rows.items():
+        print(f"{k:16s} {r:12.4e} {base / r:7.2f} {ms:8.2f}")
+    print(json.dumps({k: {"lane_ops_per_s": r, "slots": base / r} for k, (r, _) in rows.items()}))
+
+
+if __name__ == "__main__":
+    main()
