@@ -25,15 +25,45 @@ sys.path.insert(0, ROOT)
 METRIC = "Metropolis spin updates/sec (batched FP32 vs plain FP64) at 4σ oracle agreement"
 WORKLOAD = "L16-T3-p4096-fp32"
 
-# Algorithmic VALU issue cost of one FP32 Metropolis update on gfx950, in full-rate lane
-# slots (a quarter-rate instruction costs 4): Philox4x32-10 with the wave-uniform half of
-# its first two rounds on the scalar unit (18 x 64-bit multiply at 4 + 19 three-way xor),
-# three uniforms (13), the proposal (1 fma, sqrt, sin, cos at 4, 2 mul: 15), the local field
-# (15 adds), dE and the test (6 + 1 + exp2 at 4 + 1: 12), the new-spin select (3), the
-# fused measurement (4.5 on average).
-VALU_SLOTS_PER_UPDATE_F32 = 91 + 13 + 15 + 15 + 12 + 3 + 4.5
-# MI355X: 256 compute units x 4 SIMD x 16 lanes per clock x 2.4 GHz.
-VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
+# VALU roofline of the batch kernel. Peak: the published MI355X FP32 vector rate, 157.3
+# TFLOP/s = 256 CUs x 2.4 GHz x 128 lanes x 2 FLOP per FMA, i.e. 7.86e13 lane-operations/s.
+# Each instruction class costs PEAK / rate lane-slots, with the sustained rates measured on
+# gfx950 by `python -m paper_1305_6758_amd.opbench` (profiles/valu_op_rates_gfx950.md).
+VALU_PEAK = 256 * 2.4e9 * 128
+OP_RATES = {  # lane-operations per second, whole GPU
+    "v_add_f32": 6.2467e13, "v_sub_f32": 6.2675e13, "v_mul_f32": 6.2759e13, "v_fma_f32": 3.6725e13,
+    "v_cndmask_b32": 3.6135e13, "v_cmp_lt_f32": 3.2484e13, "v_alignbit_b32": 3.4979e13, "v_xor_b32": 5.4277e13,
+    "v_bitop3_b32": 5.6564e13, "v_mad_u64_u32": 2.9577e13, "v_exp_f32": 1.8809e13, "v_sin_f32": 1.8770e13,
+    "v_cos_f32": 1.8820e13, "v_sqrt_f32": 1.8793e13,
+}
+# Instructions one FP32 Metropolis update needs (per lane): Philox4x32-10 with the wave-uniform
+# half of its first two rounds on the scalar unit (18 64-bit products, 15 three-way and 4
+# two-way xors); three exact uniforms (alignbit + subtract each) and z = 2u - 1 (fma);
+# proposal (fma, sqrt, sin, cos, 2 mul); local field (15 add); dE and test (3 sub, mul,
+# 2 fma, mul, exp2, compare); new-spin select (3 cndmask); fused measurement (3 add for M,
+# 3 fma for S.h on the odd half, 1.5 on average). Site addresses are immediate offsets.
+UPDATE_OPS_F32 = {
+    "v_mad_u64_u32": 18, "v_bitop3_b32": 15, "v_xor_b32": 4, "v_alignbit_b32": 3, "v_sub_f32": 6,
+    "v_fma_f32": 5.5, "v_mul_f32": 4, "v_sqrt_f32": 1, "v_sin_f32": 1, "v_cos_f32": 1, "v_exp_f32": 1,
+    "v_add_f32": 18, "v_cmp_lt_f32": 1, "v_cndmask_b32": 3,
+}
+SLOTS_PER_UPDATE_F32 = sum(n * VALU_PEAK / OP_RATES[op] for op, n in UPDATE_OPS_F32.items())
+COUNTERS = os.path.join(ROOT, "profiles", "k_batch_f32_L16-T3-p4096_counters.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when the kernels have
+    changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1305_6758_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()[:16]
+    fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("kernels_sha256:", "traffic_bytes_per_launch:")))
+    if fields.get("kernels_sha256") != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -145,7 +175,7 @@ def main():
     wall, kernel_ms, results, stats, plan = run_batched(instances, a.steps, a.warmup)
     value = upd_step * a.steps / wall
     kms = sum(kernel_ms) / len(kernel_ms)
-    achieved = VALU_SLOTS_PER_UPDATE_F32 * upd_step / (kms * 1e-3)
+    achieved = SLOTS_PER_UPDATE_F32 * upd_step / (kms * 1e-3)
 
     golden_path = os.path.join(ROOT, "tests", "golden", f"oracle_{WORKLOAD}.json")
     parity = None
@@ -169,10 +199,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "L": 16, "T": [1.2, 1.443, 1.7], "paths_per_T": 4096,
                    "n_therm": 2000, "n_meas": 8000, "updates_per_step": upd_step, "seed": 1234, "plan": plan},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
-                     "unit": "T VALU-slots/s", "frac": achieved / VALU_PEAK_SLOTS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
                      "kernel": "k_batch<float>", "kernel_ms": kms,
-                     "slots_per_update": VALU_SLOTS_PER_UPDATE_F32},
+                     "lane_slots_per_update": SLOTS_PER_UPDATE_F32,
+                     "ceiling_updates_per_s": VALU_PEAK / SLOTS_PER_UPDATE_F32},
         "parity": parity,
         "stats": [{k: s[k] for k in ("mean_e", "se_e", "mean_absm", "se_absm", "chi", "cv_heat", "binder",
                                      "r_e", "p_norm_e", "accept_rate")} for s in stats],

@@ -127,6 +127,10 @@ mmc_ctx *mmc_create_ex(int L, double T, double J, int n_paths, int n_therm, int 
 /* Message of the last failed call on this thread ("" if none). Owned by the library. */
 const char *mmc_last_error(void);
 
+/* Status code (mmc_status) of the last failed call on this thread (MMC_OK if none); the way
+ * to learn why a call that returns a pointer returned NULL. */
+int mmc_last_status(void);
+
 /* Device bytes the context needs (spin state, accumulators, trace, queue). */
 size_t mmc_workspace_bytes(const mmc_ctx *ctx);
 

@@ -31,6 +31,13 @@ constexpr int CH = 8;  // independent chains per lane
 
 OPBENCH_KERNEL(k_add_f32, float, 1.0f + c, asm volatile("v_add_f32 %0, %0, %1" : "+v"(x[c]) : "v"(yf)))
 OPBENCH_KERNEL(k_fma_f32, float, 1.0f + c, asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(x[c]) : "v"(yf)))
+OPBENCH_KERNEL(k_mul_f32, float, 1.0f + c, asm volatile("v_mul_f32 %0, %0, %1" : "+v"(x[c]) : "v"(yf)))
+OPBENCH_KERNEL(k_sub_f32, float, 1.0f + c, asm volatile("v_sub_f32 %0, %0, %1" : "+v"(x[c]) : "v"(yf)))
+OPBENCH_KERNEL(k_cndmask_b32, uint32_t, t + c,
+               uint64_t m = 0x5555555555555555ull; asm volatile("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(x[c]) : "v"(yb), "s"(m)))
+OPBENCH_KERNEL(k_cmp_lt_f32, float, 1.0f + c,
+               uint64_t m; asm volatile("v_cmp_lt_f32_e64 %0, %1, %2" : "=s"(m) : "v"(x[c]), "v"(yf)))
+OPBENCH_KERNEL(k_alignbit_b32, uint32_t, t + c, asm volatile("v_alignbit_b32 %0, %1, %0, 9" : "+v"(x[c]) : "v"(yb)))
 OPBENCH_KERNEL(k_xor_b32, uint32_t, t + c, asm volatile("v_xor_b32 %0, %0, %1" : "+v"(x[c]) : "v"(yb)))
 OPBENCH_KERNEL(k_bitop3_b32, uint32_t, t + c, asm volatile("v_bitop3_b32 %0, %0, %1, %0 bitop3:0x96" : "+v"(x[c]) : "v"(yb)))
 OPBENCH_KERNEL(k_add_u32, uint32_t, t + c, asm volatile("v_add_u32 %0, %0, %1" : "+v"(x[c]) : "v"(yb)))
@@ -52,7 +59,9 @@ struct Op {
 };
 
 const Op k_ops[] = {
-    {"v_add_f32", k_add_f32},         {"v_fma_f32", k_fma_f32},         {"v_xor_b32", k_xor_b32},
+    {"v_add_f32", k_add_f32},         {"v_fma_f32", k_fma_f32},         {"v_mul_f32", k_mul_f32},
+    {"v_sub_f32", k_sub_f32},         {"v_cndmask_b32", k_cndmask_b32}, {"v_cmp_lt_f32", k_cmp_lt_f32},
+    {"v_alignbit_b32", k_alignbit_b32}, {"v_xor_b32", k_xor_b32},
     {"v_bitop3_b32", k_bitop3_b32},   {"v_add_u32", k_add_u32},         {"v_mul_hi_u32", k_mul_hi_u32},
     {"v_mul_lo_u32", k_mul_lo_u32},   {"v_mad_u64_u32", k_mad_u64_u32}, {"v_cvt_f32_u32", k_cvt_f32_u32},
     {"v_exp_f32", k_exp_f32},         {"v_sin_f32", k_sin_f32},         {"v_cos_f32", k_cos_f32},

@@ -20,6 +20,7 @@
 namespace {
 
 thread_local std::string g_last_error;
+thread_local int g_last_status = MMC_OK;
 
 int fail(int code, const char *fmt, ...)
 {
@@ -29,6 +30,7 @@ int fail(int code, const char *fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_last_error = buf;
+    g_last_status = code;
     return code;
 }
 
@@ -482,6 +484,8 @@ int plan_single(mmc_ctx *c)
 extern "C" {
 
 const char *mmc_last_error(void) { return g_last_error.c_str(); }
+
+int mmc_last_status(void) { return g_last_status; }
 
 mmc_ctx *mmc_create_ex(int L, double T, double J, int n_paths, int n_therm, int n_meas, uint64_t seed,
                        const mmc_config *cfg)

@@ -57,6 +57,7 @@ _SIGNATURES = [
     ("mmc_create_ex", _P, [C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, C.c_uint64,
                            C.POINTER(mmc_config)]),
     ("mmc_last_error", C.c_char_p, []),
+    ("mmc_last_status", C.c_int, []),
     ("mmc_workspace_bytes", C.c_size_t, [_P]),
     ("mmc_bind", C.c_int, [_P, _P, C.c_size_t, _P]),
     ("mmc_tune", C.c_int, [_P]),
@@ -113,7 +114,7 @@ def _check(rc):
 
 def _ptr(h):
     if not h:
-        raise MMCError(MMC_EINVAL, lib().mmc_last_error().decode())
+        raise MMCError(lib().mmc_last_status(), lib().mmc_last_error().decode())
     return h
 
 
@@ -134,6 +135,10 @@ def mmc_create_ex(L, T, J, n_paths, n_therm, n_meas, seed, cfg=None):
 
 def mmc_last_error():
     return lib().mmc_last_error().decode()
+
+
+def mmc_last_status():
+    return lib().mmc_last_status()
 
 
 def mmc_workspace_bytes(ctx):

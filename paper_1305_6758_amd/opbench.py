@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--iters", type=int, default=4096)
+    ap.add_argument("--ms", type=float, default=50.0, help="target run time per instruction class")
     ap.add_argument("--copy-bytes", type=int, default=0)
     a = ap.parse_args()
     import torch
@@ -33,9 +33,14 @@ def main():
     rows = {}
     for i in range(lib.mmc_opbench_count()):
         rate, ms = C.c_double(), C.c_double()
-        rc = lib.mmc_opbench_run(i, a.iters, C.byref(rate), C.byref(ms))
-        if rc != 0:
-            raise RuntimeError(f"opbench op {i} failed ({rc})")
+        iters = 1024
+        for _ in range(8):  # grow the run until it lasts about --ms (sustained clocks)
+            rc = lib.mmc_opbench_run(i, iters, C.byref(rate), C.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"opbench op {i} failed ({rc})")
+            if ms.value >= a.ms:
+                break
+            iters = int(iters * min(64.0, max(2.0, 1.2 * a.ms / max(ms.value, 1e-3))))
         rows[lib.mmc_opbench_name(i).decode()] = (rate.value, ms.value)
     base = rows["v_add_f32"][0]
     props = torch.cuda.get_device_properties(0)

@@ -1,0 +1,115 @@
+"""Host-side checks of the engine library that need no GPU: the C ABI loads and exports every
+function the header declares, arguments are validated before any device work, and the host
+FP64 statistics agree with the oracle's statistics and with scipy."""
+import math
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+import scipy.stats as ss
+
+from oracle import oracle as O
+from oracle import stats as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "mmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mmc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_1305_6758_amd import mmc
+    lib = mmc.lib()
+    declared = header_functions()
+    assert len(declared) >= 25
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(mmc.EXPORTED) == declared
+
+
+def test_arguments_validated_without_gpu():
+    from paper_1305_6758_amd import mmc
+    bad = [(7, 1.0, 1.0, 4, 1, 1, 1), (0, 1.0, 1.0, 4, 1, 1, 1), (8, 0.0, 1.0, 4, 1, 1, 1),
+           (8, -1.0, 1.0, 4, 1, 1, 1), (8, float("nan"), 1.0, 4, 1, 1, 1), (8, 1.0, float("inf"), 4, 1, 1, 1),
+           (8, 1.0, 1.0, 0, 1, 1, 1), (8, 1.0, 1.0, 4, -1, 1, 1), (8, 1.0, 1.0, 4, 1, -2, 1)]
+    for args in bad:
+        with pytest.raises(mmc.MMCError) as e:
+            mmc.mmc_create(*args)
+        assert e.value.code == mmc.MMC_EINVAL
+        assert mmc.mmc_last_error()
+    with pytest.raises(mmc.MMCError) as e:
+        mmc.mmc_create_ex(8, 1.0, 1.0, 4, 1, 1, 1, mmc.config(precision=mmc.MMC_FP32, placement=mmc.MMC_PLACE_PLAIN))
+    assert e.value.code == mmc.MMC_EUNSUPPORTED
+    with pytest.raises(mmc.MMCError):
+        mmc.mmc_create_ex(8, 1.0, 1.0, 4, 1, 1, 1, mmc.config(precision=7))
+    with pytest.raises(mmc.MMCError):
+        mmc.mmc_create_ex(8, 1.0, 1.0, 4, 1, 1, 1, mmc.config(instance_id=1 << 24))
+    # a valid context is created without touching a device; its first run reports the missing GPU
+    ctx = mmc.mmc_create(8, 1.5, 1.0, 4, 2, 2, 1)
+    try:
+        assert mmc.mmc_workspace_bytes(ctx) > 4 * 3 * 512 * 4
+        assert mmc.mmc_sweeps_done(ctx) == 0
+    finally:
+        mmc.mmc_destroy(ctx)
+    mmc.mmc_destroy(None)
+
+
+def test_load_rejects_missing_or_foreign_files(tmp_path):
+    from paper_1305_6758_amd import mmc
+    with pytest.raises(mmc.MMCError):
+        mmc.mmc_load(str(tmp_path / "nope.bin"))
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not a checkpoint at all")
+    with pytest.raises(mmc.MMCError):
+        mmc.mmc_load(str(junk))
+
+
+def test_host_statistics_match_oracle_statistics():
+    """mmc_stats_from_results (C++ host code: AS241 quantiles, Filliben Q-Q fit, K^2) against
+    the oracle's statistics (numpy, scipy ndtri) on real oracle output."""
+    from paper_1305_6758_amd import mmc
+    L, T = 4, 1.3
+    r = O.run_paths(L, T, n_therm=50, n_meas=100, path_end=200)
+    ref = S.path_statistics(r, L, T)
+    got = mmc.mmc_stats_from_results(r, L, T)
+    for k in ("mean_e", "se_e", "mean_absm", "se_absm", "e2", "m2", "m4", "chi", "cv_heat", "binder",
+              "r_e", "r_absm", "cv_absm", "p_norm_e", "p_norm_absm"):
+        assert abs(got[k] - ref[k]) <= 1e-12 * max(1.0, abs(ref[k])), k
+    assert got["n"] == 200
+
+
+def test_host_normality_and_qq_against_scipy():
+    from paper_1305_6758_amd import mmc
+    rng = np.random.default_rng(11)
+    for n, x in [(25, rng.standard_normal(25)), (400, rng.exponential(size=400)), (4096, rng.standard_normal(4096))]:
+        res = {k: np.zeros(n) for k in ("e2_mean", "m2_mean", "m4_mean", "final_e")}
+        res["e_mean"] = x
+        res["absm_mean"] = np.abs(x) + 1.0
+        res["final_m"] = np.zeros((n, 3))
+        res["n_accept"] = np.zeros(n, dtype=np.uint64)
+        got = mmc.mmc_stats_from_results(res, 4, 1.0)
+        assert abs(got["r_e"] - ss.probplot(x)[1][2] ** 2) < 1e-12
+        assert abs(got["p_norm_e"] - ss.normaltest(x).pvalue) < 1e-9
+        assert abs(got["mean_e"] - x.mean()) < 1e-14 * n
+        assert abs(got["se_e"] - x.std(ddof=1) / math.sqrt(n)) < 1e-13
+
+
+def test_workload_recipes():
+    from paper_1305_6758_amd.workloads import WORKLOADS, uneven_batch, updates
+    b = uneven_batch()
+    assert len(b) == 96
+    assert [x[0] for x in b[::16]] == [8, 12, 16, 24, 32, 48]
+    assert abs(b[0][1] - 1.0) < 1e-15 and abs(b[15][1] - 2.0) < 1e-15
+    assert all(64 <= x[2] <= 2048 for x in b) and all(x[3:] == (2000, 2000) for x in b)
+    assert updates(WORKLOADS["L16-T3-p4096-fp32"]["instances"]) == 3 * 4096 * 4096 * 10000
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr
