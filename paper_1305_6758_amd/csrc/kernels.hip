@@ -154,6 +154,13 @@ __device__ __forceinline__ float row_sum(float v)
     return v;
 }
 
+__device__ __forceinline__ double row_sum(double v)
+{
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 // Sum over the 64 lanes of the wave (wave-uniform result).
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -172,16 +179,6 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum over the first 16 lanes (lanes >= n contribute 0): result valid in lane 0.
-__device__ __forceinline__ float first_lanes_sum(float v) { return row_sum(v); }
-
-__device__ __forceinline__ double first_lanes_sum(double v)
-{
-#pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 enum Map { COLZ = 0, FLAT = 1 };
 
 // Everything a path group needs during its sweeps; path, key and counter word are
@@ -194,7 +191,7 @@ struct GroupCtx {
     int lane;                         // 0 .. G-1
     T *sp;                            // spins of this path while sweeping (LDS or device memory)
     double *shacc;                    // 16 doubles in LDS: the path's PathAcc while sweeping
-    T *red;                           // LDS [waves of the group][4] measurement partials
+    T *red;                           // LDS [16-lane rows of the group][4] measurement partials
 };
 
 // Site geometry of one update: half-index h, site id, and the six neighbour half-indices
@@ -305,6 +302,13 @@ __device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const 
     nacc += (unsigned long long)__popcll(__ballot(acc));
 }
 
+// Hides v from the optimizer's value tracking, keeping only that it is non-negative.
+__device__ __forceinline__ void opaque_nonneg(int &v)
+{
+    asm volatile("" : "+v"(v));
+    v &= 0x7FFFFFFF;
+}
+
 // Geometry of one column (fixed j and y) of colour c: everything but z.
 struct Column {
     int hcol;    // j + (L/2) y
@@ -349,6 +353,55 @@ __device__ __forceinline__ Site column_site(const Column &k, int z, int dzm, int
     return s;
 }
 
+// Colour- and sweep-independent site geometry of a lane in the column map with few sites
+// per lane (G >= plane, NZ <= 8), computed once per launch. Half-indices are those of the
+// lane's first site (t = 0); site t adds the compile-time offset plane * DZ * t.
+struct LaneGeom {
+    bool owns;             // lane < DZ * plane
+    int z0, zlast;
+    int b_own, b_ym, b_yp;  // own and y-neighbour half-indices
+    int b_zm, b_zp;         // z-1 neighbour of the first site, z+1 neighbour of the last (wrap-aware)
+    int dxm0, dxp1;         // x-1 offset when the x-parity is 0, x+1 offset when it is 1
+    int par0;               // x-parity of the first site for colour 0
+    int id00;               // site id of the first site for colour 0, less its x-parity
+};
+
+template <int LC, int G>
+struct ColzShape {
+    static constexpr int PLANE = LC * LC / 2;
+    static constexpr bool WIDE = LC != 0 && G >= PLANE;
+    static constexpr int DZ = WIDE ? G / PLANE : 1;
+    static constexpr int NZ = WIDE ? (LC + DZ - 1) / DZ : 0;
+    static constexpr bool FEW = WIDE && NZ <= 8;  // geometry kept in registers across sweeps
+};
+
+template <int LC, int G>
+__device__ __forceinline__ LaneGeom make_lane_geom(int lane)
+{
+    using S = ColzShape<LC, G>;
+    constexpr int PLANE = S::PLANE, DZ = S::DZ, NZ = S::NZ, HL = LC / 2;
+    LaneGeom q;
+    q.owns = lane < DZ * PLANE;
+    const int col = lane % PLANE, j = col % HL, y = col / HL;
+    q.z0 = lane / PLANE;
+    q.zlast = q.z0 + DZ * (NZ - 1);
+    q.b_own = col + PLANE * q.z0;
+    q.b_ym = q.b_own + ((y == 0) ? (LC - 1) * HL : -HL);
+    q.b_yp = q.b_own + ((y == LC - 1) ? -(LC - 1) * HL : HL);
+    q.b_zm = q.b_own + ((q.z0 == 0) ? (LC - 1) * PLANE : -PLANE);
+    q.b_zp = q.b_own + DZ * (NZ - 1) * PLANE + ((q.zlast == LC - 1) ? -(LC - 1) * PLANE : PLANE);
+    q.dxm0 = (j == 0) ? HL - 1 : -1;
+    q.dxp1 = (j == HL - 1) ? -(HL - 1) : 1;
+    q.par0 = (y + q.z0) & 1;
+    q.id00 = 2 * j + LC * y + LC * LC * q.z0;
+    opaque_nonneg(q.b_own);
+    opaque_nonneg(q.b_ym);
+    opaque_nonneg(q.b_yp);
+    opaque_nonneg(q.b_zm);
+    opaque_nonneg(q.b_zp);
+    return q;
+}
+
 // One half-sweep (colour c) of this lane's sites.
 //   COLZ (compile-time L): a lane owns whole columns (fixed x-pair and y) and a stride of z;
 //   for G >= plane (plane = L^2/2 sites of a colour) lane = column + plane z0 and
@@ -356,8 +409,9 @@ __device__ __forceinline__ Site column_site(const Column &k, int z, int dzm, int
 //   (the wrap-around planes z = 0 and L-1 peeled off).
 //   FLAT (any L): lane owns half-indices lane + G s.
 template <typename T, int LC, int G, int MAP>
-__device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, int c, uint32_t k, const Coef<T> &cf, T &pe,
-                                           T &pmx, T &pmy, T &pmz, unsigned long long &nacc)
+__device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, const LaneGeom &q, int c, uint32_t k,
+                                           const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
+                                           unsigned long long &nacc)
 {
     const int L = LC ? LC : g.L;
     const int HALF = L * L * L / 2;
@@ -370,24 +424,62 @@ __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, int c, uint32_t
     // spills) than it saves.
     int lane = g.lane;
     asm volatile("" : "+v"(lane));
+    // ... but its range stays known (non-negative bases let the backend fold the constant
+    // parts of the LDS addresses into the instructions' offset fields)
+    if constexpr ((G & (G - 1)) == 0) lane &= G - 1;
+    else __builtin_assume(lane >= 0 && lane < G);
     auto up = [&](const Site &s) { update_site<T>(g, own, oth, HALF, odd, s, k, cf, pe, pmx, pmy, pmz, nacc); };
     if constexpr (MAP == COLZ && LC != 0) {
         constexpr int PLANE = LC * LC / 2;
         if constexpr (G >= PLANE) {
             constexpr int DZ = G / PLANE;
             constexpr int NZ = (LC + DZ - 1) / DZ;
-            if (lane >= DZ * PLANE) return;
-            const int z0 = lane / PLANE;
-            const Column col = make_column(LC, lane % PLANE, c);
-            // wrap offsets: only the first z of a lane can be 0 and only its last L-1
-            const int zlast = z0 + DZ * (NZ - 1);
-            const int dzm0 = (z0 == 0) ? (LC - 1) * PLANE : -PLANE;
-            const int dzpl = (zlast == LC - 1) ? -(LC - 1) * PLANE : PLANE;
-            up(column_site<LC>(col, z0, dzm0, NZ == 1 ? dzpl : PLANE));
+            if constexpr (NZ > 8) {
+                if (lane >= DZ * PLANE) return;
+                const int z0 = lane / PLANE;
+                const Column col = make_column(LC, lane % PLANE, c);
+                // many sites per lane: a rolled loop (the wrap planes peeled)
+                const int zlast = z0 + DZ * (NZ - 1);
+                const int dzm0 = (z0 == 0) ? (LC - 1) * PLANE : -PLANE;
+                const int dzpl = (zlast == LC - 1) ? -(LC - 1) * PLANE : PLANE;
+                up(column_site<LC>(col, z0, dzm0, PLANE));
 #pragma unroll 2
-            for (int t = 1; t < NZ - 1; ++t) up(column_site<LC>(col, z0 + DZ * t, -PLANE, PLANE));
-            if constexpr (NZ > 1) {
+                for (int t = 1; t < NZ - 1; ++t) up(column_site<LC>(col, z0 + DZ * t, -PLANE, PLANE));
                 if ((LC % DZ) == 0 || zlast < LC) up(column_site<LC>(col, zlast, -PLANE, dzpl));
+                return;
+            }
+            // (uniform when every lane owns sites: the wave's accept count stays scalar)
+            if constexpr (DZ * PLANE < G) {
+                if (!q.owns) return;
+            }
+            // Colour-dependent part: the x-parity of the first site and the x-neighbours; the
+            // rest of the geometry comes from q. Opaque per half-sweep so that the counters'
+            // sweep-independent Philox work is not hoisted for all of the lane's sites.
+            const int p0 = q.par0 ^ c;
+            int b_xm0 = q.b_own + (p0 ? 0 : q.dxm0), b_xp0 = q.b_own + (p0 ? q.dxp1 : 0);
+            int b_xm1 = q.b_own + (p0 ? q.dxm0 : 0), b_xp1 = q.b_own + (p0 ? 0 : q.dxp1);
+            int id0 = q.id00 + p0;
+            opaque_nonneg(b_xm0);
+            opaque_nonneg(b_xp0);
+            opaque_nonneg(id0);
+            if constexpr (DZ & 1) {
+                opaque_nonneg(b_xm1);
+                opaque_nonneg(b_xp1);
+            }
+#pragma unroll
+            for (int t = 0; t < (NZ > 8 ? 1 : NZ); ++t) {
+                const int o = PLANE * DZ * t;
+                const bool flip = (DZ & 1) && (t & 1);
+                Site s;
+                s.h = q.b_own + o;
+                s.id = id0 + LC * LC * DZ * t + (flip ? (p0 ? -1 : 1) : 0);
+                s.nb[0] = (flip ? b_xm1 : b_xm0) + o;
+                s.nb[1] = (flip ? b_xp1 : b_xp0) + o;
+                s.nb[2] = q.b_ym + o;
+                s.nb[3] = q.b_yp + o;
+                s.nb[4] = t == 0 ? q.b_zm : q.b_own + o - PLANE;
+                s.nb[5] = t == NZ - 1 ? q.b_zp : q.b_own + o + PLANE;
+                if ((LC % DZ) == 0 || t < NZ - 1 || q.zlast < LC) up(s);
             }
         } else {
             constexpr int NCOL = (PLANE + G - 1) / G;
@@ -404,7 +496,7 @@ __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, int c, uint32_t
         }
     } else {
         const int SPL = (HALF + G - 1) / G;
-#pragma unroll 4
+#pragma unroll 2
         for (int s = 0; s < SPL; ++s) {
             const int h = lane + G * s;
             if (h < HALF) up(flat_site(L, h, c));
@@ -479,6 +571,12 @@ __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev 
 
     if (g.active && fresh) init_path<T, G>(g.sp, L, g.lane, g.path, g.key0, g.key1, g.ctr3, in.init);
     __syncthreads();
+    LaneGeom geom{};
+    if constexpr (MAP == COLZ && ColzShape<LC, G>::FEW) {
+        int lane = g.lane;
+        asm volatile("" : "+v"(lane));  // not hoisted out of a persistent kernel's item loop
+        geom = make_lane_geom<LC, G>(lane);
+    }
 
     for (int k = k0; k < k1; ++k) {
         if constexpr (std::is_same<T, float>::value) {
@@ -488,38 +586,38 @@ __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev 
             }
         }
         T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);
-        if (g.active) half_sweep<T, LC, G, MAP>(g, 0, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+        if (g.active) half_sweep<T, LC, G, MAP>(g, geom, 0, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
         __syncthreads();
-        if (g.active) half_sweep<T, LC, G, MAP>(g, 1, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+        if (g.active) half_sweep<T, LC, G, MAP>(g, geom, 1, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
         const bool meas = k >= n_therm || k < trace_sweeps || k == k1 - 1;
         if (meas) {
-            pe = wave_sum(pe);
-            pmx = wave_sum(pmx);
-            pmy = wave_sum(pmy);
-            pmz = wave_sum(pmz);
-            if ((g.lane & 63) == 0) {
-                g.red[4 * wave + 0] = pe;
-                g.red[4 * wave + 1] = pmx;
-                g.red[4 * wave + 2] = pmy;
-                g.red[4 * wave + 3] = pmz;
+            // sums over each 16-lane row; one lane per row leaves its row's four partials
+            pe = row_sum(pe);
+            pmx = row_sum(pmx);
+            pmy = row_sum(pmy);
+            pmz = row_sum(pmz);
+            if ((g.lane & 15) == 0) {
+                T *slot = g.red + 4 * (g.lane >> 4);
+                slot[0] = pe;
+                slot[1] = pmx;
+                slot[2] = pmy;
+                slot[3] = pmz;
             }
         }
         __syncthreads();
         if (meas && g.active && wave == 0) {
-            // the group's first wave adds up the wave partials (one wave per lane)
+            // the group's first wave adds up the row partials (one row per lane)
             T se = T(0), sx = T(0), sy = T(0), sz = T(0);
-            if (g.lane < W) {
+            if (g.lane < 4 * W) {
                 se = g.red[4 * g.lane + 0];
                 sx = g.red[4 * g.lane + 1];
                 sy = g.red[4 * g.lane + 2];
                 sz = g.red[4 * g.lane + 3];
             }
-            if constexpr (W > 1) {
-                se = first_lanes_sum(se);
-                sx = first_lanes_sum(sx);
-                sy = first_lanes_sum(sy);
-                sz = first_lanes_sum(sz);
-            }
+            se = wave_sum(se);
+            sx = wave_sum(sx);
+            sy = wave_sum(sy);
+            sz = wave_sum(sz);
             if (g.lane == 0) {
                 // Every bond joins an even and an odd site: E = -J sum_odd S_i . h_i.
                 const double e = -J * (double)se / Nd;
@@ -571,12 +669,13 @@ __device__ __attribute__((noinline)) void copy_spins(T *__restrict__ dst, const 
     for (int t = lane; t < n; t += G) dst[t] = src[t];
 }
 
-// LDS bytes of one workgroup: spins (LDS placement), accumulators, reduction slots.
+// LDS bytes of one workgroup: spins (LDS placement), accumulators, reduction slots (four
+// partials per 16-lane row).
 template <typename T>
 __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, bool in_lds)
 {
     return (in_lds ? (size_t)(B / G) * 3 * (size_t)L * L * L * sizeof(T) : 0) + (size_t)(B / G) * 128 +
-           (size_t)(B / 64) * 4 * sizeof(T);
+           (size_t)(B / 16) * 4 * sizeof(T);
 }
 
 // Sets up the group views of one workgroup and runs sweeps [k0, k1) for paths
@@ -606,7 +705,7 @@ __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int
     if (IN_LDS) p += P * NS * sizeof(T);
     g.shacc = reinterpret_cast<double *>(p) + 16 * group;
     p += P * 128;
-    g.red = reinterpret_cast<T *>(p) + 4 * (group * (G / 64));
+    g.red = reinterpret_cast<T *>(p) + 16 * (group * (G / 64));
     T *gsp = gbase + (size_t)group * NS;
     g.sp = IN_LDS ? lds_spins + (size_t)group * NS : gsp;
 
