@@ -1,16 +1,20 @@
 """Benchmark: Metropolis spin updates/s of the batched FP32 multipath engine on one MI355X.
 
-Workload (one step): L = 16 classical Heisenberg lattices at T = 1.2, 1.443 and 1.7, 4096
-independent paths per temperature, each from a random start through 2000 thermalisation and
-8000 measured checkerboard sweeps (FP32 spins and fields, FP64 accumulators), then the FP64
-cross-path statistics -- 5.03e11 spin updates per step, in one persistent hipGraph launch.
+Default workload (one step): L = 16 classical Heisenberg lattices at T = 1.2, 1.443 and 1.7,
+4096 independent paths per temperature, each from a random start through 2000 thermalisation
+and 8000 measured checkerboard sweeps (FP32 spins and fields, FP64 accumulators), then the
+FP64 cross-path statistics -- 5.03e11 spin updates per step, in one persistent hipGraph launch.
 
 Also reported on the same GPU: the plain per-instance FP64 engine on the same workload, the
 4-standard-error agreement of the FP32 results with the FP64 CPU oracle (sampled paths,
 stored by tests/golden/make_oracle_golden.py), the VALU roofline of the batch kernel, and
 the oracle itself timed on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-plain] [--skip-cpu]
+--workload selects another batched FP32 workload of paper_1305_6758_amd/workloads.py (same
+JSON line; the plain FP64 comparison runs only where its resident spins fit). For the
+Binder-cumulant workload the line also carries the cumulants, their ratio and the crossing.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--skip-plain] [--skip-cpu]
 """
 import argparse
 import json
@@ -48,15 +52,21 @@ UPDATE_OPS_F32 = {
     "v_add_f32": 18, "v_cmp_lt_f32": 1, "v_cndmask_b32": 3,
 }
 SLOTS_PER_UPDATE_F32 = sum(n * VALU_PEAK / OP_RATES[op] for op, n in UPDATE_OPS_F32.items())
-COUNTERS = os.path.join(ROOT, "profiles", "k_batch_f32_L16-T3-p4096_counters.md")
+# resident FP64 spins the plain engine may hold (its comparison is skipped above this)
+PLAIN_FP64_MAX_BYTES = 64 << 30
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed counter summary, or None when the kernels have
-    changed since those counters were taken."""
+def counters_file(workload):
+    short = workload[:-5] if workload.endswith("-fp32") else workload
+    return os.path.join(ROOT, "profiles", f"k_batch_f32_{short}_counters.md")
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed counter summary of the workload, or None when
+    there is none or the kernels have changed since those counters were taken."""
     import hashlib
     try:
-        text = open(COUNTERS).read()
+        text = open(counters_file(workload)).read()
     except OSError:
         return None
     sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1305_6758_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()[:16]
@@ -76,8 +86,8 @@ def four_sigma_vs_oracle(results, golden):
     out = []
     ok = True
     for inst, res in zip(golden["instances"], results):
-        row = {"T": inst["T"], "oracle_paths": len(inst["e_mean"])}
-        for key in ("e_mean", "absm_mean"):
+        row = {"L": inst["L"], "T": inst["T"], "oracle_paths": len(inst["e_mean"])}
+        for key in ("e_mean", "absm_mean", "m2_mean", "m4_mean"):
             a = np.asarray(res[key])
             b = np.asarray(inst[key])
             d = abs(a.mean() - b.mean())
@@ -139,26 +149,43 @@ def run_plain_fp64(instances):
 
 
 def cpu_baseline(instances):
-    """The FP64 CPU oracle as it stands, on the host cores: three paths per thread of the
-    T = 1.443 instance, all of their sweeps (about 10-30 s of CPU work)."""
+    """The FP64 CPU oracle as it stands, on the host cores: paths of one instance (the
+    second, or the only one), all of their sweeps, as many per thread as keep the sample near
+    15 s of CPU work (at least one per thread)."""
     from oracle import oracle as O
     threads = O.max_threads()
-    L, T, p, nt, nm = instances[1]
-    n = 3 * threads
+    idx = 1 if len(instances) > 1 else 0
+    L, T, p, nt, nm = instances[idx]
+    per_path = L ** 3 * (nt + nm)
+    per_thread = max(1, min(3, int(1.5e8 / per_path)))  # about 1e7 updates/s per thread
+    n = min(p, per_thread * threads)
     t0 = time.perf_counter()
-    O.run_paths(L, T, n_therm=nt, n_meas=nm, seed=1234, path_begin=0, path_end=n, instance=1, n_threads=threads)
+    O.run_paths(L, T, n_therm=nt, n_meas=nm, seed=1234, path_begin=0, path_end=n, instance=idx, n_threads=threads)
     dt = time.perf_counter() - t0
-    upd = n * L ** 3 * (nt + nm)
+    upd = n * per_path
     return {"value": upd / dt, "unit": "spin updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} paths (3 per thread) of the L=16, T=1.443 instance, all "
+            "sample": f"first {n} paths of the L={L}, T={T:g} instance (instance {idx}), all "
                       f"{nt}+{nm} sweeps: {upd:.3e} updates in {dt:.1f} s"}
+
+
+def binder_summary(instances, results):
+    """Cumulants of the four (L, T) instances, their ratio and the crossing (Sec. 5)."""
+    from paper_1305_6758_amd import mmc
+    cum = [mmc.mmc_binder_cumulant(r) for r in results]
+    T1, T2 = instances[0][1], instances[2][1]
+    cross = mmc.mmc_cumulant_crossing(T1, T2, [c[0] for c in cum], [c[1] for c in cum])
+    return {"cumulants": [{"L": L, "T": T, "U": c[0], "se": c[1]} for (L, T, *_), c in zip(instances, cum)],
+            "ratio": [{"T": T1, "R": cross["r_t1"], "se": cross["se_r_t1"]},
+                      {"T": T2, "R": cross["r_t2"], "se": cross["se_r_t2"]}],
+            "tc": cross["tc"], "se_tc": cross["se_tc"]}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 3; 1 off the default workload)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default 1; 0 off the default workload)")
+    ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     a = ap.parse_args()
@@ -169,46 +196,64 @@ def main():
         sys.exit(2)
 
     from paper_1305_6758_amd.workloads import WORKLOADS, updates
-    instances = WORKLOADS[WORKLOAD]["instances"]
+    if a.workload not in WORKLOADS:
+        print(f"unknown workload {a.workload}; one of {sorted(WORKLOADS)}", file=sys.stderr)
+        sys.exit(2)
+    default = a.workload == WORKLOAD
+    steps = a.steps if a.steps is not None else (3 if default else 1)
+    warmup = a.warmup if a.warmup is not None else (1 if default else 0)
+    if steps < 1 or warmup < 0:
+        print("need --steps >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+    instances = WORKLOADS[a.workload]["instances"]
     upd_step = updates(instances)
 
-    wall, kernel_ms, results, stats, plan = run_batched(instances, a.steps, a.warmup)
-    value = upd_step * a.steps / wall
+    wall, kernel_ms, results, stats, plan = run_batched(instances, steps, warmup)
+    value = upd_step * steps / wall
     kms = sum(kernel_ms) / len(kernel_ms)
     achieved = SLOTS_PER_UPDATE_F32 * upd_step / (kms * 1e-3)
 
-    golden_path = os.path.join(ROOT, "tests", "golden", f"oracle_{WORKLOAD}.json")
+    golden_path = os.path.join(ROOT, "tests", "golden", f"oracle_{a.workload}.json")
     parity = None
     if os.path.exists(golden_path):
         with open(golden_path) as f:
             ok, rows = four_sigma_vs_oracle(results, json.load(f))
-        parity = {"agree_4sigma": ok, "per_temperature": rows}
+        parity = {"agree_4sigma": ok, "per_instance": rows}
 
+    Ls = sorted({x[0] for x in instances})
+    config = {"workload": a.workload, "L": Ls[0] if len(Ls) == 1 else Ls,
+              "T": sorted({x[1] for x in instances}), "instances": len(instances),
+              "paths": sum(x[2] for x in instances), "n_therm": sorted({x[3] for x in instances}),
+              "n_meas": sorted({x[4] for x in instances}), "updates_per_step": upd_step, "seed": 1234,
+              "plan": plan}
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "spin updates/s",
         "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": wall / a.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "L": 16, "T": [1.2, 1.443, 1.7], "paths_per_T": 4096,
-                   "n_therm": 2000, "n_meas": 8000, "updates_per_step": upd_step, "seed": 1234, "plan": plan},
+        "config": config,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
+                     "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(a.workload),
                      "kernel": "k_batch<float>", "kernel_ms": kms,
                      "lane_slots_per_update": SLOTS_PER_UPDATE_F32,
                      "ceiling_updates_per_s": VALU_PEAK / SLOTS_PER_UPDATE_F32},
         "parity": parity,
-        "stats": [{k: s[k] for k in ("mean_e", "se_e", "mean_absm", "se_absm", "chi", "cv_heat", "binder",
-                                     "r_e", "p_norm_e", "accept_rate")} for s in stats],
     }
-    if not a.skip_plain:
+    if len(instances) <= 16:
+        out["stats"] = [{k: s[k] for k in ("mean_e", "se_e", "mean_absm", "se_absm", "chi", "cv_heat", "binder",
+                                           "r_e", "p_norm_e", "accept_rate")} for s in stats]
+    if a.workload.startswith("binder-"):
+        out["experiment"] = binder_summary(instances, results)
+    fits = sum(p * 3 * 8 * L ** 3 for (L, T, p, nt, nm) in instances) <= PLAIN_FP64_MAX_BYTES
+    if not a.skip_plain and fits:
         pwall, pms, presults = run_plain_fp64(instances)
         out["fp64_plain"] = {"value": upd_step / pwall, "unit": "spin updates/s", "kernel_ms": pms,
                              "speedup_of_batched_fp32": value / (upd_step / pwall)}

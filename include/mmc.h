@@ -180,6 +180,29 @@ int mmc_stats(const mmc_ctx *ctx, mmc_stats_t *out);
 /* Statistics of any result array (host only, no GPU needed); N = L^3. */
 int mmc_stats_from_results(const mmc_path_result *res, int n, int L, double T, mmc_stats_t *out);
 
+/* Fourth-order (Binder) cumulant of n path results, eq. (kum): U = 1 - <M^4>/(3 <M^2>^2) with
+ * <.> the mean over paths of each path's m4_mean and m2_mean (with n_meas = 1 these are the
+ * final state's |M|^4 and |M|^2, the paper's single-output paths). *se is the first-order
+ * standard error from the cross-path sample covariance of (M^2, M^4), paths independent.
+ * Host only. MMC_EINVAL for null pointers or n < 2. */
+int mmc_binder_cumulant(const mmc_path_result *res, int n, double *U, double *se);
+
+/* Critical-temperature estimate from two lattice sizes L > L' at two temperatures (Sec. 5:
+ * U_L(Tc)/U_L'(Tc) = 1), the ratio R(T) = U_L/U_L' taken linear between T1 and T2.
+ * u = {U_L(T1), U_L'(T1), U_L(T2), U_L'(T2)}, se = their standard errors (independent runs).
+ * Fills r_t1/se_r_t1, r_t2/se_r_t2 (the ratios and their errors), tc and its first-order error
+ * se_tc. Host only. MMC_EINVAL for null pointers, T1 == T2, a zero cumulant or R(T1) == R(T2). */
+typedef struct {
+    double tc, se_tc;
+    double r_t1, se_r_t1, r_t2, se_r_t2;
+} mmc_crossing_t;
+int mmc_cumulant_crossing(double T1, double T2, const double *u, const double *se, mmc_crossing_t *out);
+
+/* Distribution coefficient of a sample, eq. (dist-coefficient) (Sec. 3): least-squares line
+ * through the normal Q-Q plot at Filliben's order-statistic medians, r = 1 - |R|^2/((n-1) s^2).
+ * Host only; x is not modified. MMC_EINVAL for null pointers or n < 3. */
+int mmc_distribution_coefficient(const double *x, int n, double *r);
+
 /* Writes a checkpoint (configuration, plan, sweeps done, spins, accumulators, trace). */
 int mmc_save(const mmc_ctx *ctx, const char *file);
 

@@ -10,7 +10,10 @@ Paper (arXiv:1305.6758):
   - susceptibility and heat capacity, eq. (cv): chi = (L^3/T)(<M^2> - <M>^2),
     C_V = (L^3/T^2)(<H^2> - <H>^2); with per-path time averages the brackets are
     cross-path means of the per-path averaged moments;
-  - Binder cumulant, eq. (kum): U_L = 1 - <M^4> / (3 <M^2>^2);
+  - Binder cumulant, eq. (kum): U_L = 1 - <M^4> / (3 <M^2>^2), with a first-order
+    (delta-method) standard error from the cross-path covariance of (M^2, M^4);
+  - critical temperature from the cumulant ratio, Sec. 5 (Fig. TCfig): U_L(Tc)/U_L'(Tc) = 1,
+    the ratio taken linear in T between the two simulated temperatures;
   - distribution coefficient, eq. (dist-coefficient), Sec. 3: least-squares line through
     the normal Q-Q plot, r = 1 - ||R||^2 / ((N-1) sigma^2);
   - coefficient of variation of the mean, eq. (eq:cv), Sec. 4.1: sigma_X / (sqrt(N) mean).
@@ -104,6 +107,45 @@ def normality_k2(x):
     b2 = m4 / (m2 * m2)
     k2 = _z_skew(b1, n) ** 2 + _z_kurt(b2, n) ** 2
     return k2, math.exp(-0.5 * k2)
+
+
+def binder_cumulant(m2, m4):
+    """eq. (kum) and its standard error. U = 1 - A/(3 B^2) with A, B the cross-path means of
+    the per-path M^4 and M^2 (independent paths). To first order in the fluctuations of the
+    means, var U = (gA^2 s_AA + 2 gA gB s_AB + gB^2 s_BB)/n with gA = dU/dA = -1/(3 B^2),
+    gB = dU/dB = 2A/(3 B^3) and s the sample (co)variances (n - 1)."""
+    b = np.asarray(m2, dtype=np.float64)
+    a = np.asarray(m4, dtype=np.float64)
+    n = a.size
+    A = a.sum() / n
+    B = b.sum() / n
+    U = 1.0 - A / (3.0 * B * B)
+    ga = -1.0 / (3.0 * B * B)
+    gb = 2.0 * A / (3.0 * B ** 3)
+    da, db = a - A, b - B
+    saa = (da * da).sum() / (n - 1)
+    sbb = (db * db).sum() / (n - 1)
+    sab = (da * db).sum() / (n - 1)
+    var = (ga * ga * saa + 2.0 * ga * gb * sab + gb * gb * sbb) / n
+    return U, math.sqrt(max(var, 0.0))
+
+
+def cumulant_crossing(T1, T2, u, se):
+    """Sec. 5: the temperature where U_L / U_L' = 1, with the ratio R(T) taken linear between
+    T1 and T2. u = (U_L(T1), U_L'(T1), U_L(T2), U_L'(T2)) and se their standard errors, all four
+    estimates independent. Returns (Tc, se_Tc, R1, se_R1, R2, se_R2).
+
+    R_j = U_L(Tj)/U_L'(Tj), se(R_j) = |R_j| sqrt((se_L/U_L)^2 + (se_L'/U_L')^2);
+    Tc = T1 + (1 - R1)(T2 - T1)/(R2 - R1), and to first order
+    se(Tc) = |T2 - T1| sqrt(((1 - R2) se(R1))^2 + ((1 - R1) se(R2))^2) / (R2 - R1)^2."""
+    R1 = u[0] / u[1]
+    R2 = u[2] / u[3]
+    s1 = abs(R1) * math.hypot(se[0] / u[0], se[1] / u[1])
+    s2 = abs(R2) * math.hypot(se[2] / u[2], se[3] / u[3])
+    dT = T2 - T1
+    Tc = T1 + (1.0 - R1) * dT / (R2 - R1)
+    sTc = abs(dT) * math.hypot((1.0 - R2) * s1, (1.0 - R1) * s2) / (R2 - R1) ** 2
+    return Tc, sTc, R1, s1, R2, s2
 
 
 def path_statistics(res, L, T, dim=3):

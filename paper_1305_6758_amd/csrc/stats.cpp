@@ -1,6 +1,6 @@
 // stats.cpp -- host FP64 cross-path statistics of the simulation output
 // (arXiv:1305.6758: eq. (MCAV), eq. (M_and_H), the moments <|M|^k>, eq. (cv), eq. (kum),
-// eq. (dist-coefficient), eq. (eq:cv)).
+// eq. (dist-coefficient), eq. (eq:cv), and the cumulant-ratio crossing of Sec. 5).
 #include <math.h>
 
 #include <algorithm>
@@ -176,5 +176,61 @@ extern "C" int mmc_stats_from_results(const mmc_path_result *res, int n, int L, 
     s.accept_rate = NAN;  // filled by callers that know the number of attempts
     (void)acc;
     *out = s;
+    return MMC_OK;
+}
+
+extern "C" int mmc_binder_cumulant(const mmc_path_result *res, int n, double *U, double *se)
+{
+    if (!res || !U || !se || n < 2) return MMC_EINVAL;
+    const double nd = (double)n;
+    double A = 0, B = 0;
+    for (int i = 0; i < n; ++i) {
+        A += res[i].m4_mean;
+        B += res[i].m2_mean;
+    }
+    A /= nd;
+    B /= nd;
+    double saa = 0, sbb = 0, sab = 0;
+    for (int i = 0; i < n; ++i) {
+        const double da = res[i].m4_mean - A, db = res[i].m2_mean - B;
+        saa += da * da;
+        sbb += db * db;
+        sab += da * db;
+    }
+    saa /= nd - 1;
+    sbb /= nd - 1;
+    sab /= nd - 1;
+    // first-order propagation: gradient of 1 - A/(3B^2) in (A, B)
+    const double gA = -1.0 / (3.0 * B * B), gB = 2.0 * A / (3.0 * B * B * B);
+    const double var = (gA * gA * saa + 2.0 * gA * gB * sab + gB * gB * sbb) / nd;
+    *U = 1.0 - A / (3.0 * B * B);
+    *se = sqrt(var > 0 ? var : 0.0);
+    return MMC_OK;
+}
+
+extern "C" int mmc_cumulant_crossing(double T1, double T2, const double *u, const double *se, mmc_crossing_t *out)
+{
+    if (!u || !se || !out || !(T1 != T2)) return MMC_EINVAL;
+    for (int i = 0; i < 4; ++i)
+        if (!(u[i] != 0) || !isfinite(u[i]) || !(se[i] >= 0)) return MMC_EINVAL;
+    mmc_crossing_t c;
+    c.r_t1 = u[0] / u[1];
+    c.r_t2 = u[2] / u[3];
+    if (!(c.r_t2 != c.r_t1)) return MMC_EINVAL;
+    c.se_r_t1 = fabs(c.r_t1) * hypot(se[0] / u[0], se[1] / u[1]);
+    c.se_r_t2 = fabs(c.r_t2) * hypot(se[2] / u[2], se[3] / u[3]);
+    // R linear in T: R(Tc) = 1
+    const double slope = c.r_t2 - c.r_t1, dT = T2 - T1;
+    c.tc = T1 + (1.0 - c.r_t1) * dT / slope;
+    // dTc/dR1 = dT (1 - R2)/slope^2, dTc/dR2 = -dT (1 - R1)/slope^2
+    c.se_tc = fabs(dT) * hypot((1.0 - c.r_t2) * c.se_r_t1, (1.0 - c.r_t1) * c.se_r_t2) / (slope * slope);
+    *out = c;
+    return MMC_OK;
+}
+
+extern "C" int mmc_distribution_coefficient(const double *x, int n, double *r)
+{
+    if (!x || !r || n < 3) return MMC_EINVAL;
+    *r = mmc::distribution_coefficient(std::vector<double>(x, x + n));
     return MMC_OK;
 }

@@ -39,6 +39,11 @@ class mmc_stats_t(C.Structure):
                 ("p_norm_absm", C.c_double), ("accept_rate", C.c_double)]
 
 
+class mmc_crossing_t(C.Structure):
+    _fields_ = [("tc", C.c_double), ("se_tc", C.c_double), ("r_t1", C.c_double), ("se_r_t1", C.c_double),
+                ("r_t2", C.c_double), ("se_r_t2", C.c_double)]
+
+
 class mmc_instance(C.Structure):
     _fields_ = [("L", C.c_int), ("T", C.c_double), ("J", C.c_double), ("n_paths", C.c_int),
                 ("n_therm", C.c_int), ("n_meas", C.c_int)]
@@ -72,6 +77,11 @@ _SIGNATURES = [
     ("mmc_stats", C.c_int, [_P, C.POINTER(mmc_stats_t)]),
     ("mmc_stats_from_results", C.c_int, [C.POINTER(mmc_path_result), C.c_int, C.c_int, C.c_double,
                                          C.POINTER(mmc_stats_t)]),
+    ("mmc_binder_cumulant", C.c_int, [C.POINTER(mmc_path_result), C.c_int, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]),
+    ("mmc_cumulant_crossing", C.c_int, [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(mmc_crossing_t)]),
+    ("mmc_distribution_coefficient", C.c_int, [C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]),
     ("mmc_save", C.c_int, [_P, C.c_char_p]),
     ("mmc_load", _P, [C.c_char_p]),
     ("mmc_last_timing_ms", C.c_double, [_P]),
@@ -173,18 +183,35 @@ def mmc_sweeps_done(ctx):
     return lib().mmc_sweeps_done(ctx)
 
 
-def _results_to_numpy(res):
-    out = {k: np.array([getattr(r, k) for r in res]) for k in
-           ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e")}
-    out["final_m"] = np.array([list(r.final_m) for r in res]).reshape(len(res), 3)
-    out["n_accept"] = np.array([r.n_accept for r in res], dtype=np.uint64)
-    return out
+# numpy view of mmc_path_result (same field order, 80 bytes, no padding)
+RESULT_DTYPE = np.dtype([("e_mean", "<f8"), ("e2_mean", "<f8"), ("absm_mean", "<f8"), ("m2_mean", "<f8"),
+                         ("m4_mean", "<f8"), ("final_m", "<f8", (3,)), ("final_e", "<f8"), ("n_accept", "<u8")])
+assert RESULT_DTYPE.itemsize == C.sizeof(mmc_path_result)
+
+
+def _result_buffer(n):
+    buf = np.zeros(n, dtype=RESULT_DTYPE)
+    return buf, buf.ctypes.data_as(C.POINTER(mmc_path_result))
+
+
+def _results_to_numpy(buf):
+    return {k: np.array(buf[k]) for k in RESULT_DTYPE.names}
+
+
+def _results_array(results):
+    """dict of per-path arrays (as returned by mmc_results) -> C array of mmc_path_result."""
+    n = len(results["e_mean"])
+    buf, ptr = _result_buffer(n)
+    for k in RESULT_DTYPE.names:
+        if k in results:
+            buf[k] = np.asarray(results[k]).reshape(buf[k].shape)
+    return buf, ptr, n
 
 
 def mmc_results(ctx, n_paths):
-    res = (mmc_path_result * n_paths)()
-    _check(lib().mmc_results(ctx, res, n_paths))
-    return _results_to_numpy(res)
+    buf, ptr = _result_buffer(n_paths)
+    _check(lib().mmc_results(ctx, ptr, n_paths))
+    return _results_to_numpy(buf)
 
 
 def mmc_trace(ctx, n_paths, trace_sweeps):
@@ -211,18 +238,34 @@ def mmc_stats(ctx):
 
 def mmc_stats_from_results(results, L, T):
     """results: dict of arrays as returned by mmc_results."""
-    n = len(results["e_mean"])
-    arr = (mmc_path_result * n)()
-    for i in range(n):
-        r = arr[i]
-        for k in ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e"):
-            setattr(r, k, float(results[k][i]))
-        for a in range(3):
-            r.final_m[a] = float(results["final_m"][i][a])
-        r.n_accept = int(results["n_accept"][i])
+    buf, ptr, n = _results_array(results)
     s = mmc_stats_t()
-    _check(lib().mmc_stats_from_results(arr, n, L, T, C.byref(s)))
+    _check(lib().mmc_stats_from_results(ptr, n, L, T, C.byref(s)))
     return _stats_dict(s)
+
+
+def mmc_binder_cumulant(results):
+    """(U, se) of eq. (kum) over the paths of results (dict of arrays)."""
+    buf, ptr, n = _results_array(results)
+    U, se = C.c_double(), C.c_double()
+    _check(lib().mmc_binder_cumulant(ptr, n, C.byref(U), C.byref(se)))
+    return U.value, se.value
+
+
+def mmc_cumulant_crossing(T1, T2, u, se):
+    """u, se: (U_L(T1), U_L'(T1), U_L(T2), U_L'(T2)) and their errors -> dict of mmc_crossing_t."""
+    cu = (C.c_double * 4)(*[float(x) for x in u])
+    cs = (C.c_double * 4)(*[float(x) for x in se])
+    out = mmc_crossing_t()
+    _check(lib().mmc_cumulant_crossing(float(T1), float(T2), cu, cs, C.byref(out)))
+    return {name: getattr(out, name) for name, _ in mmc_crossing_t._fields_}
+
+
+def mmc_distribution_coefficient(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    r = C.c_double()
+    _check(lib().mmc_distribution_coefficient(x.ctypes.data_as(C.POINTER(C.c_double)), x.size, C.byref(r)))
+    return r.value
 
 
 def mmc_save(ctx, path):
@@ -258,9 +301,9 @@ def mmc_batch_run(ctx):
 
 
 def mmc_batch_results(ctx, inst, n_paths):
-    res = (mmc_path_result * n_paths)()
-    _check(lib().mmc_batch_results(ctx, inst, res, n_paths))
-    return _results_to_numpy(res)
+    buf, ptr = _result_buffer(n_paths)
+    _check(lib().mmc_batch_results(ctx, inst, ptr, n_paths))
+    return _results_to_numpy(buf)
 
 
 def mmc_batch_stats(ctx, inst):

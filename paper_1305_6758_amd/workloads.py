@@ -24,6 +24,11 @@ WORKLOADS = {
     "L32-T1.443-p1024": dict(precision="both", instances=[(32, 1.443, 1024, 5000, 5000)]),
     # L = 64 at T = 1.443, 256 paths, device-memory spins, FP32.
     "L64-T1.443-p256-fp32": dict(precision="fp32", instances=[(64, 1.443, 256, 10000, 10000)]),
+    # Critical temperature from the Binder-cumulant ratio U_30/U_20 (Sec. 5): L = 30 and 20 at
+    # T = 1.44 and 1.45, 10^6 single-output paths each (random start, 200 sweeps, the final
+    # state measured: 199 thermalisation sweeps + 1 measured sweep), FP32.
+    "binder-L30-L20-p1e6-fp32": dict(precision="fp32", instances=[(L, T, 10 ** 6, 199, 1)
+                                                                   for T in (1.44, 1.45) for L in (30, 20)]),
 }
 
 BATCH_LS = (8, 12, 16, 24, 32, 48)

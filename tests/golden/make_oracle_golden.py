@@ -27,6 +27,7 @@ SAMPLE = {
     "L32-T1.443-p1024": 16,
     "L64-T1.443-p256-fp32": 8,
     "uneven-batch-96-fp32": 2,
+    "binder-L30-L20-p1e6-fp32": 256,
 }
 
 

@@ -113,3 +113,28 @@ def test_workload_recipes():
 def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_host_binder_crossing_and_r_match_oracle_statistics():
+    """mmc_binder_cumulant, mmc_cumulant_crossing and mmc_distribution_coefficient (C++ host
+    code) against the oracle's statistics on oracle snapshot output (n_meas = 1)."""
+    from paper_1305_6758_amd import mmc
+    us, ses = [], []
+    for (L, T) in [(4, 1.3), (2, 1.3), (4, 1.6), (2, 1.6)]:
+        r = O.run_paths(L, T, n_therm=40, n_meas=1, path_end=300, seed=5)
+        U, se = mmc.mmc_binder_cumulant(r)
+        Ur, ser = S.binder_cumulant(r["m2_mean"], r["m4_mean"])
+        assert abs(U - Ur) < 1e-13 and abs(se - ser) < 1e-13 * max(1.0, ser)
+        us.append(U)
+        ses.append(se)
+        for a in range(3):
+            x = r["final_m"][:, a]
+            assert abs(mmc.mmc_distribution_coefficient(x) - S.distribution_coefficient(x)) < 1e-12
+    got = mmc.mmc_cumulant_crossing(1.3, 1.6, us, ses)
+    ref = S.cumulant_crossing(1.3, 1.6, us, ses)
+    for k, v in zip(("tc", "se_tc", "r_t1", "se_r_t1", "r_t2", "se_r_t2"), ref):
+        assert abs(got[k] - v) <= 1e-12 * max(1.0, abs(v)), k
+    with pytest.raises(mmc.MMCError):
+        mmc.mmc_cumulant_crossing(1.0, 1.0, us, ses)
+    with pytest.raises(mmc.MMCError):
+        mmc.mmc_distribution_coefficient([1.0, 2.0])

@@ -375,3 +375,56 @@ def test_binder_and_cv_definitions():
     assert abs(st["binder"] - (2.0 / 3.0 - 2.0 * (N - 1) / (9.0 * N))) < 1e-14
     x = np.random.default_rng(5).uniform(1, 2, size=300)
     assert abs(S.coeff_variation(x) - ss.variation(x, ddof=1) / math.sqrt(x.size)) < 1e-15
+
+
+def test_binder_cumulant_error_by_repetition():
+    """eq. (kum) with its delta-method error, pinned two ways on paths whose total spin is an
+    isotropic Gaussian vector (the high-temperature limit of M): U -> 1 - 15/(3*9) = 4/9
+    (E|g|^2 = 3, E|g|^4 = 15 for g ~ N(0, I_3)), and the reported standard error equals the
+    spread of U over independent repetitions (a dropped covariance term would overstate it
+    about 11-fold, a wrong sign in dU/d<M^2> about 21-fold)."""
+    rng = np.random.default_rng(21)
+    reps, n = 300, 4000
+    g = rng.standard_normal((reps, n, 3))
+    m2 = (g * g).sum(axis=2)
+    m4 = m2 * m2
+    us, ses = np.empty(reps), np.empty(reps)
+    for k in range(reps):
+        us[k], ses[k] = S.binder_cumulant(m2[k], m4[k])
+    assert abs(us.mean() - 4.0 / 9.0) < 4.0 * us.std(ddof=1) / math.sqrt(reps)
+    assert abs(us.std(ddof=1) / ses.mean() - 1.0) < 0.12
+    # leave-one-out jackknife on one sample agrees with the first-order error
+    a, b = m4[0], m2[0]
+    A, B = a.sum(), b.sum()
+    jk = 1.0 - ((A - a) / (n - 1)) / (3.0 * ((B - b) / (n - 1)) ** 2)
+    se_jk = math.sqrt((n - 1) / n * ((jk - jk.mean()) ** 2).sum())
+    assert abs(se_jk / ses[0] - 1.0) < 0.03
+
+
+def test_binder_cumulant_of_oracle_runs_at_infinite_temperature():
+    """Snapshot output (n_meas = 1) at beta ~ 0 on L = 2 (N = 8 independent unit spins once
+    every site has been redrawn): U = 2/3 - 2(N-1)/(9N) within 4 standard errors."""
+    N = 8
+    r = O.run_paths(2, 1e12, n_therm=1, n_meas=1, path_end=6000, seed=77)
+    U, se = S.binder_cumulant(r["m2_mean"], r["m4_mean"])
+    exact = 2.0 / 3.0 - 2.0 * (N - 1) / (9.0 * N)
+    assert 0 < se < 0.01
+    assert abs(U - exact) < 4.0 * se
+
+
+def test_cumulant_crossing_exact_and_error():
+    """Sec. 5 crossing: a ratio linear in T through 1 at Tc gives Tc to rounding; the
+    propagated error matches the spread of Tc under independent noise on the four cumulants."""
+    Tc0, k = 1.442, -3.7
+    T1, T2 = 1.44, 1.45
+    v1, v2 = 0.61, 0.58
+    u = np.array([(1 + k * (T1 - Tc0)) * v1, v1, (1 + k * (T2 - Tc0)) * v2, v2])
+    se = np.array([1e-4, 2e-4, 1.5e-4, 0.5e-4])
+    Tc, sTc, R1, s1, R2, s2 = S.cumulant_crossing(T1, T2, u, se)
+    assert abs(Tc - Tc0) < 1e-13
+    assert abs(R1 - (1 + k * (T1 - Tc0))) < 1e-15 and abs(R2 - (1 + k * (T2 - Tc0))) < 1e-15
+    rng = np.random.default_rng(8)
+    draws = u + rng.standard_normal((20000, 4)) * se
+    tcs = np.array([S.cumulant_crossing(T1, T2, d, se)[0] for d in draws])
+    assert abs(tcs.std(ddof=1) / sTc - 1.0) < 0.04
+    assert abs(tcs.mean() - Tc0) < 4.0 * sTc / math.sqrt(draws.shape[0]) + 1e-6
