@@ -58,9 +58,17 @@ typedef enum {
 typedef enum { MMC_FP32 = 0, MMC_FP64 = 1 } mmc_precision;
 
 /* Initial state (Sec. 2.2): SPHERE draws each spin uniformly on the sphere; ANGLES draws
- * both spherical angles uniformly (the paper's literal "random values of both angles");
- * ORDERED starts with every spin along +z. */
-typedef enum { MMC_INIT_SPHERE = 0, MMC_INIT_ANGLES = 1, MMC_INIT_ORDERED = 2 } mmc_init;
+ * both spherical angles uniformly (the paper's random start taken literally); ORDERED starts
+ * with every spin along +z; MIXED is the two-start set-up of Sec. 4 (half of the paths from
+ * a random start, half ordered): paths with an even index start as SPHERE, odd ones ORDERED. */
+typedef enum { MMC_INIT_SPHERE = 0, MMC_INIT_ANGLES = 1, MMC_INIT_ORDERED = 2, MMC_INIT_MIXED = 3 } mmc_init;
+
+/* Metropolis proposal. SPHERE (default): the new spin uniform on the sphere, independent of
+ * the old one. ANGLES: both spherical angles uniform (theta = pi u0, phi = 2 pi u1), the
+ * random-start parametrisation of Sec. 2.2 used for the moves; without a Hastings correction
+ * its stationary law carries an extra factor 1/sin(theta) per spin (an easy-axis bias along
+ * z). ANGLES runs on the plain FP64 engine only (placement MMC_PLACE_PLAIN, MMC_FP64). */
+typedef enum { MMC_PROPOSAL_SPHERE = 0, MMC_PROPOSAL_ANGLES = 1 } mmc_proposal;
 
 /* Where a path's spins live during a sweep. LDS: the whole lattice of one path in the
  * workgroup's LDS. HBM: spins in device memory, one workgroup per path, sweeps inside
@@ -79,6 +87,7 @@ typedef struct {
     uint32_t instance_id; /* enters Philox counter word 3 (bits 8..31); < 2^24 */
     int trace_sweeps;   /* record (e_k, M_k) for sweeps k < trace_sweeps */
     int async;          /* nonzero: mmc_run/mmc_batch_run return without waiting */
+    int proposal;       /* mmc_proposal, default MMC_PROPOSAL_SPHERE */
 } mmc_config;
 
 /* Per-path output. Means over the n_meas measured sweeps (NaN when n_meas = 0), per site:
@@ -202,6 +211,15 @@ int mmc_cumulant_crossing(double T1, double T2, const double *u, const double *s
  * through the normal Q-Q plot at Filliben's order-statistic medians, r = 1 - |R|^2/((n-1) s^2).
  * Host only; x is not modified. MMC_EINVAL for null pointers or n < 3. */
 int mmc_distribution_coefficient(const double *x, int n, double *r);
+
+/* Per-sweep cross-path statistics of a trace laid out as mmc_trace fills it
+ * (trace[path][k][4] = (e_k, Mx_k, My_k, Mz_k), k < n_sweeps), over the paths
+ * p = path_begin, path_begin + path_stride, ... < n_paths (stride 2 separates the two halves
+ * of a MIXED start). out[k][5] = (<m>, its standard error, the coefficient of variation of
+ * that mean per eq. (eq:cv), <e>, its standard error), m = |M| per site: the order parameter
+ * and its cv against the number of sweeps, Sec. 4. Host only. MMC_EINVAL for null pointers,
+ * fewer than 2 selected paths, n_sweeps < 1 or path_stride < 1. */
+int mmc_trace_stats(const double *trace, int n_paths, int n_sweeps, int path_begin, int path_stride, double *out);
 
 /* Writes a checkpoint (configuration, plan, sweeps done, spins, accumulators, trace). */
 int mmc_save(const mmc_ctx *ctx, const char *file);

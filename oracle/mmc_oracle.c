@@ -21,7 +21,10 @@
  * Readings where the paper is silent (each one is listed with its reason in the design
  * notes of the repository):
  *   - proposal: a new spin drawn uniformly on the sphere, independent of the old one
- *     (cos(theta) uniform on (-1,1), phi uniform on [0, 2 pi));
+ *     (cos(theta) uniform on (-1,1), phi uniform on [0, 2 pi)); optionally both angles
+ *     uniform (theta uniform on (0, pi)), the parametrisation of Sec. 2.2's random start
+ *     applied to the moves (without a Hastings correction its stationary law is the
+ *     Boltzmann weight times the product of 1/sin(theta_i), an easy-axis bias);
  *   - acceptance: accept iff u < exp(-beta dE), beta = 1/T, k_B = 1, u in (0,1);
  *   - random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
  *     as easy as 1, 2, 3", SC'11), counter (site, sweep, path, tag | instance << 8),
@@ -100,7 +103,8 @@ double mmco_uniform(uint32_t w)
 enum { MMCO_TAG_INIT = 0, MMCO_TAG_MET = 1, MMCO_TAG_SITE = 2 };
 enum { MMCO_SWEEP_CHECKERBOARD = 0, MMCO_SWEEP_RANDOM_SITE = 1, MMCO_SWEEP_TYPEWRITER = 2,
        MMCO_SWEEP_CHECKERBOARD_REVERSED = 3 };
-enum { MMCO_INIT_SPHERE = 0, MMCO_INIT_ANGLES = 1, MMCO_INIT_ORDERED = 2 };
+enum { MMCO_INIT_SPHERE = 0, MMCO_INIT_ANGLES = 1, MMCO_INIT_ORDERED = 2, MMCO_INIT_MIXED = 3 };
+enum { MMCO_PROPOSAL_SPHERE = 0, MMCO_PROPOSAL_ANGLES = 1 };
 
 typedef struct {
     int dim;           /* 1, 2 or 3 */
@@ -115,6 +119,7 @@ typedef struct {
     int sweep;         /* MMCO_SWEEP_* */
     int init;          /* MMCO_INIT_* */
     int trace_sweeps;  /* record (e_k, M_k) for sweeps k < trace_sweeps */
+    int proposal;      /* MMCO_PROPOSAL_* */
 } mmco_params;
 
 typedef struct {
@@ -285,7 +290,7 @@ static int metropolis_site(const mmco_params *p, double beta, double *spins, int
                            const uint32_t w[4])
 {
     double snew[3];
-    mmco_unit_vector(w[0], w[1], MMCO_INIT_SPHERE, snew);
+    mmco_unit_vector(w[0], w[1], p->proposal == MMCO_PROPOSAL_ANGLES ? MMCO_INIT_ANGLES : MMCO_INIT_SPHERE, snew);
     double dE = mmco_delta_e(p, spins, i, snew);
     double u = mmco_uniform(w[2]);
     if (mmco_accept(u, dE, beta)) {
@@ -297,14 +302,18 @@ static int metropolis_site(const mmco_params *p, double beta, double *spins, int
     return 0;
 }
 
-/* Random initial state of Sec. 2.2 (per site, Philox((i, 0, path, TAG_INIT))). */
+/* Initial state of Sec. 2.2 (per site, Philox((i, 0, path, TAG_INIT))). MIXED: the set-up of
+ * Sec. 4 with half of the paths from a random start and half from the ordered one -- paths
+ * with an even index start uniformly on the sphere, odd ones ordered. */
 void mmco_init_state(const mmco_params *p, uint32_t path, mmco_state *st)
 {
     int64_t N = n_sites(p);
+    int mode = p->init;
+    if (mode == MMCO_INIT_MIXED) mode = (path & 1u) ? MMCO_INIT_ORDERED : MMCO_INIT_SPHERE;
     for (int64_t i = 0; i < N; ++i) {
         uint32_t w[4];
         words(p, (uint32_t)i, 0u, path, MMCO_TAG_INIT, w);
-        mmco_unit_vector(w[0], w[1], p->init, st->spins + 3 * i);
+        mmco_unit_vector(w[0], w[1], mode, st->spins + 3 * i);
     }
     st->sweeps_done = 0;
     st->sum_e = st->sum_e2 = st->sum_m = st->sum_m2 = st->sum_m4 = 0.0;

@@ -12,14 +12,15 @@ import numpy as np
 from . import build as _build
 
 SWEEPS = {"checkerboard": 0, "random_site": 1, "typewriter": 2, "checkerboard_reversed": 3}
-INITS = {"sphere": 0, "angles": 1, "ordered": 2}
+INITS = {"sphere": 0, "angles": 1, "ordered": 2, "mixed": 3}
+PROPOSALS = {"sphere": 0, "angles": 1}
 
 
 class Params(C.Structure):
     _fields_ = [("dim", C.c_int), ("L", C.c_int), ("periodic", C.c_int), ("T", C.c_double),
                 ("J", C.c_double), ("n_therm", C.c_int), ("n_meas", C.c_int),
                 ("seed", C.c_uint64), ("instance", C.c_uint32), ("sweep", C.c_int),
-                ("init", C.c_int), ("trace_sweeps", C.c_int)]
+                ("init", C.c_int), ("trace_sweeps", C.c_int), ("proposal", C.c_int)]
 
 
 class PathResult(C.Structure):
@@ -83,9 +84,9 @@ def _dp(a):
 
 
 def make_params(L, T, J=1.0, n_therm=0, n_meas=0, seed=1234, instance=0, dim=3, periodic=True,
-                sweep="checkerboard", init="sphere", trace_sweeps=0):
+                sweep="checkerboard", init="sphere", trace_sweeps=0, proposal="sphere"):
     return Params(dim, L, 1 if periodic else 0, float(T), float(J), n_therm, n_meas, seed,
-                  instance, SWEEPS[sweep], INITS[init], trace_sweeps)
+                  instance, SWEEPS[sweep], INITS[init], trace_sweeps, PROPOSALS[proposal])
 
 
 def philox(ctr, key):
@@ -101,12 +102,12 @@ def philox(ctr, key):
 
 def run_paths(L, T, J=1.0, n_therm=0, n_meas=0, seed=1234, path_begin=0, path_end=1, instance=0,
               dim=3, periodic=True, sweep="checkerboard", init="sphere", trace_sweeps=0,
-              want_spins=False, n_threads=0):
+              want_spins=False, n_threads=0, proposal="sphere"):
     """Runs paths [path_begin, path_end). Returns a dict of numpy arrays:
     e_mean, e2_mean, absm_mean, m2_mean, m4_mean [n]; final_m [n,3]; final_e [n];
     n_accept [n]; trace [n, trace_sweeps, 4] (e_k, Mx_k, My_k, Mz_k); spins [n, N, 3]."""
     p = make_params(L, T, J, n_therm, n_meas, seed, instance, dim, periodic, sweep, init,
-                    trace_sweeps)
+                    trace_sweeps, proposal)
     n = path_end - path_begin
     N = L ** dim
     res = (PathResult * n)()

@@ -148,6 +148,23 @@ def cumulant_crossing(T1, T2, u, se):
     return Tc, sTc, R1, s1, R2, s2
 
 
+def trace_statistics(trace, path_begin=0, path_stride=1):
+    """Sec. 4 (Figs. TC_on_T, L10T1_T150_M_cv, ee): the order parameter <m> = <|M|> per site over
+    paths and the coefficient of variation of that mean, eq. (eq:cv), after each sweep k; plus
+    <e>. The state after sweep k of a path run longer is the final state of the same path run
+    for k + 1 sweeps (same counters), so one traced run gives every sweep count at once.
+    trace[p, k] = (e_k, Mx_k, My_k, Mz_k); paths path_begin, path_begin + stride, ...
+    Returns rows (<m>, SE, cv, <e>, SE) per sweep."""
+    t = np.asarray(trace, dtype=np.float64)[path_begin::path_stride]
+    out = np.empty((t.shape[1], 5))
+    for k in range(t.shape[1]):
+        m = np.sqrt((t[:, k, 1:4] ** 2).sum(axis=1))
+        out[k, 0], out[k, 1] = mean_se(m)
+        out[k, 2] = coeff_variation(m)
+        out[k, 3], out[k, 4] = mean_se(t[:, k, 0])
+    return out
+
+
 def path_statistics(res, L, T, dim=3):
     """Cross-path statistics of per-path results (dict of arrays as returned by
     oracle.run_paths)."""

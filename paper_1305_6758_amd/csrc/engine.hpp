@@ -19,7 +19,8 @@ struct PathAcc {
 static_assert(sizeof(PathAcc) == 128, "PathAcc layout");
 
 enum { TAG_INIT = 0, TAG_MET = 1 };
-enum { INIT_SPHERE = 0, INIT_ANGLES = 1, INIT_ORDERED = 2 };
+enum { INIT_SPHERE = 0, INIT_ANGLES = 1, INIT_ORDERED = 2, INIT_MIXED = 3 };
+enum { PROPOSAL_SPHERE = 0, PROPOSAL_ANGLES = 1 };
 
 // One instance as the kernels see it.
 struct InstDev {
@@ -28,6 +29,7 @@ struct InstDev {
     int n_therm, n_meas; // sweeps: measured when k >= n_therm
     int trace_sweeps;    // trace rows for k < trace_sweeps
     int init;            // INIT_*
+    int proposal;        // PROPOSAL_* (ANGLES: plain FP64 engine only)
     int renorm_every;    // FP32 only; <= 0: never
     uint32_t ctr3;       // Philox counter word 3 without the tag: instance_id << 8
     uint32_t key0, key1; // Philox key = seed

@@ -241,7 +241,7 @@ struct Coef {
 // One Metropolis attempt at site s of colour c (own = this colour's spins, oth = the other
 // colour's), sweep k. Adds the resulting spin (and for the odd colour S . h) to the
 // measurement partials and the accepted count of the wave to nacc.
-template <typename T>
+template <typename T, bool ANG = false>
 __device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const T *oth, int HALF, bool odd,
                                             const Site &s, uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy,
                                             T &pmz, unsigned long long &nacc)
@@ -274,7 +274,8 @@ __device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const 
         hz = ((az[0] + az[1]) + (az[2] + az[3])) + (az[4] + az[5]);
     }
     T nx, ny, nz;
-    Arith<T>::sphere(w.w0, w.w1, nx, ny, nz);
+    if constexpr (ANG) Arith<T>::angles(w.w0, w.w1, nx, ny, nz);  // both angles uniform
+    else Arith<T>::sphere(w.w0, w.w1, nx, ny, nz);
     const T dx = nx - sx, dy = ny - sy, dz = nz - sz;
     bool acc;
     if constexpr (std::is_same<T, double>::value) {
@@ -512,6 +513,8 @@ __device__ __attribute__((noinline)) void init_path(T *sp, int L, int lane, uint
                                                     uint32_t key1, uint32_t ctr3, int init)
 {
     const int HALF = L * L * L / 2;
+    // mixed start: even paths from the random (sphere) start, odd paths ordered
+    if (init == INIT_MIXED) init = (path & 1u) ? INIT_ORDERED : INIT_SPHERE;
     for (int t = lane; t < 2 * HALF; t += G) {
         const int c = t >= HALF, h = t - c * HALF;
         const Site s = flat_site(L, h, c);
@@ -815,14 +818,15 @@ __global__ __launch_bounds__(256) void k_plain_init(InstDev in)
     if (blockIdx.x == 0 && threadIdx.x < 16) reinterpret_cast<double *>(in.acc + path)[threadIdx.x] = 0.0;
     if (h >= HALF) return;
     double *sp = reinterpret_cast<double *>(in.spins) + (size_t)path * 6 * HALF;
+    const int init = in.init == INIT_MIXED ? ((path & 1) ? INIT_ORDERED : INIT_SPHERE) : in.init;
     for (int c = 0; c < 2; ++c) {
         const Site s = flat_site(L, h, c);
         double x, y, z;
-        if (in.init == INIT_ORDERED) {
+        if (init == INIT_ORDERED) {
             x = 0.0; y = 0.0; z = 1.0;
         } else {
             const Words w = philox4x32_10((uint32_t)s.id, 0u, (uint32_t)path, TAG_INIT | in.ctr3, in.key0, in.key1);
-            if (in.init == INIT_ANGLES) Arith<double>::angles(w.w0, w.w1, x, y, z);
+            if (init == INIT_ANGLES) Arith<double>::angles(w.w0, w.w1, x, y, z);
             else Arith<double>::sphere(w.w0, w.w1, x, y, z);
         }
         double *own = sp + c * 3 * HALF;
@@ -853,8 +857,14 @@ __global__ __launch_bounds__(256) void k_plain_half(InstDev in, const int *k_dev
         cf.J = in.J;
         cf.q = 0.0f;
         double pe = 0.0, px = 0.0, py = 0.0, pz = 0.0;
-        update_site<double>(g, g.sp + (c ? 3 * HALF : 0), g.sp + (c ? 0 : 3 * HALF), HALF, c != 0, flat_site(L, h, c),
-                            (uint32_t)*k_dev, cf, pe, px, py, pz, nacc);
+        double *own = g.sp + (c ? 3 * HALF : 0);
+        const double *oth = g.sp + (c ? 0 : 3 * HALF);
+        const Site s = flat_site(L, h, c);
+        const uint32_t k = (uint32_t)*k_dev;
+        if (in.proposal == PROPOSAL_ANGLES)
+            update_site<double, true>(g, own, oth, HALF, c != 0, s, k, cf, pe, px, py, pz, nacc);
+        else
+            update_site<double, false>(g, own, oth, HALF, c != 0, s, k, cf, pe, px, py, pz, nacc);
     }
     if ((threadIdx.x & 63) == 0 && nacc) atomicAdd(&in.acc[path].n_accept, nacc);
 }

@@ -133,6 +133,7 @@ mmc::InstDev inst_dev(const mmc_ctx *c, const Instance &in, uint32_t instance_id
     d.n_meas = in.n_meas;
     d.trace_sweeps = c->batch ? 0 : c->cfg.trace_sweeps;
     d.init = c->cfg.init;
+    d.proposal = c->cfg.proposal;
     d.renorm_every = c->cfg.renorm_every == 0 ? 64 : (c->cfg.renorm_every < 0 ? 0 : c->cfg.renorm_every);
     d.ctr3 = instance_id << 8;
     d.key0 = (uint32_t)c->seed;
@@ -501,7 +502,8 @@ mmc_ctx *mmc_create_ex(int L, double T, double J, int n_paths, int n_therm, int 
         fail(MMC_EINVAL, "precision must be MMC_FP32 or MMC_FP64");
         return nullptr;
     }
-    if (c0.init < MMC_INIT_SPHERE || c0.init > MMC_INIT_ORDERED || c0.placement < 0 || c0.placement > MMC_PLACE_PLAIN ||
+    if (c0.init < MMC_INIT_SPHERE || c0.init > MMC_INIT_MIXED || c0.placement < 0 || c0.placement > MMC_PLACE_PLAIN ||
+        c0.proposal < MMC_PROPOSAL_SPHERE || c0.proposal > MMC_PROPOSAL_ANGLES ||
         c0.block < 0 || c0.lanes_per_path < 0 || c0.trace_sweeps < 0 || c0.instance_id >= (1u << 24)) {
         fail(MMC_EINVAL, "configuration out of range");
         return nullptr;
@@ -522,6 +524,11 @@ mmc_ctx *mmc_create_ex(int L, double T, double J, int n_paths, int n_therm, int 
     c->ws_bytes = layout_single(c);
     if (c0.placement == MMC_PLACE_PLAIN && !c->fp64) {
         fail(MMC_EUNSUPPORTED, "the plain engine is FP64 only");
+        delete c;
+        return nullptr;
+    }
+    if (c0.proposal == MMC_PROPOSAL_ANGLES && c0.placement != MMC_PLACE_PLAIN) {
+        fail(MMC_EUNSUPPORTED, "the both-angles proposal runs on the plain FP64 engine only");
         delete c;
         return nullptr;
     }
@@ -774,7 +781,7 @@ int mmc_stats(const mmc_ctx *c, mmc_stats_t *out)
 }
 
 // ---------------------------------------------------------------- checkpoints
-static const char k_magic[8] = {'M', 'M', 'C', 'C', 'K', 'P', 'T', '1'};
+static const char k_magic[8] = {'M', 'M', 'C', 'C', 'K', 'P', 'T', '2'};
 
 int mmc_save(const mmc_ctx *c, const char *file)
 {
@@ -934,8 +941,13 @@ mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, c
         fail(MMC_EUNSUPPORTED, "the plain engine has no batch form");
         return nullptr;
     }
-    if (c0.init < MMC_INIT_SPHERE || c0.init > MMC_INIT_ORDERED) {
+    if (c0.init < MMC_INIT_SPHERE || c0.init > MMC_INIT_MIXED || c0.proposal < MMC_PROPOSAL_SPHERE ||
+        c0.proposal > MMC_PROPOSAL_ANGLES) {
         fail(MMC_EINVAL, "configuration out of range");
+        return nullptr;
+    }
+    if (c0.proposal != MMC_PROPOSAL_SPHERE) {
+        fail(MMC_EUNSUPPORTED, "the both-angles proposal runs on the plain FP64 engine only");
         return nullptr;
     }
     c0.trace_sweeps = 0;

@@ -234,3 +234,37 @@ extern "C" int mmc_distribution_coefficient(const double *x, int n, double *r)
     *r = mmc::distribution_coefficient(std::vector<double>(x, x + n));
     return MMC_OK;
 }
+
+extern "C" int mmc_trace_stats(const double *trace, int n_paths, int n_sweeps, int path_begin, int path_stride,
+                               double *out)
+{
+    if (!trace || !out || n_sweeps < 1 || path_stride < 1 || path_begin < 0) return MMC_EINVAL;
+    const int n = path_begin >= n_paths ? 0 : (n_paths - path_begin + path_stride - 1) / path_stride;
+    if (n < 2) return MMC_EINVAL;
+    const double nd = (double)n;
+    for (int k = 0; k < n_sweeps; ++k) {
+        double sm = 0, se = 0;
+        for (int p = path_begin; p < n_paths; p += path_stride) {
+            const double *r = trace + ((size_t)p * n_sweeps + k) * 4;
+            sm += sqrt(r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+            se += r[0];
+        }
+        const double mm = sm / nd, me = se / nd;
+        double vm = 0, ve = 0;
+        for (int p = path_begin; p < n_paths; p += path_stride) {
+            const double *r = trace + ((size_t)p * n_sweeps + k) * 4;
+            const double dm = sqrt(r[1] * r[1] + r[2] * r[2] + r[3] * r[3]) - mm, de = r[0] - me;
+            vm += dm * dm;
+            ve += de * de;
+        }
+        vm /= nd - 1;
+        ve /= nd - 1;
+        double *o = out + (size_t)k * 5;
+        o[0] = mm;
+        o[1] = sqrt(vm / nd);
+        o[2] = sqrt(vm) / (sqrt(nd) * mm);
+        o[3] = me;
+        o[4] = sqrt(ve / nd);
+    }
+    return MMC_OK;
+}

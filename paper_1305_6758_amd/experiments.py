@@ -6,9 +6,14 @@ happens here.
 
   - binder_crossing: the O(3) critical temperature from the ratio of fourth-order cumulants
     U_30/U_20 at two temperatures, 10^6 single-output paths per (L, T) and 200 sweeps
-    (Sec. 5, eq. (kum)).
+    (Sec. 5, eq. (kum));
+  - thermalisation: the order parameter <|M|> and the coefficient of variation of its mean
+    against the number of sweeps from one traced run, for any start (random, both-angles,
+    ordered, or the mixed half-and-half set-up with each half reported separately) (Sec. 4);
+  - distribution_table: the distribution coefficient r of the single-output paths' H, M^x,
+    M^y, M^z and |M^z| per temperature (Sec. 3, Table 1), for either proposal.
 
-Usage: python -m paper_1305_6758_amd.experiments binder [--paths N] [--fp64]
+Usage: python -m paper_1305_6758_amd.experiments {binder,thermalisation,table} [options]
 """
 import argparse
 import json
@@ -57,14 +62,106 @@ def binder_crossing(Ls=(30, 20), Ts=(1.44, 1.45), n_paths=10 ** 6, sweeps=200, s
     return out
 
 
+INITS = {"sphere": mmc.MMC_INIT_SPHERE, "angles": mmc.MMC_INIT_ANGLES, "ordered": mmc.MMC_INIT_ORDERED,
+         "mixed": mmc.MMC_INIT_MIXED}
+
+
+def doubling_sweeps(n):
+    """Sweep counts 1, 2, 4, ... up to n, and n itself (the paper doubles the number of sweeps
+    from one simulation to the next)."""
+    out, k = [], 1
+    while k < n:
+        out.append(k)
+        k *= 2
+    return out + [n]
+
+
+def thermalisation(L=10, T=1.0, n_paths=1000, sweeps=5000, init="sphere", fp64=False, seed=SEED, instance_id=0,
+                   report=None):
+    """One run of n_paths paths through `sweeps` sweeps with every sweep traced. Row k of the
+    trace is the output a path would give if it stopped after k + 1 sweeps, so the paper's
+    series of simulations with growing sweep counts come from one run. Returns, at the sweep
+    counts `report` (default: doubling), <m> with its standard error and the coefficient of
+    variation of the mean, and <e>, over all paths and -- for the mixed start -- over the
+    random-start (even) and ordered-start (odd) halves separately."""
+    cfg = mmc.config(precision=mmc.MMC_FP64 if fp64 else mmc.MMC_FP32, init=INITS[init], trace_sweeps=sweeps,
+                     instance_id=instance_id)
+    ctx = mmc.mmc_create_ex(L, T, 1.0, n_paths, sweeps, 0, seed, cfg)
+    try:
+        mmc.mmc_run(ctx)
+        kernel_ms = mmc.mmc_last_timing_ms(ctx)
+        plan = mmc.mmc_plan(ctx)
+        trace = mmc.mmc_trace(ctx, n_paths, sweeps)
+    finally:
+        mmc.mmc_destroy(ctx)
+    report = report or doubling_sweeps(sweeps)
+    sets = {"all": (0, 1)}
+    if init == "mixed":
+        sets.update({"random_half": (0, 2), "ordered_half": (1, 2)})
+    out = {"L": L, "T": T, "n_paths": n_paths, "sweeps": sweeps, "init": init,
+           "precision": "fp64" if fp64 else "fp32", "plan": plan, "kernel_ms": kernel_ms,
+           "updates_per_s": n_paths * L ** 3 * sweeps / (kernel_ms * 1e-3), "report_sweeps": report}
+    for name, (b, st) in sets.items():
+        rows = mmc.mmc_trace_stats(trace, b, st)
+        out[name] = [{"sweeps": k, "m": rows[k - 1, 0], "se_m": rows[k - 1, 1], "cv_m": rows[k - 1, 2],
+                      "e": rows[k - 1, 3], "se_e": rows[k - 1, 4]} for k in report]
+    return out
+
+
+def distribution_table(L=10, Ts=(0.6, 0.8, 1.0, 1.2, 1.4, 1.6), n_paths=10 ** 4, sweeps=5000, proposal="sphere",
+                       init="sphere", seed=SEED, fp64=False):
+    """Table 1 of Sec. 3: for each T, n_paths single-output paths (random start, `sweeps`
+    sweeps, the final state measured) and the distribution coefficient r, eq.
+    (dist-coefficient), of H/N, M^x, M^y, M^z and |M^z| over the paths. The paper leaves out
+    r(M^z) in the ordered phase (two accumulation points) and r(|M^z|) in the disordered one;
+    both are reported here. proposal 'angles' (both angles uniform) runs on the plain FP64
+    engine; 'sphere' on the FP32 engine (FP64 with fp64=True). Instance id = index of T."""
+    rows = []
+    for i, T in enumerate(Ts):
+        if proposal == "angles":
+            cfg = mmc.config(precision=mmc.MMC_FP64, placement=mmc.MMC_PLACE_PLAIN, proposal=mmc.MMC_PROPOSAL_ANGLES,
+                             init=INITS[init], instance_id=i)
+        else:
+            cfg = mmc.config(precision=mmc.MMC_FP64 if fp64 else mmc.MMC_FP32, init=INITS[init], instance_id=i)
+        ctx = mmc.mmc_create_ex(L, T, 1.0, n_paths, sweeps - 1, 1, seed, cfg)
+        try:
+            mmc.mmc_run(ctx)
+            ms = mmc.mmc_last_timing_ms(ctx)
+            plan = mmc.mmc_plan(ctx)
+            r = mmc.mmc_results(ctx, n_paths)
+        finally:
+            mmc.mmc_destroy(ctx)
+        fm = r["final_m"]
+        rows.append({"T": T, "plan": plan, "kernel_ms": ms,
+                     "updates_per_s": n_paths * L ** 3 * sweeps / (ms * 1e-3),
+                     "r_H": mmc.mmc_distribution_coefficient(r["final_e"]),
+                     "r_Mx": mmc.mmc_distribution_coefficient(fm[:, 0]),
+                     "r_My": mmc.mmc_distribution_coefficient(fm[:, 1]),
+                     "r_Mz": mmc.mmc_distribution_coefficient(fm[:, 2]),
+                     "r_absMz": mmc.mmc_distribution_coefficient(abs(fm[:, 2])),
+                     "mean_absMz": float(abs(fm[:, 2]).mean()),
+                     "mean_m": float(((fm ** 2).sum(axis=1) ** 0.5).mean())})
+    return {"L": L, "n_paths": n_paths, "sweeps": sweeps, "proposal": proposal, "init": init, "rows": rows}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("experiment", choices=["binder"])
-    ap.add_argument("--paths", type=int, default=10 ** 6)
-    ap.add_argument("--sweeps", type=int, default=200)
+    ap.add_argument("experiment", choices=["binder", "thermalisation", "table"])
+    ap.add_argument("--paths", type=int, default=None)
+    ap.add_argument("--sweeps", type=int, default=None)
+    ap.add_argument("--L", type=int, default=10)
+    ap.add_argument("--T", type=float, default=1.0)
+    ap.add_argument("--init", default="sphere", choices=sorted(INITS))
+    ap.add_argument("--proposal", default="sphere", choices=["sphere", "angles"])
     ap.add_argument("--fp64", action="store_true")
     a = ap.parse_args(argv)
-    out = binder_crossing(n_paths=a.paths, sweeps=a.sweeps, fp64=a.fp64)
+    if a.experiment == "binder":
+        out = binder_crossing(n_paths=a.paths or 10 ** 6, sweeps=a.sweeps or 200, fp64=a.fp64)
+    elif a.experiment == "thermalisation":
+        out = thermalisation(L=a.L, T=a.T, n_paths=a.paths or 1000, sweeps=a.sweeps or 5000, init=a.init, fp64=a.fp64)
+    else:
+        out = distribution_table(L=a.L, n_paths=a.paths or 10 ** 4, sweeps=a.sweeps or 5000, proposal=a.proposal,
+                                 init=a.init)
     print(json.dumps(out), flush=True)
     return 0
 

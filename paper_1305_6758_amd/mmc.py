@@ -15,14 +15,15 @@ LIB_PATH = os.path.join(HERE, "libmmc.so")
 
 MMC_OK, MMC_EINVAL, MMC_ENOMEM, MMC_EHIP, MMC_ESTATE, MMC_EUNSUPPORTED, MMC_EIO = 0, -1, -2, -3, -4, -5, -6
 MMC_FP32, MMC_FP64 = 0, 1
-MMC_INIT_SPHERE, MMC_INIT_ANGLES, MMC_INIT_ORDERED = 0, 1, 2
+MMC_INIT_SPHERE, MMC_INIT_ANGLES, MMC_INIT_ORDERED, MMC_INIT_MIXED = 0, 1, 2, 3
+MMC_PROPOSAL_SPHERE, MMC_PROPOSAL_ANGLES = 0, 1
 MMC_PLACE_AUTO, MMC_PLACE_LDS, MMC_PLACE_HBM, MMC_PLACE_PLAIN = 0, 1, 2, 3
 
 
 class mmc_config(C.Structure):
     _fields_ = [("precision", C.c_int), ("init", C.c_int), ("placement", C.c_int), ("block", C.c_int),
                 ("lanes_per_path", C.c_int), ("renorm_every", C.c_int), ("instance_id", C.c_uint32),
-                ("trace_sweeps", C.c_int), ("async_", C.c_int)]
+                ("trace_sweeps", C.c_int), ("async_", C.c_int), ("proposal", C.c_int)]
 
 
 class mmc_path_result(C.Structure):
@@ -82,6 +83,7 @@ _SIGNATURES = [
     ("mmc_cumulant_crossing", C.c_int, [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(mmc_crossing_t)]),
     ("mmc_distribution_coefficient", C.c_int, [C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]),
+    ("mmc_trace_stats", C.c_int, [C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]),
     ("mmc_save", C.c_int, [_P, C.c_char_p]),
     ("mmc_load", _P, [C.c_char_p]),
     ("mmc_last_timing_ms", C.c_double, [_P]),
@@ -129,9 +131,9 @@ def _ptr(h):
 
 
 def config(precision=MMC_FP32, init=MMC_INIT_SPHERE, placement=MMC_PLACE_AUTO, block=0, lanes_per_path=0,
-           renorm_every=0, instance_id=0, trace_sweeps=0, async_=0):
+           renorm_every=0, instance_id=0, trace_sweeps=0, async_=0, proposal=MMC_PROPOSAL_SPHERE):
     return mmc_config(precision, init, placement, block, lanes_per_path, renorm_every, instance_id,
-                      trace_sweeps, async_)
+                      trace_sweeps, async_, proposal)
 
 
 # ---------------------------------------------------------------- same names as the C ABI
@@ -259,6 +261,18 @@ def mmc_cumulant_crossing(T1, T2, u, se):
     out = mmc_crossing_t()
     _check(lib().mmc_cumulant_crossing(float(T1), float(T2), cu, cs, C.byref(out)))
     return {name: getattr(out, name) for name, _ in mmc_crossing_t._fields_}
+
+
+def mmc_trace_stats(trace, path_begin=0, path_stride=1):
+    """trace: [n_paths, n_sweeps, 4] as returned by mmc_trace -> [n_sweeps, 5] array of
+    (<m>, se, cv of the mean, <e>, se) over the selected paths."""
+    t = np.ascontiguousarray(trace, dtype=np.float64)
+    n_paths, n_sweeps = t.shape[0], t.shape[1]
+    out = np.empty((n_sweeps, 5))
+    dp = C.POINTER(C.c_double)
+    _check(lib().mmc_trace_stats(t.ctypes.data_as(dp), n_paths, n_sweeps, path_begin, path_stride,
+                                 out.ctypes.data_as(dp)))
+    return out
 
 
 def mmc_distribution_coefficient(x):

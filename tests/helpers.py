@@ -7,13 +7,13 @@ RESULT_KEYS = ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e"
 
 
 def engine_run(L, T, n_paths, n_therm, n_meas, *, J=1.0, seed=1234, fp64=True, placement=0, block=0,
-               lanes=0, init=0, trace=0, instance_id=0, renorm_every=0, spins_of=(), torch_ws=False):
+               lanes=0, init=0, trace=0, instance_id=0, renorm_every=0, spins_of=(), torch_ws=False, proposal=0):
     """Runs one instance on the GPU engine; returns (results dict, trace or None, {path: spins},
     plan string, ms)."""
     from paper_1305_6758_amd import mmc
     cfg = mmc.config(precision=mmc.MMC_FP64 if fp64 else mmc.MMC_FP32, init=init, placement=placement,
                      block=block, lanes_per_path=lanes, renorm_every=renorm_every, instance_id=instance_id,
-                     trace_sweeps=trace)
+                     trace_sweeps=trace, proposal=proposal)
     ctx = mmc.mmc_create_ex(L, T, J, n_paths, n_therm, n_meas, seed, cfg)
     ws = None
     try:
@@ -33,11 +33,11 @@ def engine_run(L, T, n_paths, n_therm, n_meas, *, J=1.0, seed=1234, fp64=True, p
 
 
 def oracle_run(L, T, n_paths, n_therm, n_meas, *, J=1.0, seed=1234, init="sphere", trace=0, instance_id=0,
-               path_begin=0, want_spins=False, threads=0):
+               path_begin=0, want_spins=False, threads=0, proposal="sphere"):
     from oracle import oracle as O
     return O.run_paths(L, T, J=J, n_therm=n_therm, n_meas=n_meas, seed=seed, path_begin=path_begin,
                        path_end=path_begin + n_paths, instance=instance_id, init=init,
-                       trace_sweeps=trace, want_spins=want_spins, n_threads=threads)
+                       trace_sweeps=trace, want_spins=want_spins, n_threads=threads, proposal=proposal)
 
 
 def max_abs_diff(a, b):

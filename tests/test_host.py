@@ -138,3 +138,31 @@ def test_host_binder_crossing_and_r_match_oracle_statistics():
         mmc.mmc_cumulant_crossing(1.0, 1.0, us, ses)
     with pytest.raises(mmc.MMCError):
         mmc.mmc_distribution_coefficient([1.0, 2.0])
+
+
+def test_host_trace_stats_match_oracle_and_config_checks():
+    """mmc_trace_stats (C++ host) against the oracle's per-sweep statistics of an oracle trace
+    with the mixed start, for all paths and for each half; configuration checks of the mixed
+    start and the both-angles proposal (no GPU needed)."""
+    from paper_1305_6758_amd import mmc
+    r = O.run_paths(4, 1.0, n_therm=30, n_meas=0, path_end=21, init="mixed", trace_sweeps=30)
+    for b, st in ((0, 1), (0, 2), (1, 2)):
+        got = mmc.mmc_trace_stats(r["trace"], b, st)
+        ref = S.trace_statistics(r["trace"], b, st)
+        assert np.max(np.abs(got - ref)) < 1e-13
+    with pytest.raises(mmc.MMCError):
+        mmc.mmc_trace_stats(r["trace"][:1])
+    ctx = mmc.mmc_create_ex(8, 1.0, 1.0, 4, 1, 1, 1, mmc.config(init=mmc.MMC_INIT_MIXED))
+    mmc.mmc_destroy(ctx)
+    ctx = mmc.mmc_create_ex(8, 1.0, 1.0, 4, 1, 1, 1, mmc.config(precision=mmc.MMC_FP64, placement=mmc.MMC_PLACE_PLAIN,
+                                                               proposal=mmc.MMC_PROPOSAL_ANGLES))
+    mmc.mmc_destroy(ctx)
+    for cfg in (mmc.config(proposal=mmc.MMC_PROPOSAL_ANGLES),
+                mmc.config(precision=mmc.MMC_FP64, placement=mmc.MMC_PLACE_HBM, proposal=mmc.MMC_PROPOSAL_ANGLES)):
+        with pytest.raises(mmc.MMCError) as e:
+            mmc.mmc_create_ex(8, 1.0, 1.0, 4, 1, 1, 1, cfg)
+        assert e.value.code == mmc.MMC_EUNSUPPORTED
+    for cfg in (mmc.config(init=4), mmc.config(proposal=2)):
+        with pytest.raises(mmc.MMCError) as e:
+            mmc.mmc_create_ex(8, 1.0, 1.0, 4, 1, 1, 1, cfg)
+        assert e.value.code == mmc.MMC_EINVAL

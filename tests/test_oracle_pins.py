@@ -428,3 +428,78 @@ def test_cumulant_crossing_exact_and_error():
     tcs = np.array([S.cumulant_crossing(T1, T2, d, se)[0] for d in draws])
     assert abs(tcs.std(ddof=1) / sTc - 1.0) < 0.04
     assert abs(tcs.mean() - Tc0) < 4.0 * sTc / math.sqrt(draws.shape[0]) + 1e-6
+
+
+def _angle_proposal_two_spin_moments(K, n=96):
+    """<S1.S2> and <cos^2 theta_1> for two coupled spins under the both-angles-uniform proposal.
+    Its stationary law is the Boltzmann weight times prod 1/sin(theta_i) on the sphere, i.e.
+    exp(K c) times the flat measure d theta1 d phi1 d theta2 d phi2; integrated over (theta1,
+    theta2, phi1 - phi2) by Gauss-Legendre in the polar angles and the trapezoid rule in phi."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    th, wt = (x + 1) * math.pi / 2, w * math.pi / 2
+    m = 2 * n
+    ph = np.arange(m) * 2 * math.pi / m
+    T1, T2, P = np.meshgrid(th, th, ph, indexing="ij")
+    W = wt[:, None, None] * wt[None, :, None]
+    c = np.cos(T1) * np.cos(T2) + np.sin(T1) * np.sin(T2) * np.cos(P)
+    b = W * np.exp(K * c)
+    return (c * b).sum() / b.sum(), (np.cos(T1) ** 2 * b).sum() / b.sum()
+
+
+@pytest.mark.parametrize("K", [1.0, 2.0])
+def test_angle_proposal_two_spin_law(K):
+    """The both-angles-uniform proposal (Sec. 2.2's random-start parametrisation used for the
+    moves) leaves Metropolis without a Hastings correction: its stationary law is anisotropic.
+    Two spins on one bond: <S1.S2> and <(S1^z)^2> against the quadrature of that law (they
+    differ from the isotropic coth K - 1/K and 1/3 by many standard errors); the sphere
+    proposal on the same chain keeps <(S1^z)^2> = 1/3."""
+    T = 1.0 / K
+    c_ref, z2_ref = _angle_proposal_two_spin_moments(K)
+    n = 16000
+    r = O.run_paths(2, T, n_therm=60, n_meas=0, path_end=n, dim=1, periodic=False, proposal="angles",
+                    want_spins=True)
+    c = -2.0 * r["final_e"]
+    m, se = S.mean_se(c)
+    assert within_4sigma(m, se, c_ref)
+    assert abs(c_ref - langevin(K)) > 8 * se
+    z2 = r["spins"][:, 0, 2] ** 2
+    m, se = S.mean_se(z2)
+    assert within_4sigma(m, se, z2_ref)
+    r = O.run_paths(2, T, n_therm=60, n_meas=0, path_end=n, dim=1, periodic=False, want_spins=True)
+    m, se = S.mean_se(r["spins"][:, 0, 2] ** 2)
+    assert within_4sigma(m, se, 1.0 / 3.0)
+
+
+def test_mixed_start_is_sphere_and_ordered_by_path_parity():
+    """The mixed start of Sec. 4 (half of the paths random, half ordered): even paths are the
+    random-start (sphere) paths and odd paths the ordered-start paths, bit for bit."""
+    kw = dict(n_therm=3, n_meas=4, path_end=6, seed=9, instance=2)
+    mix = O.run_paths(4, 1.2, init="mixed", want_spins=True, **kw)
+    sph = O.run_paths(4, 1.2, init="sphere", want_spins=True, **kw)
+    ordr = O.run_paths(4, 1.2, init="ordered", want_spins=True, **kw)
+    for k in ("e_mean", "absm_mean", "m4_mean", "final_e", "final_m", "n_accept", "spins"):
+        assert np.array_equal(mix[k][0::2], sph[k][0::2]), k
+        assert np.array_equal(mix[k][1::2], ordr[k][1::2]), k
+    st = O.run_paths(4, 1.2, init="mixed", n_therm=0, n_meas=0, path_end=2, want_spins=True)
+    assert np.all(st["spins"][1] == np.array([0.0, 0.0, 1.0]))
+    assert np.std(st["spins"][0][:, 2]) > 0.3
+
+
+def test_trace_statistics_against_scipy():
+    """Per-sweep statistics of a trace (Sec. 4: <m> and the coefficient of variation of the
+    mean, eq. (eq:cv)) against scipy's sem and variation of |M_k| computed directly."""
+    r = O.run_paths(4, 1.2, n_therm=12, n_meas=0, path_end=30, init="mixed", trace_sweeps=12, seed=3)
+    t = r["trace"]
+    for b, st in ((0, 1), (1, 2)):
+        rows = S.trace_statistics(t, b, st)
+        for k in range(12):
+            m = np.linalg.norm(t[b::st, k, 1:4], axis=1)
+            assert abs(rows[k, 0] - m.mean()) < 1e-15
+            assert abs(rows[k, 1] - ss.sem(m)) < 1e-15
+            assert abs(rows[k, 2] - ss.variation(m, ddof=1) / math.sqrt(m.size)) < 1e-14
+            assert abs(rows[k, 3] - t[b::st, k, 0].mean()) < 1e-15
+            assert abs(rows[k, 4] - ss.sem(t[b::st, k, 0])) < 1e-15
+    # the ordered half starts at |m| = 1 exactly, the random half far below
+    rows = S.trace_statistics(O.run_paths(4, 1.2, n_therm=1, n_meas=0, path_end=30, init="mixed", trace_sweeps=1,
+                                          seed=3)["trace"], 1, 2)
+    assert rows[0, 0] > 0.9
