@@ -53,6 +53,30 @@ def uneven_batch():
 WORKLOADS["uneven-batch-96-fp32"] = dict(precision="fp32", instances=uneven_batch())
 
 
+# Experiments of Secs. 3 and 4 run through paper_1305_6758_amd.experiments (single-instance
+# contexts: traced sweeps, or the plain FP64 engine for the both-angles proposal).
+TABLE1_TS = (0.6, 0.8, 1.0, 1.2, 1.4, 1.6)
+EXPERIMENTS = {
+    # Sec. 4: L = 10, T = 1, 10^4 paths, half from a random start and half ordered, every one of
+    # 5000 sweeps traced; <m> and its cv per sweep for each half.
+    "thermalisation-L10-T1-mixed-p1e4-fp32": dict(kind="thermalisation", L=10, T=1.0, n_paths=10 ** 4,
+                                                  sweeps=5000, init="mixed", fp64=False),
+    # Sec. 3, Table 1: L = 10 at six temperatures, 10^4 single-output paths after 5000 sweeps;
+    # isotropic proposal on the FP32 engine, both-angles proposal on the plain FP64 engine.
+    "table1-L10-sphere-p1e4-fp32": dict(kind="table", L=10, Ts=TABLE1_TS, n_paths=10 ** 4, sweeps=5000,
+                                        proposal="sphere", init="sphere", fp64=False),
+    "table1-L10-angles-p1e4-fp64": dict(kind="table", L=10, Ts=TABLE1_TS, n_paths=10 ** 4, sweeps=5000,
+                                        proposal="angles", init="angles", fp64=True),
+}
+
+
+def experiment_instances(spec):
+    """(L, T, n_paths, n_therm, n_meas) per context an experiment runs (instance id = index)."""
+    if spec["kind"] == "thermalisation":
+        return [(spec["L"], spec["T"], spec["n_paths"], spec["sweeps"], 0)]
+    return [(spec["L"], T, spec["n_paths"], spec["sweeps"] - 1, 1) for T in spec["Ts"]]
+
+
 def updates(instances):
     """Metropolis attempts of a workload: sum over instances of paths * L^3 * sweeps."""
     return sum(p * L ** 3 * (nt + nm) for (L, T, p, nt, nm) in instances)
