@@ -72,9 +72,17 @@ typedef enum { MMC_PROPOSAL_SPHERE = 0, MMC_PROPOSAL_ANGLES = 1 } mmc_proposal;
 
 /* Where a path's spins live during a sweep. LDS: the whole lattice of one path in the
  * workgroup's LDS. HBM: spins in device memory, one workgroup per path, sweeps inside
- * one launch. PLAIN: the plain FP64 engine, one launch per half-sweep and one thread per
- * site (FP64 only). AUTO: the tuner decides. */
-typedef enum { MMC_PLACE_AUTO = 0, MMC_PLACE_LDS = 1, MMC_PLACE_HBM = 2, MMC_PLACE_PLAIN = 3 } mmc_placement;
+ * one launch. WINDOW: spins in device memory, each workgroup (one path) running several
+ * sweeps per pass through a sliding window of z-planes in LDS (compiled for L = 24, 30, 32
+ * in FP32 and 12, 16 in FP64). PLAIN: the plain FP64 engine, one launch per half-sweep and
+ * one thread per site (FP64 only). AUTO: the tuner decides. */
+typedef enum {
+    MMC_PLACE_AUTO = 0,
+    MMC_PLACE_LDS = 1,
+    MMC_PLACE_HBM = 2,
+    MMC_PLACE_PLAIN = 3,
+    MMC_PLACE_WINDOW = 4
+} mmc_placement;
 
 /* Zero-initialised = defaults. */
 typedef struct {

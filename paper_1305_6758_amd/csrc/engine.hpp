@@ -68,6 +68,7 @@ struct Variant {
     // launch over all paths: sweeps [k0, k1); fresh = initialise first
     hipError_t (*launch)(const InstDev &in, int k0, int k1, int fresh, hipStream_t s);
     const void *kernel;  // the __global__ function (resident variants)
+    int window;          // sweeps per pass of the z-pipelined window variants, 0 otherwise
 };
 
 // Variants usable by resident runs, and by the batch kernel (fixed block size).

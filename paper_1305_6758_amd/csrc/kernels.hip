@@ -755,6 +755,410 @@ hipError_t launch_resident(const InstDev &in, int k0, int k1, int fresh, hipStre
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ z-pipelined window
+// For lattices whose spins do not fit in LDS: the path's spins stay in device memory and the
+// workgroup (one path) runs D sweeps per pass over them, holding a sliding window of
+// z-planes (both colours, three components) in LDS. Stage j = 2d + c of a pass is the
+// colour-c half-sweep of sweep ks + d; at step tau it updates every site of colour c in
+// virtual plane v = tau - 2j (physical plane v mod L), for v in [j, j + L). Stage j lags
+// stage j - 1 by three steps and starts one plane further round the periodic z-ring, so
+// each site sees exactly the neighbour values of the sequential half-sweep order (even
+// then odd, sweep after sweep), the periodic wrap included; stages that are active in the
+// same step touch disjoint data and run together between two barriers. A plane is read from
+// device memory into registers four steps before its first use, stored into the window at
+// the end of the next step (so the load's latency overlaps a whole step of updates), and
+// written back the step after its last use; virtual planes v and v + L are the same physical plane and
+// are never in the window together (L > 4D + 4). Device-memory traffic is about
+// 24 (1 + (2D + 1)/L) / D bytes per update in FP32 instead of 36.
+// Renormalisation boundaries (FP32) always start a pass: the pass normalises every site
+// when it first loads its plane, as the resident kernels do at the start of that sweep.
+template <typename T>
+__host__ __device__ constexpr size_t win_lds_bytes(int L, int B, int D)
+{
+    return (size_t)(4 * D + 4) * 3 * (size_t)L * L * sizeof(T) + 128 + (size_t)D * (B / 64) * 16 * sizeof(T);
+}
+
+__device__ __forceinline__ int wrap_mod(int v, int n)
+{
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Waves dealt out over n active stages (1 <= n <= NMAX): wave w serves stage slot w % n as
+// the (w / n)-th of its cnt waves. Division by a small runtime n through constant divisors.
+template <int M>
+__device__ __forceinline__ void deal_by(unsigned w, unsigned nwaves, int &slot, int &rank, int &cnt)
+{
+    slot = (int)(w % M);
+    rank = (int)(w / M);
+    cnt = (int)((nwaves - slot + M - 1) / M);
+}
+
+template <int NMAX>
+__device__ __forceinline__ void deal_waves(int w, int n, int nwaves, int &slot, int &rank, int &cnt)
+{
+    static_assert(NMAX <= 6, "at most six stages");
+    switch (n) {  // wave-uniform: one branch taken
+    case 1: slot = 0; rank = w; cnt = nwaves; break;
+    case 2: deal_by<2>(w, nwaves, slot, rank, cnt); break;
+    case 3: deal_by<3>(w, nwaves, slot, rank, cnt); break;
+    case 4: deal_by<4>(w, nwaves, slot, rank, cnt); break;
+    case 5: deal_by<5>(w, nwaves, slot, rank, cnt); break;
+    default: deal_by<6>(w, nwaves, slot, rank, cnt); break;
+    }
+}
+
+// Active stages j (3j <= tau < 3j + L) of a pass with nst stages: [lo, hi].
+__device__ __forceinline__ void active_stages(int tau, int L, int nst, int &lo, int &hi)
+{
+    lo = tau >= L ? (tau - L) / 3 + 1 : 0;
+    hi = tau / 3 < nst - 1 ? tau / 3 : nst - 1;
+}
+
+// One plane (both colours) of a path held by the workgroup's lanes in registers: lane t owns
+// the sites t, t + B, ... of the plane's 2 * plane sites (colour-major).
+template <typename T, int LC, int B>
+struct PlaneRegs {
+    static constexpr int PLANE = LC * LC / 2, NPS = (2 * PLANE + B - 1) / B;
+    T x[NPS], y[NPS], z[NPS];
+};
+
+template <typename T, int LC, int B>
+__device__ __forceinline__ void plane_load(PlaneRegs<T, LC, B> &r, const T *gsp, int zp, int tid, bool norm)
+{
+    constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE, NPS = PlaneRegs<T, LC, B>::NPS;
+#pragma unroll
+    for (int i = 0; i < NPS; ++i) {
+        const int e = tid + B * i;
+        if ((2 * PLANE) % B == 0 || e < 2 * PLANE) {
+            const int c = e >= PLANE, s = e - c * PLANE;
+            const T *q = gsp + c * 3 * HALF + zp * PLANE + s;
+            T x = q[0], y = q[HALF], z = q[2 * HALF];
+            if constexpr (std::is_same<T, float>::value) {
+                if (norm) {
+                    const float n = __builtin_amdgcn_rsqf(fmaf(z, z, fmaf(y, y, x * x)));
+                    x = x * n;
+                    y = y * n;
+                    z = z * n;
+                }
+            }
+            r.x[i] = x;
+            r.y[i] = y;
+            r.z[i] = z;
+        }
+    }
+}
+
+template <typename T, int LC, int B>
+__device__ __forceinline__ void plane_to_lds(const PlaneRegs<T, LC, B> &r, T *slot, int tid)
+{
+    constexpr int PLANE = LC * LC / 2, NPS = PlaneRegs<T, LC, B>::NPS;
+#pragma unroll
+    for (int i = 0; i < NPS; ++i) {
+        const int e = tid + B * i;
+        if ((2 * PLANE) % B == 0 || e < 2 * PLANE) {
+            const int c = e >= PLANE, s = e - c * PLANE;
+            T *q = slot + c * 3 * PLANE + s;
+            q[0] = r.x[i];
+            q[PLANE] = r.y[i];
+            q[2 * PLANE] = r.z[i];
+        }
+    }
+}
+
+template <typename T, int LC, int B>
+__device__ __forceinline__ void plane_writeback(const T *slot, T *gsp, int zp, int tid)
+{
+    constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE;
+    for (int e = tid; e < 2 * PLANE; e += B) {
+        const int c = e >= PLANE, s = e - c * PLANE;
+        const T *q = slot + c * 3 * PLANE + s;
+        T *o = gsp + c * 3 * HALF + zp * PLANE + s;
+        o[0] = q[0];
+        o[HALF] = q[PLANE];
+        o[2 * HALF] = q[2 * PLANE];
+    }
+}
+
+// Adds a wave's register partials of sweep d (if measured) to the sweep's LDS slots: sums
+// over each 16-lane row, one slot per (wave, row).
+template <typename T, int W>
+__device__ __forceinline__ void flush_partials(T *red, int d, bool meas, int wave, int wl, T &pe, T &pmx, T &pmy,
+                                               T &pmz)
+{
+    if (d >= 0 && meas) {
+        pe = row_sum(pe);
+        pmx = row_sum(pmx);
+        pmy = row_sum(pmy);
+        pmz = row_sum(pmz);
+        if ((wl & 15) == 0) {
+            T *q = red + ((d * W + wave) * 4 + (wl >> 4)) * 4;
+            q[0] += pe;
+            q[1] += pmx;
+            q[2] += pmy;
+            q[3] += pmz;
+        }
+    }
+    pe = pmx = pmy = pmz = T(0);
+}
+
+// Sweeps [k0, k1) of one path (the whole workgroup, B lanes) with spins in device memory
+// (g.sp). win: LDS window of 4D + 4 plane slots; red: LDS [D][B/64 waves][4 rows][4]
+// measurement partials.
+template <typename T, int LC, int B, int D>
+__device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const InstDev &in, int k0, int k1, bool fresh,
+                                                T *win, T *red)
+{
+    constexpr int L = LC, HL = L / 2, PLANE = L * L / 2, SLOT = 6 * PLANE, NW = 4 * D + 4, W = B / 64;
+    static_assert(L > 4 * D + 4, "the two copies of a plane must not meet in the window");
+    const double Nd = (double)L * L * L;
+    const int n_therm = in.n_therm, trace_sweeps = in.trace_sweeps, renorm_every = in.renorm_every;
+    const double J = in.J;
+    double *const trace = in.trace;
+    Coef<T> cf;
+    cf.beta = (T)in.beta;
+    cf.J = (T)in.J;
+    cf.q = (float)(in.beta * in.J * 1.4426950408889634);  // beta J log2(e)
+    const int tid = g.lane, wave = tid >> 6, wl = tid & 63;
+    unsigned long long nacc = 0;
+
+    if (g.active && fresh) init_path<T, B>(g.sp, L, tid, g.path, g.key0, g.key1, g.ctr3, in.init);
+    __syncthreads();
+    for (int ks = k0; ks < k1;) {
+        int Dp = k1 - ks < D ? k1 - ks : D;
+        bool rn = false;
+        if constexpr (std::is_same<T, float>::value) {
+            if (renorm_every > 0) {
+                const int next = (ks / renorm_every + 1) * renorm_every;
+                if (next - ks < Dp) Dp = next - ks;
+                rn = ks > 0 && ks % renorm_every == 0;
+            }
+        }
+        const int NST = 2 * Dp;                 // stages of this pass
+        const int vhi = L + NST - 1;            // last virtual plane read
+        const int tau_end = 3 * (NST - 1) + L - 1;
+        for (int i = tid; i < D * W * 16; i += B) red[i] = T(0);
+        PlaneRegs<T, LC, B> cur;  // the plane stored into the window at the end of the step
+        T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);  // this wave's partials of sweep acc_d
+        int acc_d = -1;
+        bool acc_meas = false;
+        if (g.active) {
+#pragma unroll 1
+            for (int v = -1; v <= 2; ++v) {
+                PlaneRegs<T, LC, B> r;
+                plane_load<T, LC, B>(r, g.sp, wrap_mod(v, L), tid, rn);
+                plane_to_lds<T, LC, B>(r, win + wrap_mod(v, NW) * SLOT, tid);
+            }
+            plane_load<T, LC, B>(cur, g.sp, 3, tid, rn);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int tau = 0; tau <= tau_end; ++tau) {
+            // the plane whose last use was the previous step goes back to device memory
+            const int vout = tau - 2 * NST;
+            if (vout >= 0 && g.active) plane_writeback<T, LC, B>(win + wrap_mod(vout, NW) * SLOT, g.sp, wrap_mod(vout, L), tid);
+            // prefetch of the plane first used four steps later (stored into the window next step)
+            const int vin = tau + 3, vnext = tau + 4;
+            const bool have_in = vin <= vhi && g.active;
+            PlaneRegs<T, LC, B> nxt;
+            if (vnext <= vhi && g.active) plane_load<T, LC, B>(nxt, g.sp, wrap_mod(vnext, L), tid, rn && vnext < L);
+            // a sweep whose odd stage ended two steps ago is complete (its partials reached the
+            // LDS slots at the start of the previous step): its measurement
+            const int jf = tau - 2 - (L - 1);
+            if (jf >= 3 && jf % 3 == 0 && ((jf / 3) & 1) && jf / 3 < NST) {
+                const int d = (jf / 3) >> 1;
+                const int k = ks + d;
+                if ((k >= n_therm || k < trace_sweeps || k == k1 - 1) && g.active && wave == 0) {
+                    T se = T(0), sx = T(0), sy = T(0), sz = T(0);
+                    if (wl < 4 * W) {
+                        const T *p = red + (d * W * 4 + wl) * 4;
+                        se = p[0];
+                        sx = p[1];
+                        sy = p[2];
+                        sz = p[3];
+                    }
+                    se = wave_sum(se);
+                    sx = wave_sum(sx);
+                    sy = wave_sum(sy);
+                    sz = wave_sum(sz);
+                    if (wl == 0) {
+                        const double e = -J * (double)se / Nd;
+                        const double mx = (double)sx / Nd, my = (double)sy / Nd, mz = (double)sz / Nd;
+                        if (k >= n_therm) {
+                            const double m = sqrt(mx * mx + my * my + mz * mz);
+                            g.shacc[0] += e;
+                            g.shacc[1] += e * e;
+                            g.shacc[2] += m;
+                            g.shacc[3] += m * m;
+                            g.shacc[4] += (m * m) * (m * m);
+                        }
+                        if (k < trace_sweeps) {
+                            double *tr = trace + ((size_t)g.path * trace_sweeps + k) * 4;
+                            tr[0] = e;
+                            tr[1] = mx;
+                            tr[2] = my;
+                            tr[3] = mz;
+                        }
+                        if (k == k1 - 1) {
+                            g.shacc[5] = e;
+                            g.shacc[6] = mx;
+                            g.shacc[7] = my;
+                            g.shacc[8] = mz;
+                        }
+                    }
+                }
+            }
+            // active stages j: 3j <= tau < 3j + L; waves are dealt out over them
+            int j_lo, j_hi, my, rank, nw;
+            active_stages(tau, L, NST, j_lo, j_hi);
+            deal_waves<2 * D>(wave, j_hi - j_lo + 1, W, my, rank, nw);
+            my = __builtin_amdgcn_readfirstlane(my);
+            rank = __builtin_amdgcn_readfirstlane(rank);
+            nw = __builtin_amdgcn_readfirstlane(nw);
+            // the partials stay in registers while the wave keeps serving the same sweep; they
+            // go to the sweep's LDS slots when it moves on to another one
+            if (((j_lo + my) >> 1) != acc_d) {
+                flush_partials<T, W>(red, acc_d, acc_meas, wave, wl, pe, pmx, pmy, pmz);
+                acc_d = (j_lo + my) >> 1;
+                acc_meas = ks + acc_d >= n_therm || ks + acc_d < trace_sweeps || ks + acc_d == k1 - 1;
+            }
+            const int stage = j_lo + my;
+            const int v = tau - 2 * stage, c = stage & 1, d = stage >> 1;
+            const int k = ks + d;
+            const int zp = wrap_mod(v, L);
+            const int sv = wrap_mod(v, NW);
+            const int dm = (wrap_mod(v - 1, NW) - sv) * SLOT, dp = (wrap_mod(v + 1, NW) - sv) * SLOT;
+            T *own = win + sv * SLOT + c * 3 * PLANE;
+            const T *oth = win + sv * SLOT + (1 - c) * 3 * PLANE;
+            if (g.active) {
+#pragma unroll 2
+                for (int s = rank * 64 + wl; s < PLANE; s += nw * 64) {
+                    const int jx = s % HL, y = s / HL;
+                    const int p = (y + zp + c) & 1;
+                    Site st;
+                    st.h = s;
+                    st.id = 2 * jx + p + L * y + L * L * zp;
+                    st.nb[0] = s + (p ? 0 : (jx == 0 ? HL - 1 : -1));
+                    st.nb[1] = s + (p ? (jx == HL - 1 ? -(HL - 1) : 1) : 0);
+                    st.nb[2] = s + (y == 0 ? (L - 1) * HL : -HL);
+                    st.nb[3] = s + (y == L - 1 ? -(L - 1) * HL : HL);
+                    st.nb[4] = s + dm;
+                    st.nb[5] = s + dp;
+                    update_site<T>(g, own, oth, PLANE, c != 0, st, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+                }
+            }
+            if (have_in) plane_to_lds<T, LC, B>(cur, win + wrap_mod(vin, NW) * SLOT, tid);
+            cur = nxt;
+            __syncthreads();
+        }
+        // the last sweep's measurement (the loop reaches the completion step of every other
+        // sweep), and the planes still in the window
+        flush_partials<T, W>(red, acc_d, acc_meas, wave, wl, pe, pmx, pmy, pmz);
+        __syncthreads();
+        {
+            const int d = Dp - 1, k = ks + d;
+            if ((k >= n_therm || k < trace_sweeps || k == k1 - 1) && g.active && wave == 0) {
+                T se = T(0), sx = T(0), sy = T(0), sz = T(0);
+                if (wl < 4 * W) {
+                    const T *p = red + (d * W * 4 + wl) * 4;
+                    se = p[0];
+                    sx = p[1];
+                    sy = p[2];
+                    sz = p[3];
+                }
+                se = wave_sum(se);
+                sx = wave_sum(sx);
+                sy = wave_sum(sy);
+                sz = wave_sum(sz);
+                if (wl == 0) {
+                    const double e = -J * (double)se / Nd;
+                    const double mx = (double)sx / Nd, my = (double)sy / Nd, mz = (double)sz / Nd;
+                    if (k >= n_therm) {
+                        const double m = sqrt(mx * mx + my * my + mz * mz);
+                        g.shacc[0] += e;
+                        g.shacc[1] += e * e;
+                        g.shacc[2] += m;
+                        g.shacc[3] += m * m;
+                        g.shacc[4] += (m * m) * (m * m);
+                    }
+                    if (k < trace_sweeps) {
+                        double *tr = trace + ((size_t)g.path * trace_sweeps + k) * 4;
+                        tr[0] = e;
+                        tr[1] = mx;
+                        tr[2] = my;
+                        tr[3] = mz;
+                    }
+                    if (k == k1 - 1) {
+                        g.shacc[5] = e;
+                        g.shacc[6] = mx;
+                        g.shacc[7] = my;
+                        g.shacc[8] = mz;
+                    }
+                }
+            }
+        }
+        if (g.active) {
+#pragma unroll 1
+            for (int v = tau_end + 1 - 2 * NST; v <= L + NST - 2; ++v)
+                plane_writeback<T, LC, B>(win + wrap_mod(v, NW) * SLOT, g.sp, wrap_mod(v, L), tid);
+        }
+        __syncthreads();
+        ks += Dp;
+    }
+    if (g.active && wl == 0) atomicAdd((unsigned long long *)&g.shacc[9], nacc);
+    __syncthreads();
+}
+
+// One path per workgroup (B lanes), spins in device memory at gsp, window in LDS.
+template <typename T, int LC, int B, int D>
+__device__ __forceinline__ void wg_run_win(const InstDev &in, int path, int k0, int k1, bool fresh, char *smem, T *gsp)
+{
+    constexpr int NW = 4 * D + 4;
+    GroupCtx<T> g;
+    g.L = in.L;
+    g.lane = threadIdx.x;
+    g.path = (uint32_t)__builtin_amdgcn_readfirstlane(path);
+    g.key0 = in.key0;
+    g.key1 = in.key1;
+    g.ctr3 = in.ctr3;
+    g.active = path < in.n_paths;
+    T *win = reinterpret_cast<T *>(smem);
+    char *p = smem + (size_t)NW * 3 * LC * LC * sizeof(T);
+    g.shacc = reinterpret_cast<double *>(p);
+    T *red = reinterpret_cast<T *>(p + 128);
+    g.red = red;
+    g.sp = gsp;
+    load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
+    path_sweeps_win<T, LC, B, D>(g, in, k0, k1, fresh, win, red);
+    store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
+}
+
+template <typename T, int B, int D>
+constexpr int win_waves(int L)
+{
+    const int wgs = (int)((size_t)160 * 1024 / win_lds_bytes<T>(L, B, D));
+    const int w = (wgs < 1 ? 1 : wgs) * (B / 64) / 4, cap = sizeof(T) == 8 ? 2 : 8;
+    return w < 1 ? 1 : (w > cap ? cap : w);
+}
+
+template <typename T, int LC, int B, int D>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(win_waves<T, B, D>(LC))))
+void k_window(InstDev in, int k0, int k1, int fresh)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int path = blockIdx.x;
+    wg_run_win<T, LC, B, D>(in, path, k0, k1, fresh != 0, smem,
+                            reinterpret_cast<T *>(in.spins) + (size_t)path * 3 * LC * LC * LC);
+}
+
+template <typename T, int LC, int B, int D>
+hipError_t launch_window(const InstDev &in, int k0, int k1, int fresh, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_window<T, LC, B, D>), dim3(in.n_paths), dim3(B), win_lds_bytes<T>(LC, B, D), s, in, k0, k1,
+                       fresh);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ persistent batch kernel
 constexpr int BATCH_B = 512;
 
@@ -975,7 +1379,11 @@ __global__ void k_set_int(int *p, int v) { *p = v; }
 #define MMC_RES(TT, LC, G, B, MAP, LDS, NAME)                                                         \
     Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, LDS ? 1 : 0, B, G,                      \
             (LC ? lds_layout_bytes<TT>(LC, B, G, LDS) : 0), &launch_resident<TT, LC, G, B, MAP, LDS>,           \
-            (const void *)&k_resident<TT, LC, G, B, MAP, LDS>},
+            (const void *)&k_resident<TT, LC, G, B, MAP, LDS>, 0},
+
+#define MMC_WIN(TT, LC, B, D, NAME)                                                                   \
+    Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, 0, B, B, win_lds_bytes<TT>(LC, B, D),          \
+            &launch_window<TT, LC, B, D>, (const void *)&k_window<TT, LC, B, D>, D},
 
 static const Variant k_variants[] = {
     // FP32, spins in LDS
@@ -996,6 +1404,12 @@ static const Variant k_variants[] = {
     MMC_RES(float, 64, 512, 512, COLZ, false, "f32-hbm-L64-g512-b512")
     MMC_RES(float, 64, 1024, 1024, COLZ, false, "f32-hbm-L64-g1024-b1024")
     MMC_RES(float, 0, 512, 512, FLAT, false, "f32-hbm-any-g512-b512")
+    // FP32, spins in device memory, z-pipelined window in LDS
+    MMC_WIN(float, 24, 512, 2, "f32-win-L24-d2-b512")
+    MMC_WIN(float, 24, 1024, 3, "f32-win-L24-d3-b1024")
+    MMC_WIN(float, 30, 1024, 2, "f32-win-L30-d2-b1024")
+    MMC_WIN(float, 32, 512, 2, "f32-win-L32-d2-b512")
+    MMC_WIN(float, 32, 1024, 2, "f32-win-L32-d2-b1024")
     // FP64, spins in LDS
     MMC_RES(double, 8, 64, 256, COLZ, true, "f64-lds-L8-g64-b256")
     MMC_RES(double, 8, 256, 256, COLZ, true, "f64-lds-L8-g256-b256")
@@ -1007,8 +1421,12 @@ static const Variant k_variants[] = {
     MMC_RES(double, 32, 512, 512, COLZ, false, "f64-hbm-L32-g512-b512")
     MMC_RES(double, 64, 1024, 1024, COLZ, false, "f64-hbm-L64-g1024-b1024")
     MMC_RES(double, 0, 512, 512, FLAT, false, "f64-hbm-any-g512-b512")
+    // FP64, window (small lattices: parity of the pipelined schedule with the oracle)
+    MMC_WIN(double, 12, 256, 1, "f64-win-L12-d1-b256")
+    MMC_WIN(double, 16, 256, 2, "f64-win-L16-d2-b256")
 };
 #undef MMC_RES
+#undef MMC_WIN
 
 const Variant *variants(int *count)
 {
@@ -1018,7 +1436,7 @@ const Variant *variants(int *count)
 
 #define MMC_BV(TT, LC, G, MAP, LDS, NAME)                                                            \
     Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, LDS ? 1 : 0, BATCH_B, G,               \
-            (LC ? lds_layout_bytes<TT>(LC, BATCH_B, G, LDS) : 0), nullptr, nullptr},
+            (LC ? lds_layout_bytes<TT>(LC, BATCH_B, G, LDS) : 0), nullptr, nullptr, 0},
 static const Variant k_batch_f32[] = {MMC_BATCH_VARIANTS_F32(MMC_BV)};
 static const Variant k_batch_f64[] = {MMC_BATCH_VARIANTS_F64(MMC_BV)};
 #undef MMC_BV
@@ -1037,6 +1455,7 @@ int batch_block() { return BATCH_B; }
 
 size_t variant_lds_bytes(const Variant &v, int L)
 {
+    if (v.window) return v.lds_bytes;
     return v.fp64 ? lds_layout_bytes<double>(L, v.block, v.lanes, v.lds) : lds_layout_bytes<float>(L, v.block, v.lanes, v.lds);
 }
 

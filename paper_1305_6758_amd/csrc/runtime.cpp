@@ -227,7 +227,7 @@ bool variant_fits(const mmc::Variant &v, int fp64, int L, int lds_limit)
 {
     if (v.fp64 != fp64) return false;
     if (v.L != 0 && v.L != L) return false;
-    if (v.lds && mmc::variant_lds_bytes(v, L) > (size_t)lds_limit) return false;
+    if ((v.lds || v.window) && mmc::variant_lds_bytes(v, L) > (size_t)lds_limit) return false;
     return true;
 }
 
@@ -242,7 +242,8 @@ std::vector<int> single_candidates(const mmc_ctx *c, int L)
         const mmc::Variant &v = vs[i];
         if (!variant_fits(v, c->fp64, L, lim)) continue;
         if (place == MMC_PLACE_LDS && !v.lds) continue;
-        if (place == MMC_PLACE_HBM && v.lds) continue;
+        if (place == MMC_PLACE_HBM && (v.lds || v.window)) continue;
+        if (place == MMC_PLACE_WINDOW && !v.window) continue;
         if (c->cfg.block && v.block != c->cfg.block) continue;
         if (c->cfg.lanes_per_path && v.lanes != c->cfg.lanes_per_path) continue;
         out.push_back(i);
@@ -266,6 +267,7 @@ std::vector<int> batch_candidates(int fp64, int L, int placement)
         if (v.lds && mmc::variant_lds_bytes(v, L) > lds_budget) continue;
         if (placement == MMC_PLACE_LDS && !v.lds) continue;
         if (placement == MMC_PLACE_HBM && v.lds) continue;
+        if (placement == MMC_PLACE_WINDOW) continue;  // no batch form yet
         out.push_back(i);
     }
     bool have_exact = false;
@@ -502,7 +504,7 @@ mmc_ctx *mmc_create_ex(int L, double T, double J, int n_paths, int n_therm, int 
         fail(MMC_EINVAL, "precision must be MMC_FP32 or MMC_FP64");
         return nullptr;
     }
-    if (c0.init < MMC_INIT_SPHERE || c0.init > MMC_INIT_MIXED || c0.placement < 0 || c0.placement > MMC_PLACE_PLAIN ||
+    if (c0.init < MMC_INIT_SPHERE || c0.init > MMC_INIT_MIXED || c0.placement < 0 || c0.placement > MMC_PLACE_WINDOW ||
         c0.proposal < MMC_PROPOSAL_SPHERE || c0.proposal > MMC_PROPOSAL_ANGLES ||
         c0.block < 0 || c0.lanes_per_path < 0 || c0.trace_sweeps < 0 || c0.instance_id >= (1u << 24)) {
         fail(MMC_EINVAL, "configuration out of range");

@@ -17,7 +17,7 @@ MMC_OK, MMC_EINVAL, MMC_ENOMEM, MMC_EHIP, MMC_ESTATE, MMC_EUNSUPPORTED, MMC_EIO 
 MMC_FP32, MMC_FP64 = 0, 1
 MMC_INIT_SPHERE, MMC_INIT_ANGLES, MMC_INIT_ORDERED, MMC_INIT_MIXED = 0, 1, 2, 3
 MMC_PROPOSAL_SPHERE, MMC_PROPOSAL_ANGLES = 0, 1
-MMC_PLACE_AUTO, MMC_PLACE_LDS, MMC_PLACE_HBM, MMC_PLACE_PLAIN = 0, 1, 2, 3
+MMC_PLACE_AUTO, MMC_PLACE_LDS, MMC_PLACE_HBM, MMC_PLACE_PLAIN, MMC_PLACE_WINDOW = 0, 1, 2, 3, 4
 
 
 class mmc_config(C.Structure):
