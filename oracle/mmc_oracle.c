@@ -450,3 +450,151 @@ int mmco_max_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------------------
+ * Two-dimensional Ising model (appendix "2D Ising model"): spins s = +-1 on an L x L
+ * periodic square lattice, H = -J sum over bonds s_i s_j, the same multipath set-up as the
+ * Heisenberg model (random start, checkerboard Metropolis sweeps, per-path outputs).
+ *
+ * Site id i = x + L y; colour c = (x + y) mod 2; j = floor(x / 2) indexes the site within its
+ * row of colour c. Readings where the appendix is silent (listed in the design notes):
+ *   - move: flip s_i; dE = 2 J s_i h_i with h_i the sum of the four neighbours; accept iff
+ *     u < exp(-beta dE) (downhill and level moves always taken);
+ *   - random numbers: one Philox4x32-10 call serves a "quad" of four consecutive sites of a
+ *     row of one colour: quad jq = floor(j / 4) of row y of colour c has index
+ *     q = c L Q + y Q + jq with Q = ceil((L/2) / 4) quads per row; sweep k of path p uses
+ *     counter (q, k, p, TAG_ISING | instance << 8) and the site takes word j mod 4 as its
+ *     uniform u = (w + 1/2) 2^-32 (rows whose length is not a multiple of four leave the
+ *     spare words of their last quad unused);
+ *   - random start: counter (q, 0, p, TAG_ISING_INIT | instance << 8), word j mod 4: s = +1
+ *     when w < 2^31, else -1; ORDERED: all +1; MIXED: even paths random, odd paths ordered;
+ *   - outputs: per sweep e = E/N and m = M/N (signed); the per-path means of e, e^2, |m|,
+ *     m^2, m^4 over the measured sweeps; final_m = (m, 0, 0) and final_e of the last state.
+ * ---------------------------------------------------------------------------------- */
+enum { MMCO_TAG_ISING = 3, MMCO_TAG_ISING_INIT = 4 };
+
+static int ising_quads_per_row(int L) { return (L / 2 + 3) / 4; }
+
+/* Uniform word of site (x, y) at counter word 1 = k (k = 0 with tag INIT for the start). */
+static uint32_t ising_word(int L, int x, int y, uint32_t k, uint32_t path, uint32_t tag, uint32_t instance,
+                           uint64_t seed)
+{
+    int Q = ising_quads_per_row(L), c = (x + y) & 1, j = x >> 1;
+    uint32_t q = (uint32_t)(c * L * Q + y * Q + (j >> 2));
+    uint32_t ctr[4] = { q, k, path, tag | (instance << 8) };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t w[4];
+    mmco_philox4x32_10(ctr, key, w);
+    return w[j & 3];
+}
+
+static int ising_field(int L, const int8_t *s, int x, int y)
+{
+    int xm = (x + L - 1) % L, xp = (x + 1) % L, ym = (y + L - 1) % L, yp = (y + 1) % L;
+    return s[xm + L * y] + s[xp + L * y] + s[x + L * ym] + s[x + L * yp];
+}
+
+/* Exported for the pins: the start and one Metropolis attempt, exactly as the runs do them. */
+int mmco_ising_init_spin(int L, int x, int y, uint32_t path, uint32_t instance, uint64_t seed)
+{
+    return ising_word(L, x, y, 0u, path, MMCO_TAG_ISING_INIT, instance, seed) < 0x80000000u ? 1 : -1;
+}
+
+int mmco_ising_accept(int L, int x, int y, uint32_t k, uint32_t path, uint32_t instance, uint64_t seed,
+                      double beta, double J, int s_times_h)
+{
+    double dE = 2.0 * J * (double)s_times_h;
+    double u = mmco_uniform(ising_word(L, x, y, k, path, MMCO_TAG_ISING, instance, seed));
+    return u < exp(-beta * dE);
+}
+
+/* Paths [path_begin, path_end) of the Ising model; out[t] as for the Heisenberg runs (final_m
+ * = (M/N, 0, 0)); trace[t][k][4] = (e_k, m_k, 0, 0) for k < trace_sweeps; spins_out[t][N]. */
+int mmco_ising_run_paths(int L, double T, double J, int n_therm, int n_meas, uint64_t seed, uint32_t instance,
+                         int init, int path_begin, int path_end, int trace_sweeps, mmco_path_result *out,
+                         double *trace, int8_t *spins_out, int n_threads)
+{
+    if (L < 2 || (L & 1) || !(T > 0.0) || n_therm < 0 || n_meas < 0 || path_end < path_begin) return -1;
+    const int N = L * L;
+    const double beta = isinf(T) ? 0.0 : 1.0 / T;
+    const int n = path_end - path_begin;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int t = 0; t < n; ++t) {
+        const uint32_t path = (uint32_t)(path_begin + t);
+        int8_t *s = (int8_t *)malloc((size_t)N);
+        int mode = init == MMCO_INIT_MIXED ? ((path & 1u) ? MMCO_INIT_ORDERED : MMCO_INIT_SPHERE) : init;
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x)
+                s[x + L * y] = (int8_t)(mode == MMCO_INIT_ORDERED ? 1 : mmco_ising_init_spin(L, x, y, path, instance, seed));
+        double sum_e = 0, sum_e2 = 0, sum_m = 0, sum_m2 = 0, sum_m4 = 0, e = 0, m = 0;
+        uint64_t acc = 0;
+        const int K = n_therm + n_meas;
+        for (int k = 0; k < K; ++k) {
+            for (int c = 0; c < 2; ++c)
+                for (int y = 0; y < L; ++y)
+                    for (int x = 0; x < L; ++x) {
+                        if (((x + y) & 1) != c) continue;
+                        int a = s[x + L * y] * ising_field(L, s, x, y);
+                        if (mmco_ising_accept(L, x, y, (uint32_t)k, path, instance, seed, beta, J, a)) {
+                            s[x + L * y] = (int8_t)-s[x + L * y];
+                            ++acc;
+                        }
+                    }
+            /* H = -(J/2) sum_i s_i h_i and M = sum_i s_i, from the definition */
+            long long sh = 0, M = 0;
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    sh += s[x + L * y] * ising_field(L, s, x, y);
+                    M += s[x + L * y];
+                }
+            e = -J * (double)(sh / 2) / (double)N;
+            m = (double)M / (double)N;
+            if (k >= n_therm) {
+                double am = fabs(m);
+                sum_e += e;
+                sum_e2 += e * e;
+                sum_m += am;
+                sum_m2 += m * m;
+                sum_m4 += (m * m) * (m * m);
+            }
+            if (trace && k < trace_sweeps) {
+                double *r = trace + ((size_t)t * trace_sweeps + k) * 4;
+                r[0] = e;
+                r[1] = m;
+                r[2] = 0.0;
+                r[3] = 0.0;
+            }
+        }
+        mmco_path_result *o = out + t;
+        if (n_meas > 0) {
+            o->e_mean = sum_e / n_meas;
+            o->e2_mean = sum_e2 / n_meas;
+            o->absm_mean = sum_m / n_meas;
+            o->m2_mean = sum_m2 / n_meas;
+            o->m4_mean = sum_m4 / n_meas;
+        } else {
+            o->e_mean = o->e2_mean = o->absm_mean = o->m2_mean = o->m4_mean = NAN;
+        }
+        if (K == 0) {
+            long long sh = 0, M = 0;
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    sh += s[x + L * y] * ising_field(L, s, x, y);
+                    M += s[x + L * y];
+                }
+            e = -J * (double)(sh / 2) / (double)N;
+            m = (double)M / (double)N;
+        }
+        o->final_m[0] = m;
+        o->final_m[1] = 0.0;
+        o->final_m[2] = 0.0;
+        o->final_e = e;
+        o->n_accept = acc;
+        if (spins_out) memcpy(spins_out + (size_t)t * N, s, (size_t)N);
+        free(s);
+    }
+    return 0;
+}

@@ -75,6 +75,15 @@ def lib():
                                      dp, dp, C.c_int]
         L.mmco_run_paths.restype = C.c_int
         L.mmco_max_threads.restype = C.c_int
+        L.mmco_ising_init_spin.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint32, C.c_uint32, C.c_uint64]
+        L.mmco_ising_init_spin.restype = C.c_int
+        L.mmco_ising_accept.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
+                                        C.c_double, C.c_double, C.c_int]
+        L.mmco_ising_accept.restype = C.c_int
+        L.mmco_ising_run_paths.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.c_uint64,
+                                           C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(PathResult),
+                                           dp, C.POINTER(C.c_int8), C.c_int]
+        L.mmco_ising_run_paths.restype = C.c_int
         _lib = L
     return _lib
 
@@ -116,6 +125,32 @@ def run_paths(L, T, J=1.0, n_therm=0, n_meas=0, seed=1234, path_begin=0, path_en
     rc = lib().mmco_run_paths(C.byref(p), path_begin, path_end, res,
                               _dp(trace) if trace is not None else None,
                               _dp(spins) if spins is not None else None, n_threads)
+    if rc != 0:
+        raise ValueError("oracle rejected the parameters")
+    out = {k: np.array([getattr(r, k) for r in res]) for k in
+           ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e", "n_accept")}
+    out["final_m"] = np.array([list(r.final_m) for r in res]).reshape(n, 3)
+    out["n_accept"] = out["n_accept"].astype(np.uint64)
+    if trace is not None:
+        out["trace"] = trace
+    if spins is not None:
+        out["spins"] = spins
+    return out
+
+
+def ising_run_paths(L, T, J=1.0, n_therm=0, n_meas=0, seed=1234, path_begin=0, path_end=1, instance=0,
+                    init="sphere", trace_sweeps=0, want_spins=False, n_threads=0):
+    """2-D Ising paths [path_begin, path_end) (init 'sphere' = random start). Same result keys as
+    run_paths; final_m[:, 0] = M/N; trace [n, trace_sweeps, 4] = (e_k, m_k, 0, 0); spins [n, L*L]
+    int8 in site-id order (x fastest)."""
+    n = path_end - path_begin
+    res = (PathResult * n)()
+    trace = np.zeros((n, trace_sweeps, 4)) if trace_sweeps > 0 else None
+    spins = np.zeros((n, L * L), dtype=np.int8) if want_spins else None
+    rc = lib().mmco_ising_run_paths(L, float(T), float(J), n_therm, n_meas, seed, instance, INITS[init], path_begin,
+                                    path_end, trace_sweeps, res, _dp(trace) if trace is not None else None,
+                                    spins.ctypes.data_as(C.POINTER(C.c_int8)) if spins is not None else None,
+                                    n_threads)
     if rc != 0:
         raise ValueError("oracle rejected the parameters")
     out = {k: np.array([getattr(r, k) for r in res]) for k in
