@@ -70,6 +70,19 @@ typedef enum { MMC_INIT_SPHERE = 0, MMC_INIT_ANGLES = 1, MMC_INIT_ORDERED = 2, M
  * z). ANGLES runs on the plain FP64 engine only (placement MMC_PLACE_PLAIN, MMC_FP64). */
 typedef enum { MMC_PROPOSAL_SPHERE = 0, MMC_PROPOSAL_ANGLES = 1 } mmc_proposal;
 
+/* Model. HEISENBERG3D (default): the classical O(3) Heisenberg model on an L^3 periodic simple
+ * cubic lattice (Sec. 2). ISING2D: the Ising model on an L x L periodic square lattice (the
+ * paper's appendix), spins +-1, H = -J sum over bonds s_i s_j, the same multipath set-up:
+ * checkerboard Metropolis flips, one Philox4x32-10 call per quad of four sites of a row of one
+ * colour (counter (c L Q + y Q + floor(j/4), sweep, path, 3 | instance << 8), Q = ceil(L/8),
+ * j = floor(x/2), word j mod 4 for site (x, y) of colour c = (x + y) mod 2; the start uses tag
+ * 4 and sweep word 0: s = +1 iff the word is below 2^31), exact integer decisions. Per-path
+ * outputs as for the Heisenberg model with m = M/N signed, final_m = (m, 0, 0) and the trace
+ * (e, m, 0, 0); mmc_get_spins puts s in the z component of site x + L y. Single-instance
+ * contexts only (no batch), spins in LDS; precision, proposal, block and lanes do not apply;
+ * init SPHERE means the random start. */
+typedef enum { MMC_MODEL_HEISENBERG3D = 0, MMC_MODEL_ISING2D = 1 } mmc_model;
+
 /* Where a path's spins live during a sweep. LDS: the whole lattice of one path in the
  * workgroup's LDS. HBM: spins in device memory, one workgroup per path, sweeps inside
  * one launch. WINDOW: spins in device memory, each workgroup (one path) running several
@@ -96,6 +109,7 @@ typedef struct {
     int trace_sweeps;   /* record (e_k, M_k) for sweeps k < trace_sweeps */
     int async;          /* nonzero: mmc_run/mmc_batch_run return without waiting */
     int proposal;       /* mmc_proposal, default MMC_PROPOSAL_SPHERE */
+    int model;          /* mmc_model, default MMC_MODEL_HEISENBERG3D */
 } mmc_config;
 
 /* Per-path output. Means over the n_meas measured sweeps (NaN when n_meas = 0), per site:

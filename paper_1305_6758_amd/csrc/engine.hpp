@@ -37,6 +37,10 @@ struct InstDev {
     void *spins;         // resident state [n_paths][2 colours][3][N/2] (T), or nullptr
     PathAcc *acc;        // [n_paths]
     double *trace;       // [n_paths][trace_sweeps][4] or nullptr
+    // 2-D Ising model: accept iff the word is below ithr[(a + 4) / 2] or bit (a + 4) / 2 of iall
+    // is set, for a = s h in {-4, -2, 0, 2, 4}
+    uint32_t ithr[5];
+    uint32_t iall;
 };
 
 // One work item of a batch: paths [path0, path0 + paths_per_item) of instance inst.
@@ -73,6 +77,8 @@ struct Variant {
 
 // Variants usable by resident runs, and by the batch kernel (fixed block size).
 const Variant *variants(int *count);
+const Variant *ising_variants(int *count);  // 2-D Ising model (spins in LDS)
+size_t ising_variant_lds_bytes(int L);
 const Variant *batch_variants(int fp64, int *count);  // index = BatchDev::variant value
 size_t variant_lds_bytes(const Variant &v, int L);             // dynamic LDS at side L
 int batch_block();                                      // threads per workgroup in the batch kernel

@@ -17,6 +17,11 @@
 #include "../../include/mmc.h"
 #include "engine.hpp"
 
+namespace mmc {
+// Host statistics of n path results of a lattice of N sites (stats.cpp).
+int stats_of(const mmc_path_result *res, int n, double N, double T, mmc_stats_t *out);
+}  // namespace mmc
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -93,7 +98,17 @@ struct mmc_ctx {
     bool tuned = false;
 };
 
-size_t spin_bytes_of(const mmc_ctx *c, int L) { return 3 * (size_t)L * L * L * (c->fp64 ? 8 : 4); }
+size_t spin_bytes_of(const mmc_ctx *c, int L)
+{
+    if (c->cfg.model == MMC_MODEL_ISING2D) return (size_t)L * L;  // one byte per spin
+    return 3 * (size_t)L * L * L * (c->fp64 ? 8 : 4);
+}
+
+// Kernel variants of a single-instance context's model.
+const mmc::Variant *single_table(const mmc_ctx *c, int *n)
+{
+    return c->cfg.model == MMC_MODEL_ISING2D ? mmc::ising_variants(n) : mmc::variants(n);
+}
 
 namespace {
 
@@ -143,6 +158,22 @@ mmc::InstDev inst_dev(const mmc_ctx *c, const Instance &in, uint32_t instance_id
     d.spins = c->batch ? nullptr : c->ws + in.off_spins;
     d.acc = reinterpret_cast<mmc::PathAcc *>(c->ws + in.off_acc);
     d.trace = (!c->batch && c->cfg.trace_sweeps > 0) ? reinterpret_cast<double *>(c->ws + in.off_trace) : nullptr;
+    if (c->cfg.model == MMC_MODEL_ISING2D) {
+        // u = (w + 1/2) 2^-32 < p  <=>  w < ceil(p 2^32 - 1/2) for integer w (p 2^32 is exact
+        // and the subtraction too, p < 2^20); p >= 1 - 2^-33 takes every word
+        d.iall = 0;
+        for (int i = 0; i < 5; ++i) {
+            const double dE = 2.0 * in.J * (double)(2 * i - 4);
+            const double p = exp(-d.beta * dE);
+            const double t = ceil(p * 4294967296.0 - 0.5);
+            if (t >= 4294967296.0) {
+                d.iall |= 1u << i;
+                d.ithr[i] = 0;
+            } else {
+                d.ithr[i] = (uint32_t)t;
+            }
+        }
+    }
     return d;
 }
 
@@ -234,9 +265,18 @@ bool variant_fits(const mmc::Variant &v, int fp64, int L, int lds_limit)
 std::vector<int> single_candidates(const mmc_ctx *c, int L)
 {
     int n;
-    const mmc::Variant *vs = mmc::variants(&n);
+    const mmc::Variant *vs = single_table(c, &n);
     const int lim = device_lds_limit();
     std::vector<int> out;
+    if (c->cfg.model == MMC_MODEL_ISING2D) {
+        // the variant compiled for this L, else the generic one if its LDS fits
+        for (int i = 0; i < n; ++i)
+            if (vs[i].L == L) out.push_back(i);
+        if (out.empty() && mmc::ising_variant_lds_bytes(L) <= (size_t)lim)
+            for (int i = 0; i < n; ++i)
+                if (vs[i].L == 0) out.push_back(i);
+        return out;
+    }
     const int place = c->cfg.placement;
     for (int i = 0; i < n; ++i) {
         const mmc::Variant &v = vs[i];
@@ -387,7 +427,7 @@ int enqueue_single(mmc_ctx *c, int k0, int k1, bool fresh, hipStream_t s)
         return MMC_OK;
     }
     int n;
-    const mmc::Variant *vs = mmc::variants(&n);
+    const mmc::Variant *vs = single_table(c, &n);
     hipError_t e = vs[in.variant].launch(d, k0, k1, fresh ? 1 : 0, s);
     if (e != hipSuccess) return fail(MMC_EHIP, "launch %s: %s", vs[in.variant].name, hipGetErrorString(e));
     return MMC_OK;
@@ -446,7 +486,7 @@ double time_single_candidate(mmc_ctx *c, int variant, int sweeps)
     d.trace_sweeps = 0;
     d.trace = nullptr;
     int n;
-    const mmc::Variant *vs = mmc::variants(&n);
+    const mmc::Variant *vs = single_table(c, &n);
     double best = 1e30;
     for (int rep = 0; rep < 2; ++rep) {
         if (hipEventRecord(c->ev0, c->stream) != hipSuccess) break;
@@ -509,6 +549,21 @@ mmc_ctx *mmc_create_ex(int L, double T, double J, int n_paths, int n_therm, int 
         c0.block < 0 || c0.lanes_per_path < 0 || c0.trace_sweeps < 0 || c0.instance_id >= (1u << 24)) {
         fail(MMC_EINVAL, "configuration out of range");
         return nullptr;
+    }
+    if (c0.model != MMC_MODEL_HEISENBERG3D && c0.model != MMC_MODEL_ISING2D) {
+        fail(MMC_EINVAL, "model must be MMC_MODEL_HEISENBERG3D or MMC_MODEL_ISING2D");
+        return nullptr;
+    }
+    if (c0.model == MMC_MODEL_ISING2D) {
+        if (c0.placement != MMC_PLACE_AUTO && c0.placement != MMC_PLACE_LDS) {
+            fail(MMC_EUNSUPPORTED, "the Ising model runs with its spins in LDS only");
+            return nullptr;
+        }
+        if (c0.init == MMC_INIT_ANGLES || c0.proposal != MMC_PROPOSAL_SPHERE || c0.block || c0.lanes_per_path) {
+            fail(MMC_EINVAL, "Ising: init must be SPHERE (random), ORDERED or MIXED; no proposal, block or lane choice");
+            return nullptr;
+        }
+        c0.precision = MMC_FP32;  // integer spins; the statistics are FP64 either way
     }
     if (c0.trace_sweeps > n_therm + n_meas) c0.trace_sweeps = n_therm + n_meas;
     mmc_ctx *c = new mmc_ctx;
@@ -585,7 +640,7 @@ int mmc_tune(mmc_ctx *c)
         return MMC_OK;
     }
     int n;
-    const mmc::Variant *vs = mmc::variants(&n);
+    const mmc::Variant *vs = single_table(c, &n);
     const std::string key = tune_key(false, c->fp64, in.L, in.n_paths);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -743,12 +798,27 @@ int mmc_get_spins(const mmc_ctx *c, int path, double *xyz, size_t n_out)
     if (c->batch) return fail(MMC_EUNSUPPORTED, "no resident spins on a batch");
     const Instance &in = c->inst[0];
     const int L = in.L, HL = L / 2;
-    const size_t N = (size_t)L * L * L, HALF = N / 2;
+    const size_t N = (size_t)L * L * (c->cfg.model == MMC_MODEL_ISING2D ? 1 : L), HALF = N / 2;
     if (path < 0 || path >= in.n_paths) return fail(MMC_EINVAL, "path %d out of range", path);
     if (!xyz || n_out < 3 * N) return fail(MMC_EINVAL, "spin output needs %zu doubles", 3 * N);
     if (!c->ws || c->sweeps_done == 0) return fail(MMC_ESTATE, "nothing has run yet");
     HIP_TRY(hipStreamSynchronize(c->stream));
     const size_t bytes = spin_bytes_of(c, L);
+    if (c->cfg.model == MMC_MODEL_ISING2D) {
+        // [colour][y][x >> 1] bytes; the spin goes to the z component of site x + L y
+        if (n_out < 3 * (size_t)L * L) return fail(MMC_EINVAL, "spin output needs %zu doubles", 3 * (size_t)L * L);
+        std::vector<int8_t> raw(bytes);
+        HIP_TRY(hipMemcpy(raw.data(), c->ws + in.off_spins + (size_t)path * bytes, bytes, hipMemcpyDeviceToHost));
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                const size_t i = (size_t)x + (size_t)L * y;
+                const int colour = (x + y) & 1;
+                xyz[3 * i + 0] = 0.0;
+                xyz[3 * i + 1] = 0.0;
+                xyz[3 * i + 2] = (double)raw[(size_t)colour * L * HL + (size_t)y * HL + (x >> 1)];
+            }
+        return MMC_OK;
+    }
     std::vector<char> raw(bytes);
     HIP_TRY(hipMemcpy(raw.data(), c->ws + in.off_spins + (size_t)path * bytes, bytes, hipMemcpyDeviceToHost));
     for (int z = 0; z < L; ++z)
@@ -774,11 +844,12 @@ int mmc_stats(const mmc_ctx *c, mmc_stats_t *out)
     std::vector<mmc_path_result> r(in.n_paths);
     int rc = mmc_results(c, r.data(), in.n_paths);
     if (rc) return rc;
-    rc = mmc_stats_from_results(r.data(), in.n_paths, in.L, in.T, out);
+    const double N = (double)in.L * in.L * (c->cfg.model == MMC_MODEL_ISING2D ? 1 : in.L);
+    rc = mmc::stats_of(r.data(), in.n_paths, N, in.T, out);
     if (rc) return rc;
     double acc = 0;
     for (auto &x : r) acc += (double)x.n_accept;
-    out->accept_rate = acc / ((double)in.n_paths * c->sweeps_done * (double)in.L * in.L * in.L);
+    out->accept_rate = acc / ((double)in.n_paths * c->sweeps_done * N);
     return MMC_OK;
 }
 
@@ -800,7 +871,7 @@ int mmc_save(const mmc_ctx *c, const char *file)
     HIP_TRY(hipMemcpy(buf.data() + sb, c->ws + in.off_acc, ab, hipMemcpyDeviceToHost));
     if (tb) HIP_TRY(hipMemcpy(buf.data() + sb + ab, c->ws + in.off_trace, tb, hipMemcpyDeviceToHost));
     int n;
-    const mmc::Variant *vs = mmc::variants(&n);
+    const mmc::Variant *vs = single_table(c, &n);
     char vname[64] = {0};
     snprintf(vname, sizeof vname, "%s", in.plain ? "plain" : vs[in.variant].name);
     FILE *f = fopen(file, "wb");
@@ -871,7 +942,7 @@ mmc_ctx *mmc_load(const char *file)
     // but keeping it avoids a tuning run on a context that has state)
     if (!in.plain) {
         int n;
-        const mmc::Variant *vs = mmc::variants(&n);
+        const mmc::Variant *vs = single_table(c, &n);
         for (int i = 0; i < n; ++i)
             if (strcmp(vs[i].name, vname) == 0) in.variant = i;
     }
@@ -905,7 +976,7 @@ int mmc_plan(const mmc_ctx *c, char *buf, size_t n)
         }
     } else {
         const Instance &in = c->inst[0];
-        const mmc::Variant *vs = mmc::variants(&nv);
+        const mmc::Variant *vs = single_table(c, &nv);
         s = in.plain ? "plain-f64" : (in.variant >= 0 ? vs[in.variant].name : "unplanned");
     }
     snprintf(buf, n, "%s", s.c_str());
@@ -941,6 +1012,10 @@ mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, c
     }
     if (c0.placement == MMC_PLACE_PLAIN) {
         fail(MMC_EUNSUPPORTED, "the plain engine has no batch form");
+        return nullptr;
+    }
+    if (c0.model != MMC_MODEL_HEISENBERG3D) {
+        fail(MMC_EUNSUPPORTED, "batches run the Heisenberg model only");
         return nullptr;
     }
     if (c0.init < MMC_INIT_SPHERE || c0.init > MMC_INIT_MIXED || c0.proposal < MMC_PROPOSAL_SPHERE ||

@@ -133,10 +133,13 @@ double normality_p(const std::vector<double> &x)
 
 }  // namespace mmc
 
-extern "C" int mmc_stats_from_results(const mmc_path_result *res, int n, int L, double T, mmc_stats_t *out)
+namespace mmc {
+
+// Cross-path statistics of n path results of a lattice of N sites.
+int stats_of(const mmc_path_result *res, int n, double N, double T, mmc_stats_t *out)
 {
-    if (!res || !out || n < 1 || L < 1 || !(T > 0)) return MMC_EINVAL;
-    const double N = (double)L * L * L, nd = (double)n;
+    if (!res || !out || n < 1 || !(N > 0) || !(T > 0)) return MMC_EINVAL;
+    const double nd = (double)n;
     std::vector<double> e(n), m(n);
     double se = 0, sm = 0, se2 = 0, sm2 = 0, sm4 = 0, acc = 0;
     for (int i = 0; i < n; ++i) {
@@ -177,6 +180,14 @@ extern "C" int mmc_stats_from_results(const mmc_path_result *res, int n, int L, 
     (void)acc;
     *out = s;
     return MMC_OK;
+}
+
+}  // namespace mmc
+
+extern "C" int mmc_stats_from_results(const mmc_path_result *res, int n, int L, double T, mmc_stats_t *out)
+{
+    if (L < 1) return MMC_EINVAL;
+    return mmc::stats_of(res, n, (double)L * L * L, T, out);
 }
 
 extern "C" int mmc_binder_cumulant(const mmc_path_result *res, int n, double *U, double *se)

@@ -17,13 +17,14 @@ MMC_OK, MMC_EINVAL, MMC_ENOMEM, MMC_EHIP, MMC_ESTATE, MMC_EUNSUPPORTED, MMC_EIO 
 MMC_FP32, MMC_FP64 = 0, 1
 MMC_INIT_SPHERE, MMC_INIT_ANGLES, MMC_INIT_ORDERED, MMC_INIT_MIXED = 0, 1, 2, 3
 MMC_PROPOSAL_SPHERE, MMC_PROPOSAL_ANGLES = 0, 1
+MMC_MODEL_HEISENBERG3D, MMC_MODEL_ISING2D = 0, 1
 MMC_PLACE_AUTO, MMC_PLACE_LDS, MMC_PLACE_HBM, MMC_PLACE_PLAIN, MMC_PLACE_WINDOW = 0, 1, 2, 3, 4
 
 
 class mmc_config(C.Structure):
     _fields_ = [("precision", C.c_int), ("init", C.c_int), ("placement", C.c_int), ("block", C.c_int),
                 ("lanes_per_path", C.c_int), ("renorm_every", C.c_int), ("instance_id", C.c_uint32),
-                ("trace_sweeps", C.c_int), ("async_", C.c_int), ("proposal", C.c_int)]
+                ("trace_sweeps", C.c_int), ("async_", C.c_int), ("proposal", C.c_int), ("model", C.c_int)]
 
 
 class mmc_path_result(C.Structure):
@@ -131,9 +132,10 @@ def _ptr(h):
 
 
 def config(precision=MMC_FP32, init=MMC_INIT_SPHERE, placement=MMC_PLACE_AUTO, block=0, lanes_per_path=0,
-           renorm_every=0, instance_id=0, trace_sweeps=0, async_=0, proposal=MMC_PROPOSAL_SPHERE):
+           renorm_every=0, instance_id=0, trace_sweeps=0, async_=0, proposal=MMC_PROPOSAL_SPHERE,
+           model=MMC_MODEL_HEISENBERG3D):
     return mmc_config(precision, init, placement, block, lanes_per_path, renorm_every, instance_id,
-                      trace_sweeps, async_, proposal)
+                      trace_sweeps, async_, proposal, model)
 
 
 # ---------------------------------------------------------------- same names as the C ABI
@@ -222,8 +224,9 @@ def mmc_trace(ctx, n_paths, trace_sweeps):
     return out
 
 
-def mmc_get_spins(ctx, path, L):
-    out = np.empty((L ** 3, 3))
+def mmc_get_spins(ctx, path, L, dim=3):
+    """[L^dim, 3] spins of one path (dim = 2 for the Ising model: s in the z component)."""
+    out = np.empty((L ** dim, 3))
     _check(lib().mmc_get_spins(ctx, path, out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
     return out
 

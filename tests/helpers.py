@@ -7,13 +7,14 @@ RESULT_KEYS = ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e"
 
 
 def engine_run(L, T, n_paths, n_therm, n_meas, *, J=1.0, seed=1234, fp64=True, placement=0, block=0,
-               lanes=0, init=0, trace=0, instance_id=0, renorm_every=0, spins_of=(), torch_ws=False, proposal=0):
+               lanes=0, init=0, trace=0, instance_id=0, renorm_every=0, spins_of=(), torch_ws=False, proposal=0,
+               model=0):
     """Runs one instance on the GPU engine; returns (results dict, trace or None, {path: spins},
     plan string, ms)."""
     from paper_1305_6758_amd import mmc
     cfg = mmc.config(precision=mmc.MMC_FP64 if fp64 else mmc.MMC_FP32, init=init, placement=placement,
                      block=block, lanes_per_path=lanes, renorm_every=renorm_every, instance_id=instance_id,
-                     trace_sweeps=trace, proposal=proposal)
+                     trace_sweeps=trace, proposal=proposal, model=model)
     ctx = mmc.mmc_create_ex(L, T, J, n_paths, n_therm, n_meas, seed, cfg)
     ws = None
     try:
@@ -22,7 +23,7 @@ def engine_run(L, T, n_paths, n_therm, n_meas, *, J=1.0, seed=1234, fp64=True, p
         mmc.mmc_run(ctx)
         res = mmc.mmc_results(ctx, n_paths)
         tr = mmc.mmc_trace(ctx, n_paths, trace) if trace else None
-        spins = {p: mmc.mmc_get_spins(ctx, p, L) for p in spins_of}
+        spins = {p: mmc.mmc_get_spins(ctx, p, L, 2 if model == 1 else 3) for p in spins_of}
         plan = mmc.mmc_plan(ctx)
         ms = mmc.mmc_last_timing_ms(ctx)
         if ws is not None:
