@@ -52,6 +52,17 @@ UPDATE_OPS_F32 = {
     "v_add_f32": 18, "v_cmp_lt_f32": 1, "v_cndmask_b32": 3,
 }
 SLOTS_PER_UPDATE_F32 = sum(n * VALU_PEAK / OP_RATES[op] for op, n in UPDATE_OPS_F32.items())
+# 2-D Ising update (per site): a quarter of one Philox4x32-10 call (one call serves four
+# sites); the field (3 adds), a = s h (multiply), the threshold index (2) and the
+# always-accept flag (2), the threshold select (4 cndmask) and compare, the flipped spin
+# (cndmask), the accept and magnetisation counts (2 adds), s h on the odd half (1/2 multiply
+# and add).
+UPDATE_OPS_ISING = {
+    "v_mad_u64_u32": 4.5, "v_bitop3_b32": 3.75, "v_xor_b32": 1.0, "v_add_u32": 9.5, "v_mul_lo_u32": 1.5,
+    "v_cndmask_b32": 5.0, "v_cmp_lt_f32": 1.0,
+}
+OP_RATES.update({"v_add_u32": 5.2908e13, "v_mul_lo_u32": 3.4925e13})
+SLOTS_PER_UPDATE_ISING = sum(n * VALU_PEAK / OP_RATES[op] for op, n in UPDATE_OPS_ISING.items())
 # resident FP64 spins the plain engine may hold (its comparison is skipped above this)
 PLAIN_FP64_MAX_BYTES = 64 << 30
 
@@ -141,6 +152,38 @@ def run_batched(instances, steps, warmup):
     return wall, kernel_ms, results, stats, plan
 
 
+def run_single(instance, steps, warmup, placement):
+    """A one-instance workload on the tuned single-instance FP32 engine (spins resident in
+    device memory between launches): every step reruns all sweeps from the random start."""
+    import torch
+    from paper_1305_6758_amd import mmc
+    L, T, p, nt, nm = instance
+    ctx = mmc.mmc_create_ex(L, T, 1.0, p, nt, nm, 1234, mmc.config(precision=mmc.MMC_FP32, placement=placement))
+    kernel_ms = []
+    try:
+        mmc.mmc_tune(ctx)
+        plan = mmc.mmc_plan(ctx)
+        log("plan:", plan)
+        for it in range(warmup + steps):
+            if it == warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            if it:
+                mmc.mmc_reset(ctx)
+            mmc.mmc_run(ctx)
+            stats = [mmc.mmc_stats(ctx)]
+            kms = mmc.mmc_last_timing_ms(ctx)
+            if it >= warmup:
+                kernel_ms.append(kms)
+            log(f"single step {it} ({'warmup' if it < warmup else 'timed'}): kernel {kms:.1f} ms")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        results = [mmc.mmc_results(ctx, p)]
+    finally:
+        mmc.mmc_destroy(ctx)
+    return wall, kernel_ms, results, stats, plan
+
+
 def run_plain_fp64(instances):
     """One pass of the same workload on the plain per-instance FP64 engine."""
     import torch
@@ -163,7 +206,7 @@ def run_plain_fp64(instances):
     return time.perf_counter() - t0, total_ms, results
 
 
-def cpu_baseline(instances, init="sphere", proposal="sphere", trace=False):
+def cpu_baseline(instances, init="sphere", proposal="sphere", trace=False, ising=False):
     """The FP64 CPU oracle as it stands, on the host cores, on a bounded sample of the
     workload: paths of one instance (the second, or the only one), as many per thread as keep
     the sample near 1.5e8 updates per thread (about 15 s); where one path's full sweep count
@@ -173,17 +216,22 @@ def cpu_baseline(instances, init="sphere", proposal="sphere", trace=False):
     threads = O.max_threads()
     idx = 1 if len(instances) > 1 else 0
     L, T, p, nt, nm = instances[idx]
+    N = L * L if ising else L ** 3
     budget = 1.5e8  # updates per thread
-    sweeps = min(nt + nm, max(1, int(budget / L ** 3)))
+    sweeps = min(nt + nm, max(1, int(budget / N)))
     nm_s = round(sweeps * nm / (nt + nm)) if nt + nm else 0
     nt_s = sweeps - nm_s
-    per_path = L ** 3 * sweeps
+    per_path = N * sweeps
     per_thread = max(1, min(3, int(budget / per_path)))
     n = min(p, per_thread * threads)
     log(f"cpu baseline: {n} paths of L={L}, {nt_s}+{nm_s} sweeps on {threads} threads")
     t0 = time.perf_counter()
-    O.run_paths(L, T, n_therm=nt_s, n_meas=nm_s, seed=1234, path_begin=0, path_end=n, instance=idx, n_threads=threads,
-                init=init, proposal=proposal, trace_sweeps=sweeps if trace else 0)
+    if ising:
+        O.ising_run_paths(L, T, n_therm=nt_s, n_meas=nm_s, seed=1234, path_begin=0, path_end=n, instance=idx,
+                          init=init, trace_sweeps=sweeps if trace else 0, n_threads=threads)
+    else:
+        O.run_paths(L, T, n_therm=nt_s, n_meas=nm_s, seed=1234, path_begin=0, path_end=n, instance=idx,
+                    n_threads=threads, init=init, proposal=proposal, trace_sweeps=sweeps if trace else 0)
     dt = time.perf_counter() - t0
     upd = n * per_path
     full = "all " if sweeps == nt + nm else f"the first {sweeps} of the "
@@ -205,17 +253,25 @@ def binder_summary(instances, results):
 
 
 def run_experiment(name, spec, steps):
-    """An experiment of Secs. 3-4 through paper_1305_6758_amd.experiments; returns the JSON line."""
+    """An experiment of Secs. 3-5 or of the 2-D Ising appendix through
+    paper_1305_6758_amd.experiments; returns the JSON line."""
     from paper_1305_6758_amd import experiments as X
-    from paper_1305_6758_amd.workloads import experiment_instances, updates
+    from paper_1305_6758_amd.workloads import experiment_instances, site_count
     instances = experiment_instances(spec)
-    upd = updates(instances)
+    upd = sum(p * site_count(spec, L) * (nt + nm) for (L, T, p, nt, nm) in instances)
+    ising = spec.get("model", 0) == 1 or spec["kind"].startswith("ising")
     walls, kms, out = [], [], None
     for it in range(steps):
         t0 = time.perf_counter()
         if spec["kind"] == "thermalisation":
             out = X.thermalisation(L=spec["L"], T=spec["T"], n_paths=spec["n_paths"], sweeps=spec["sweeps"],
-                                   init=spec["init"], fp64=spec["fp64"])
+                                   init=spec["init"], fp64=spec["fp64"], model=spec.get("model", 0))
+            kms.append(out["kernel_ms"])
+        elif spec["kind"] == "ising_m":
+            out = X.ising_magnetisation(Ls=spec["Ls"], Ts=spec["Ts"], n_paths=spec["n_paths"], sweeps=spec["sweeps"])
+            kms.append(out["kernel_ms"])
+        elif spec["kind"] == "ising_binder":
+            out = X.ising_binder(Ls=spec["Ls"], Ts=spec["Ts"], n_paths=spec["n_paths"], sweeps=spec["sweeps"])
             kms.append(out["kernel_ms"])
         else:
             out = X.distribution_table(L=spec["L"], Ts=spec["Ts"], n_paths=spec["n_paths"], sweeps=spec["sweeps"],
@@ -225,22 +281,23 @@ def run_experiment(name, spec, steps):
         log(f"{name} step {it}: kernels {kms[-1]:.1f} ms, wall {walls[-1]:.2f} s")
     wall, kms_avg = sum(walls) / steps, sum(kms) / steps
     plan = out["plan"] if "plan" in out else out["rows"][0]["plan"]
-    kernel = "k_plain_half" if plan.startswith("plain") else "k_resident<float>"
+    kernel = "k_ising" if ising else ("k_plain_half" if plan.startswith("plain") else "k_resident<float>")
     line = {
         "metric": METRIC, "value": upd / wall, "unit": "spin updates/s", "n_gpus": 1, "steps": steps, "warmup": 0,
         "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if spec["fp64"] else "f32", "data": "synthetic",
+        "dtype": "i8" if ising else ("f64" if spec["fp64"] else "f32"), "data": "synthetic",
         "config": {"workload": name, **{k: v for k, v in spec.items() if k != "fp64"}, "updates_per_step": upd,
                    "seed": 1234, "plan": plan},
         "kernel_updates_per_s": upd / (kms_avg * 1e-3),
         "experiment": {k: v for k, v in out.items() if k not in ("plan",)},
     }
     if not spec["fp64"]:
-        achieved = SLOTS_PER_UPDATE_F32 * upd / (kms_avg * 1e-3)
+        slots = SLOTS_PER_UPDATE_ISING if ising else SLOTS_PER_UPDATE_F32
+        achieved = slots * upd / (kms_avg * 1e-3)
         line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                             "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
-                            "kernel": kernel, "kernel_ms": kms_avg,
-                            "lane_slots_per_update": SLOTS_PER_UPDATE_F32}
+                            "kernel": kernel, "kernel_ms": kms_avg, "lane_slots_per_update": slots,
+                            "ceiling_updates_per_s": VALU_PEAK / slots}
     else:
         # plain FP64 engine: 72 B of algorithmic device-memory traffic per update
         achieved = 72.0 * upd / (kms_avg * 1e-3)
@@ -256,6 +313,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 3; 1 off the default workload)")
     ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default 1; 0 off the default workload)")
     ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--placement", default="auto", choices=["auto", "lds", "hbm", "window"],
+                    help="one-instance workloads: spin placement of the single-instance engine")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     a = ap.parse_args()
@@ -274,7 +333,8 @@ def main():
         line, instances = run_experiment(a.workload, spec, a.steps or 1)
         if not a.skip_cpu:
             line["cpu_baseline"] = cpu_baseline(instances, init=spec["init"], proposal=spec.get("proposal", "sphere"),
-                                                trace=spec["kind"] == "thermalisation")
+                                                trace=spec["kind"] == "thermalisation",
+                                                ising=spec.get("model", 0) == 1 or spec["kind"].startswith("ising"))
         print(json.dumps(line), flush=True)
         return
     default = a.workload == WORKLOAD
@@ -286,14 +346,23 @@ def main():
     instances = WORKLOADS[a.workload]["instances"]
     upd_step = updates(instances)
 
-    wall, kernel_ms, results, stats, plan = run_batched(instances, steps, warmup)
+    from paper_1305_6758_amd import mmc as _m
+    single = len(instances) == 1
+    if single:
+        place = {"auto": _m.MMC_PLACE_AUTO, "lds": _m.MMC_PLACE_LDS, "hbm": _m.MMC_PLACE_HBM,
+                 "window": _m.MMC_PLACE_WINDOW}[a.placement]
+        wall, kernel_ms, results, stats, plan = run_single(instances[0], steps, warmup, place)
+    else:
+        wall, kernel_ms, results, stats, plan = run_batched(instances, steps, warmup)
     value = upd_step * steps / wall
     kms = sum(kernel_ms) / len(kernel_ms)
     achieved = SLOTS_PER_UPDATE_F32 * upd_step / (kms * 1e-3)
     # device-memory variants move 36 B per update (read own 12 B, write 12 B, read the other
     # colour 12 B per half-sweep); when they carry most of the updates the kernel is bound by HBM
-    variants = plan.split(";", 1)[1].split() if ";" in plan else []
+    variants = plan.split(";", 1)[1].split() if ";" in plan else [plan]
     hbm_upd = sum(p * L ** 3 * (nt + nm) for (L, T, p, nt, nm), v in zip(instances, variants) if "-hbm-" in v)
+    kernel_name = "k_batch<float>" if not single else (
+        "k_window<float>" if "-win-" in plan else "k_resident<float>")
 
     golden_path = os.path.join(ROOT, "tests", "golden", f"oracle_{a.workload}.json")
     parity = None
@@ -307,7 +376,7 @@ def main():
               "T": sorted({x[1] for x in instances}), "instances": len(instances),
               "paths": sum(x[2] for x in instances), "n_therm": sorted({x[3] for x in instances}),
               "n_meas": sorted({x[4] for x in instances}), "updates_per_step": upd_step, "seed": 1234,
-              "plan": plan}
+              "plan": plan, "engine": "single-instance, tuned" if single else "batch"}
     out = {
         "metric": METRIC,
         "value": value,
@@ -324,7 +393,7 @@ def main():
         "config": config,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(a.workload),
-                     "kernel": "k_batch<float>", "kernel_ms": kms,
+                     "kernel": kernel_name, "kernel_ms": kms,
                      "lane_slots_per_update": SLOTS_PER_UPDATE_F32,
                      "ceiling_updates_per_s": VALU_PEAK / SLOTS_PER_UPDATE_F32},
         "parity": parity,
@@ -333,7 +402,7 @@ def main():
         gbs = 36.0 * hbm_upd / (kms * 1e-3) / 1e9
         out["roofline_valu"] = out["roofline"]
         out["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-                           "traffic": measured_traffic(a.workload), "kernel": "k_batch<float>", "kernel_ms": kms,
+                           "traffic": measured_traffic(a.workload), "kernel": kernel_name, "kernel_ms": kms,
                            "bytes_per_update": 36, "hbm_updates_per_step": hbm_upd}
     if len(instances) <= 16:
         out["stats"] = [{k: s[k] for k in ("mean_e", "se_e", "mean_absm", "se_absm", "chi", "cv_heat", "binder",

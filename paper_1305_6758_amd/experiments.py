@@ -11,12 +11,16 @@ happens here.
     against the number of sweeps from one traced run, for any start (random, both-angles,
     ordered, or the mixed half-and-half set-up with each half reported separately) (Sec. 4);
   - distribution_table: the distribution coefficient r of the single-output paths' H, M^x,
-    M^y, M^z and |M^z| per temperature (Sec. 3, Table 1), for either proposal.
+    M^y, M^z and |M^z| per temperature (Sec. 3, Table 1), for either proposal;
+  - ising_magnetisation / ising_binder: the appendix's 2-D Ising runs -- the order parameter
+    <|m|> of single-output paths against temperature beside the exact spontaneous
+    magnetisation, and the critical temperature from the cumulant ratio of two lattices.
 
-Usage: python -m paper_1305_6758_amd.experiments {binder,thermalisation,table} [options]
+Usage: python -m paper_1305_6758_amd.experiments {binder,thermalisation,table,ising-m,ising-binder} [options]
 """
 import argparse
 import json
+import math
 import sys
 import time
 
@@ -77,7 +81,7 @@ def doubling_sweeps(n):
 
 
 def thermalisation(L=10, T=1.0, n_paths=1000, sweeps=5000, init="sphere", fp64=False, seed=SEED, instance_id=0,
-                   report=None):
+                   report=None, model=mmc.MMC_MODEL_HEISENBERG3D):
     """One run of n_paths paths through `sweeps` sweeps with every sweep traced. Row k of the
     trace is the output a path would give if it stopped after k + 1 sweeps, so the paper's
     series of simulations with growing sweep counts come from one run. Returns, at the sweep
@@ -85,7 +89,7 @@ def thermalisation(L=10, T=1.0, n_paths=1000, sweeps=5000, init="sphere", fp64=F
     variation of the mean, and <e>, over all paths and -- for the mixed start -- over the
     random-start (even) and ordered-start (odd) halves separately."""
     cfg = mmc.config(precision=mmc.MMC_FP64 if fp64 else mmc.MMC_FP32, init=INITS[init], trace_sweeps=sweeps,
-                     instance_id=instance_id)
+                     instance_id=instance_id, model=model)
     ctx = mmc.mmc_create_ex(L, T, 1.0, n_paths, sweeps, 0, seed, cfg)
     try:
         mmc.mmc_run(ctx)
@@ -98,9 +102,10 @@ def thermalisation(L=10, T=1.0, n_paths=1000, sweeps=5000, init="sphere", fp64=F
     sets = {"all": (0, 1)}
     if init == "mixed":
         sets.update({"random_half": (0, 2), "ordered_half": (1, 2)})
-    out = {"L": L, "T": T, "n_paths": n_paths, "sweeps": sweeps, "init": init,
+    dim = 2 if model == mmc.MMC_MODEL_ISING2D else 3
+    out = {"L": L, "T": T, "n_paths": n_paths, "sweeps": sweeps, "init": init, "model": model,
            "precision": "fp64" if fp64 else "fp32", "plan": plan, "kernel_ms": kernel_ms,
-           "updates_per_s": n_paths * L ** 3 * sweeps / (kernel_ms * 1e-3), "report_sweeps": report}
+           "updates_per_s": n_paths * L ** dim * sweeps / (kernel_ms * 1e-3), "report_sweeps": report}
     for name, (b, st) in sets.items():
         rows = mmc.mmc_trace_stats(trace, b, st)
         out[name] = [{"sweeps": k, "m": rows[k - 1, 0], "se_m": rows[k - 1, 1], "cv_m": rows[k - 1, 2],
@@ -144,9 +149,71 @@ def distribution_table(L=10, Ts=(0.6, 0.8, 1.0, 1.2, 1.4, 1.6), n_paths=10 ** 4,
     return {"L": L, "n_paths": n_paths, "sweeps": sweeps, "proposal": proposal, "init": init, "rows": rows}
 
 
+def onsager_yang(T, J=1.0):
+    """Exact spontaneous magnetisation of the square-lattice Ising model (Onsager; Yang 1952):
+    (1 - sinh(2J/T)^-4)^(1/8) below T_c = 2J/ln(1 + sqrt 2), zero above."""
+    x = 1.0 - math.sinh(2.0 * J / T) ** -4
+    return x ** 0.125 if x > 0 else 0.0
+
+
+def _ising_single_output(L, T, n_paths, sweeps, seed, instance_id):
+    cfg = mmc.config(model=mmc.MMC_MODEL_ISING2D, instance_id=instance_id)
+    ctx = mmc.mmc_create_ex(L, T, 1.0, n_paths, sweeps - 1, 1, seed, cfg)
+    try:
+        mmc.mmc_run(ctx)
+        ms = mmc.mmc_last_timing_ms(ctx)
+        plan = mmc.mmc_plan(ctx)
+        r = mmc.mmc_results(ctx, n_paths)
+    finally:
+        mmc.mmc_destroy(ctx)
+    return r, ms, plan
+
+
+def ising_magnetisation(Ls=(20, 40, 50, 60), Ts=(1.0, 1.5, 2.0, 2.1, 2.2, 2.269, 2.3, 2.4, 2.5, 3.0),
+                        n_paths=10 ** 4, sweeps=3 * 10 ** 4, seed=SEED):
+    """Appendix, Fig. Izing a): n_paths single-output paths per (L, T) from random starts through
+    `sweeps` sweeps; <|m|> of the final states with its standard error, beside the exact
+    spontaneous magnetisation. Instance id = index of (L, T) in L-major order."""
+    rows, total_ms, upd = [], 0.0, 0
+    for a, L in enumerate(Ls):
+        for b, T in enumerate(Ts):
+            r, ms, plan = _ising_single_output(L, T, n_paths, sweeps, seed, a * len(Ts) + b)
+            am = abs(r["final_m"][:, 0])
+            se = float(am.std(ddof=1) / math.sqrt(am.size))
+            rows.append({"L": L, "T": T, "m": float(am.mean()), "se": se, "exact": onsager_yang(T),
+                         "e": float(r["final_e"].mean()), "plan": plan, "kernel_ms": ms})
+            total_ms += ms
+            upd += n_paths * L * L * sweeps
+    return {"n_paths": n_paths, "sweeps": sweeps, "rows": rows, "kernel_ms": total_ms, "updates": upd,
+            "updates_per_s": upd / (total_ms * 1e-3)}
+
+
+def ising_binder(Ls=(60, 50), Ts=(2.264, 2.268), n_paths=5 * 10 ** 4, sweeps=3 * 10 ** 4, seed=SEED):
+    """Appendix: T_c of the square-lattice Ising model from U_L/U_L' = 1 between two
+    temperatures, single-output paths (instance id = index of (L, T) in T-major order, as in
+    binder_crossing)."""
+    cum, total_ms, upd, plans = [], 0.0, 0, []
+    i = 0
+    for T in Ts:
+        for L in Ls:
+            r, ms, plan = _ising_single_output(L, T, n_paths, sweeps, seed, i)
+            U, se = mmc.mmc_binder_cumulant(r)
+            cum.append({"L": L, "T": T, "U": U, "se": se})
+            total_ms += ms
+            upd += n_paths * L * L * sweeps
+            plans.append(plan)
+            i += 1
+    cross = mmc.mmc_cumulant_crossing(Ts[0], Ts[1], [c["U"] for c in cum], [c["se"] for c in cum])
+    return {"Ls": list(Ls), "Ts": list(Ts), "n_paths": n_paths, "sweeps": sweeps, "cumulants": cum,
+            "ratio": [{"T": Ts[0], "R": cross["r_t1"], "se": cross["se_r_t1"]},
+                      {"T": Ts[1], "R": cross["r_t2"], "se": cross["se_r_t2"]}],
+            "tc": cross["tc"], "se_tc": cross["se_tc"], "tc_exact": 2.0 / math.log(1.0 + math.sqrt(2.0)),
+            "plan": " ".join(plans), "kernel_ms": total_ms, "updates": upd, "updates_per_s": upd / (total_ms * 1e-3)}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("experiment", choices=["binder", "thermalisation", "table"])
+    ap.add_argument("experiment", choices=["binder", "thermalisation", "table", "ising-m", "ising-binder"])
     ap.add_argument("--paths", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
     ap.add_argument("--L", type=int, default=10)
@@ -159,9 +226,13 @@ def main(argv=None):
         out = binder_crossing(n_paths=a.paths or 10 ** 6, sweeps=a.sweeps or 200, fp64=a.fp64)
     elif a.experiment == "thermalisation":
         out = thermalisation(L=a.L, T=a.T, n_paths=a.paths or 1000, sweeps=a.sweeps or 5000, init=a.init, fp64=a.fp64)
-    else:
+    elif a.experiment == "table":
         out = distribution_table(L=a.L, n_paths=a.paths or 10 ** 4, sweeps=a.sweeps or 5000, proposal=a.proposal,
                                  init=a.init)
+    elif a.experiment == "ising-m":
+        out = ising_magnetisation(n_paths=a.paths or 10 ** 4, sweeps=a.sweeps or 3 * 10 ** 4)
+    else:
+        out = ising_binder(n_paths=a.paths or 5 * 10 ** 4, sweeps=a.sweeps or 3 * 10 ** 4)
     print(json.dumps(out), flush=True)
     return 0
 

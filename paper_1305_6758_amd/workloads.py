@@ -56,6 +56,7 @@ WORKLOADS["uneven-batch-96-fp32"] = dict(precision="fp32", instances=uneven_batc
 # Experiments of Secs. 3 and 4 run through paper_1305_6758_amd.experiments (single-instance
 # contexts: traced sweeps, or the plain FP64 engine for the both-angles proposal).
 TABLE1_TS = (0.6, 0.8, 1.0, 1.2, 1.4, 1.6)
+ISING_TS = (1.0, 1.5, 2.0, 2.1, 2.2, 2.269, 2.3, 2.4, 2.5, 3.0)
 EXPERIMENTS = {
     # Sec. 4: L = 10, T = 1, 10^4 paths, half from a random start and half ordered, every one of
     # 5000 sweeps traced; <m> and its cv per sweep for each half.
@@ -67,6 +68,17 @@ EXPERIMENTS = {
                                         proposal="sphere", init="sphere", fp64=False),
     "table1-L10-angles-p1e4-fp64": dict(kind="table", L=10, Ts=TABLE1_TS, n_paths=10 ** 4, sweeps=5000,
                                         proposal="angles", init="angles", fp64=True),
+    # Appendix, 2-D Ising model: <|m|> of 10^4 single-output paths after 3 10^4 sweeps for
+    # L = 20, 40, 50, 60 at ten temperatures; T_c from U_60/U_50 at T = 2.264 and 2.268 with
+    # 5 10^4 paths; the thermalisation of <|m|> and its cv at T = 3 and T = 1 (L = 50).
+    "ising-magnetisation-L20-60-p1e4": dict(kind="ising_m", Ls=(20, 40, 50, 60), Ts=ISING_TS, n_paths=10 ** 4,
+                                            sweeps=3 * 10 ** 4, init="sphere", fp64=False),
+    "ising-binder-L60-L50-p5e4": dict(kind="ising_binder", Ls=(60, 50), Ts=(2.264, 2.268), n_paths=5 * 10 ** 4,
+                                      sweeps=3 * 10 ** 4, init="sphere", fp64=False),
+    "ising-thermalisation-L50-T3-p1e4": dict(kind="thermalisation", model=1, L=50, T=3.0, n_paths=10 ** 4,
+                                             sweeps=3000, init="sphere", fp64=False),
+    "ising-thermalisation-L50-T1-p1e4": dict(kind="thermalisation", model=1, L=50, T=1.0, n_paths=10 ** 4,
+                                             sweeps=3000, init="sphere", fp64=False),
 }
 
 
@@ -74,7 +86,16 @@ def experiment_instances(spec):
     """(L, T, n_paths, n_therm, n_meas) per context an experiment runs (instance id = index)."""
     if spec["kind"] == "thermalisation":
         return [(spec["L"], spec["T"], spec["n_paths"], spec["sweeps"], 0)]
+    if spec["kind"] == "ising_m":
+        return [(L, T, spec["n_paths"], spec["sweeps"] - 1, 1) for L in spec["Ls"] for T in spec["Ts"]]
+    if spec["kind"] == "ising_binder":
+        return [(L, T, spec["n_paths"], spec["sweeps"] - 1, 1) for T in spec["Ts"] for L in spec["Ls"]]
     return [(spec["L"], T, spec["n_paths"], spec["sweeps"] - 1, 1) for T in spec["Ts"]]
+
+
+def site_count(spec, L):
+    """Sites of one lattice of side L in an experiment's model."""
+    return L * L if spec.get("model", 0) == 1 or spec["kind"].startswith("ising") else L ** 3
 
 
 def updates(instances):

@@ -91,3 +91,36 @@ def test_ising_rejects_unsupported_configurations():
     with pytest.raises(mmc.MMCError) as e:
         mmc.mmc_batch_create([(10, 2.0, 1.0, 4, 1, 1)], 1, mmc.config(model=ISING))
     assert e.value.code == mmc.MMC_EUNSUPPORTED
+
+
+def test_ising_experiment_drivers_match_oracle():
+    """The appendix drivers (order parameter per (L, T), cumulant crossing, traced
+    thermalisation) on small lattices equal the oracle's statistics of the oracle's paths."""
+    from oracle import stats as S
+    from paper_1305_6758_amd import experiments as X
+    say("case ising magnetisation driver")
+    out = X.ising_magnetisation(Ls=(4, 6), Ts=(2.0, 3.0), n_paths=32, sweeps=20)
+    for i, row in enumerate(out["rows"]):
+        o = ising_oracle(row["L"], row["T"], 32, 19, 1, instance=i)
+        am = np.abs(o["final_m"][:, 0])
+        assert abs(row["m"] - am.mean()) < 1e-15 and abs(row["se"] - am.std(ddof=1) / math.sqrt(32)) < 1e-15
+    say("case ising binder driver")
+    out = X.ising_binder(Ls=(6, 4), Ts=(2.2, 2.4), n_paths=40, sweeps=15)
+    us, ses = [], []
+    for i, c in enumerate(out["cumulants"]):
+        o = ising_oracle(c["L"], c["T"], 40, 14, 1, instance=i)
+        U, se = S.binder_cumulant(o["m2_mean"], o["m4_mean"])
+        assert abs(c["U"] - U) < 1e-13 and abs(c["se"] - se) < 1e-13
+        us.append(U)
+        ses.append(se)
+    Tc, sTc, *_ = S.cumulant_crossing(2.2, 2.4, us, ses)
+    assert abs(out["tc"] - Tc) < 1e-12 and abs(out["se_tc"] - sTc) < 1e-12
+    say("case ising thermalisation driver")
+    out = X.thermalisation(L=8, T=2.5, n_paths=24, sweeps=16, init="mixed", model=ISING, instance_id=2)
+    o = ising_oracle(8, 2.5, 24, 16, 0, init="mixed", trace=16, instance=2)
+    for name, (b, st) in (("all", (0, 1)), ("random_half", (0, 2)), ("ordered_half", (1, 2))):
+        ref = S.trace_statistics(o["trace"], b, st)
+        for row in out[name]:
+            k = row["sweeps"] - 1
+            got = np.array([row["m"], row["se_m"], row["cv_m"], row["e"], row["se_e"]])
+            assert np.max(np.abs(got - ref[k])) < 1e-12, (name, k)
