@@ -79,6 +79,8 @@ struct Variant {
 const Variant *variants(int *count);
 const Variant *ising_variants(int *count);  // 2-D Ising model (spins in LDS)
 size_t ising_variant_lds_bytes(int L);
+size_t ising_spin_bytes(int L);  // bytes of one path's state in device memory
+int ising_row_stride(int L);     // bytes per row: [colour][y][row stride], byte j = x >> 1
 const Variant *batch_variants(int fp64, int *count);  // index = BatchDev::variant value
 size_t variant_lds_bytes(const Variant &v, int L);             // dynamic LDS at side L
 int batch_block();                                      // threads per workgroup in the batch kernel

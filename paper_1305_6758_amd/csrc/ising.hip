@@ -2,19 +2,24 @@
 // model (arXiv:1305.6758, appendix "2D Ising model": the same multipath set-up as the
 // Heisenberg model on an L x L periodic square lattice of spins s = +-1).
 //
-// One path per wave: its L^2 spins live in LDS as bytes, [colour][row y][j] with j = x >> 1,
-// so a path of L = 60 takes 3.6 KB and a workgroup of four waves holds four paths. A wave
-// sweeps its own path alone; the workgroup barrier between half-sweeps only orders each
-// wave's LDS traffic (all four paths run the same number of sweeps).
+// One path per wave: its spins live in LDS as bytes b = (s + 1) / 2, [colour][row y][j] with
+// j = x >> 1, each row padded to RS = 4 ceil((L/2 + 1) / 4) bytes so that the four sites of a
+// quad (j = 4 jq ... 4 jq + 3) form one aligned dword; byte L/2 of a row repeats byte 0 (the
+// periodic x-neighbour of the last site), refreshed after every half-sweep. A workgroup of
+// four waves holds four paths (L = 60: 2 KB each); the workgroup barrier between half-sweeps
+// only orders each wave's LDS traffic.
 //
-// Random numbers: one Philox4x32-10 call serves a quad of four consecutive sites (j = 4 jq
-// ... 4 jq + 3) of a row of one colour: counter (c L Q + y Q + jq, sweep, path,
-// tag | instance << 8) with Q = ceil((L/2) / 4) quads per row; site j takes word j mod 4. The
-// move flips s_i; with a = s_i h_i (h_i the sum of the four neighbours) it is taken iff
-// (w + 1/2) 2^-32 < exp(-2 beta J a). a takes five values, so the host turns the test into an
-// integer comparison w < t[a] with thresholds computed once, which is the same decision as the
-// floating-point test for every word w. Energy and magnetisation are integer sums (every bond
-// joins an even and an odd site: E = -J sum_odd s_i h_i), fused into the half-sweeps.
+// A quad is updated with packed byte arithmetic: the number of up neighbours n of its four
+// sites is the sum of four dwords (the other colour's rows y - 1, y + 1 and the row y shifted
+// by one byte either way; bytes 0..4, no carries); with a = s h = 2i - 4 the threshold index of
+// a site is i = b ? n : 4 - n. Random numbers: one Philox4x32-10 call per quad, counter
+// (c L Q + y Q + jq, sweep, path, tag | instance << 8), Q = ceil((L/2) / 4); site j takes word
+// j mod 4. The move flips s; it is taken iff (w + 1/2) 2^-32 < exp(-2 beta J a). Downhill and
+// level moves always pass; the two uphill energies (4|J| and 8|J|) have integer thresholds
+// computed on the host, so the test is w < t, the same decision as the floating-point test for
+// every word w. Energy and magnetisation are integer sums (every bond joins an even and an odd
+// site: E = -J sum_odd s_i h_i), fused into the half-sweeps through popcounts and byte dot
+// products.
 #include "engine.hpp"
 #include "philox.hpp"
 
@@ -31,48 +36,99 @@ __device__ __forceinline__ int wave_isum(int v)
     return v;
 }
 
-// Metropolis decision for a = s h in {-4, -2, 0, 2, 4}: threshold i = (a + 4) / 2.
-__device__ __forceinline__ bool ising_accept(const InstDev &in, int a, uint32_t w)
+__host__ __device__ constexpr int ising_row_bytes(int L) { return 4 * ((L / 2 + 4) / 4); }
+// One path: both colours' padded rows, and a dword of slack for the next-byte read of a row's
+// last quad.
+__host__ __device__ constexpr int ising_path_bytes(int L) { return (2 * L * ising_row_bytes(L) + 16 + 15) & ~15; }
+
+// Aligned dword access to byte rows (memcpy keeps the byte and dword views of the same bytes
+// well defined; it compiles to one load or store).
+__device__ __forceinline__ uint32_t ld4(const uint8_t *p)
 {
-    const int i = (a + 4) >> 1;
-    const uint32_t t = i == 0 ? in.ithr[0] : i == 1 ? in.ithr[1] : i == 2 ? in.ithr[2] : i == 3 ? in.ithr[3] : in.ithr[4];
-    return ((in.iall >> i) & 1u) || w < t;
+    uint32_t v;
+    __builtin_memcpy(&v, __builtin_assume_aligned(p, 4), 4);
+    return v;
+}
+__device__ __forceinline__ void st4(uint8_t *p, uint32_t v) { __builtin_memcpy(__builtin_assume_aligned(p, 4), &v, 4); }
+
+// Acceptance parameters of a context, in the sign-normalised index i' = (J >= 0 ? i : 4 - i):
+// i' <= 2 are downhill or level (always taken), i' = 3 and 4 are the uphill moves of 4|J| and
+// 8|J| with thresholds ta and tb; all_mask bit i' set means "always" (infinite temperature).
+struct IsingAcc {
+    uint32_t ta, tb, all_mask, jneg;
+};
+
+__device__ __forceinline__ IsingAcc ising_acc(const InstDev &in)
+{
+    IsingAcc a;
+    if (in.J < 0) {
+        a.ta = in.ithr[1];
+        a.tb = in.ithr[0];
+        a.all_mask = 0;
+        for (int i = 0; i < 5; ++i) a.all_mask |= ((in.iall >> i) & 1u) << (4 - i);
+        a.jneg = 0x01010101u;
+    } else {
+        a.ta = in.ithr[3];
+        a.tb = in.ithr[4];
+        a.all_mask = in.iall;
+        a.jneg = 0;
+    }
+    return a;
 }
 
-// Half-sweep c of sweep k over one path (sp: the path's spins in LDS). Adds the final spins to
-// msum and, on the odd colour, s h to esum; accepted moves to nacc.
+// Half-sweep c of sweep k over one path (sp: the path's bytes in LDS). Adds sum s of the
+// updated sites to msum and, on the odd colour, sum s h to esum; accepted moves to nacc.
 template <int LC>
-__device__ __forceinline__ void ising_half(const InstDev &in, int8_t *sp, int L, int c, uint32_t k, uint32_t path,
-                                           int lane, int &msum, int &esum, int &nacc)
+__device__ __forceinline__ void ising_half(const InstDev &in, const IsingAcc &ac, uint8_t *sp, int L, int c,
+                                           uint32_t k, uint32_t path, int lane, int &msum, int &esum, int &nacc)
 {
-    const int HL = L / 2, Q = (HL + 3) / 4, NQ = L * Q;
-    int8_t *own = sp + c * L * HL;
-    const int8_t *oth = sp + (1 - c) * L * HL;
+    const int HL = L / 2, Q = (HL + 3) / 4, NQ = L * Q, RS = ising_row_bytes(LC ? LC : L);
+    uint8_t *own = sp + c * L * RS;
+    const uint8_t *oth = sp + (1 - c) * L * RS;
     for (int q = lane; q < NQ; q += 64) {
-        const int y = q / Q, jq = q - y * Q;
+        const int y = q / Q, jq = q - y * Q, j0 = 4 * jq;
         const Words w = philox4x32_10((uint32_t)(c * NQ + q), k, path, TAG_ISING | in.ctr3, in.key0, in.key1);
-        const uint32_t wu[4] = {w.w0, w.w1, w.w2, w.w3};
         const int p = (y + c) & 1;
         const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
-        int8_t *orow = own + y * HL;
-        const int8_t *r0 = oth + y * HL, *rm = oth + ym * HL, *rp = oth + yp * HL;
+        const uint8_t *r0 = oth + y * RS;
+        const uint32_t o0 = ld4(r0 + j0);
+        // x-neighbours: p = 0 -> (j - 1, j), p = 1 -> (j, j + 1); the byte shifted in is the
+        // other colour's site 4 jq - 1 (L/2 - 1 for the first quad) or 4 jq + 4 (the ghost copy
+        // of site 0 after a row's last site)
+        const uint32_t bx = r0[p ? j0 + 4 : (jq ? j0 - 1 : HL - 1)];
+        const uint32_t xs = p ? ((o0 >> 8) | (bx << 24)) : ((o0 << 8) | bx);
+        const uint32_t n = o0 + xs + ld4(oth + ym * RS + j0) + ld4(oth + yp * RS + j0);
+        uint8_t *orow = own + y * RS + j0;
+        const uint32_t b = ld4(orow);
+        const uint32_t bn = b ^ ac.jneg;
+        const int nv = (LC != 0 && (LC / 2) % 4 == 0) ? 4 : (HL - j0 < 4 ? HL - j0 : 4);
+        const uint32_t vmask = nv == 4 ? 0x01010101u : (0x01010101u & ((1u << (8 * nv)) - 1u));
+        const uint32_t wu[4] = {w.w0, w.w1, w.w2, w.w3};
+        uint32_t flip = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int j = 4 * jq + u;
-            if ((LC != 0 && (LC / 2) % 4 == 0) || j < HL) {
-                const int s = orow[j];
-                const int jm = p ? j : (j == 0 ? HL - 1 : j - 1);
-                const int jp = p ? (j == HL - 1 ? 0 : j + 1) : j;
-                const int h = r0[jm] + r0[jp] + rm[j] + rp[j];
-                const bool acc = ising_accept(in, s * h, wu[u]);
-                const int f = acc ? -s : s;
-                if (acc) orow[j] = (int8_t)f;
-                nacc += acc;
-                msum += f;
-                if (c) esum += f * h;
-            }
+            const uint32_t nu = (n >> (8 * u)) & 0xFFu, bu = (bn >> (8 * u)) & 1u;
+            const uint32_t ip = bu ? nu : 4u - nu;
+            const uint32_t t = ip == 4u ? ac.tb : ac.ta;
+            const uint32_t acc = ((ac.all_mask >> ip) & 1u) | (uint32_t)(wu[u] < t);
+            flip |= acc << (8 * u);
+        }
+        flip &= vmask;
+        const uint32_t b2 = b ^ flip;
+        st4(orow, b2);
+        const uint32_t up = b2 & vmask;
+        const int ups = __builtin_popcount(up);
+        nacc += __builtin_popcount(flip);
+        msum += 2 * ups - nv;
+        if (c) {
+            // sum (2b' - 1)(2n - 4) = 4 sum b'n - 8 sum b' - 2 sum n + 4 nv over the quad's sites
+            const int bn_dot = (int)__builtin_amdgcn_udot4(up, n, 0u, false);
+            const int n_sum = (int)__builtin_amdgcn_udot4(vmask, n, 0u, false);
+            esum += 4 * bn_dot - 8 * ups - 2 * n_sum + 4 * nv;
         }
     }
+    // ghost copies of this colour's first sites (after every row's last site)
+    for (int y = lane; y < L; y += 64) own[y * RS + HL] = own[y * RS];
 }
 
 template <int LC>
@@ -80,42 +136,46 @@ __global__ __launch_bounds__(IS_B) void k_ising(InstDev in, int k0, int k1, int 
 {
     extern __shared__ __align__(16) char smem[];
     const int L = LC ? LC : in.L, HL = L / 2, N = L * L, Q = (HL + 3) / 4, NQ = L * Q;
+    const int RS = ising_row_bytes(L), PB = ising_path_bytes(L);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int pth = blockIdx.x * (IS_B / 64) + wave;
     const uint32_t path = (uint32_t)__builtin_amdgcn_readfirstlane(pth);
     const bool active = pth < in.n_paths;
     double *shacc = reinterpret_cast<double *>(smem) + 16 * wave;
-    const int SPN = (N + 15) & ~15;
-    int8_t *sp = reinterpret_cast<int8_t *>(smem + (IS_B / 64) * 128) + wave * SPN;
-    int8_t *gsp = reinterpret_cast<int8_t *>(in.spins) + (size_t)pth * N;
+    uint8_t *sp = reinterpret_cast<uint8_t *>(smem + (IS_B / 64) * 128) + wave * PB;
+    uint8_t *gsp = reinterpret_cast<uint8_t *>(in.spins) + (size_t)pth * PB;
     const double J = in.J, Nd = (double)N;
+    const IsingAcc ac = ising_acc(in);
 
     if (lane < 16) shacc[lane] = (active && !fresh) ? reinterpret_cast<const double *>(in.acc + pth)[lane] : 0.0;
     if (active) {
         if (fresh) {
-            // random start (counter (quad, 0, path, TAG_ISING_INIT)); ordered: all +1; mixed by path parity
+            // random start (counter (quad, 0, path, TAG_ISING_INIT)): b = 1 iff the word < 2^31;
+            // ordered: all up; mixed by path parity
             const int mode = in.init == INIT_MIXED ? ((path & 1u) ? INIT_ORDERED : INIT_SPHERE) : in.init;
+            for (int i = lane; i < PB / 4; i += 64) st4(sp + 4 * i, 0u);
             for (int q = lane; q < 2 * NQ; q += 64) {
                 const int c = q >= NQ, qq = q - c * NQ, y = qq / Q, jq = qq - y * Q;
                 const Words w = philox4x32_10((uint32_t)q, 0u, path, TAG_ISING_INIT | in.ctr3, in.key0, in.key1);
                 const uint32_t wu[4] = {w.w0, w.w1, w.w2, w.w3};
+                uint32_t v = 0;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = 4 * jq + u;
-                    if (j < HL) sp[c * L * HL + y * HL + j] = (int8_t)(mode == INIT_ORDERED ? 1 : (wu[u] < 0x80000000u ? 1 : -1));
-                }
+                for (int u = 0; u < 4; ++u)
+                    if (4 * jq + u < HL) v |= (uint32_t)(mode == INIT_ORDERED ? 1 : (wu[u] < 0x80000000u ? 1 : 0)) << (8 * u);
+                st4(sp + c * L * RS + y * RS + 4 * jq, v);
             }
+            for (int r = lane; r < 2 * L; r += 64) sp[r * RS + HL] = sp[r * RS];
         } else {
-            for (int i = lane; i < N; i += 64) sp[i] = gsp[i];
+            for (int i = lane; i < PB / 4; i += 64) st4(sp + 4 * i, ld4(gsp + 4 * i));
         }
     }
     __syncthreads();
     int nacc = 0;
     for (int k = k0; k < k1; ++k) {
         int msum = 0, esum = 0;
-        if (active) ising_half<LC>(in, sp, L, 0, (uint32_t)k, path, lane, msum, esum, nacc);
+        if (active) ising_half<LC>(in, ac, sp, L, 0, (uint32_t)k, path, lane, msum, esum, nacc);
         __syncthreads();
-        if (active) ising_half<LC>(in, sp, L, 1, (uint32_t)k, path, lane, msum, esum, nacc);
+        if (active) ising_half<LC>(in, ac, sp, L, 1, (uint32_t)k, path, lane, msum, esum, nacc);
         __syncthreads();
         const bool meas = k >= in.n_therm || k < in.trace_sweeps || k == k1 - 1;
         if (meas && active) {
@@ -149,12 +209,12 @@ __global__ __launch_bounds__(IS_B) void k_ising(InstDev in, int k0, int k1, int 
     if (active) {
         nacc = wave_isum(nacc);
         if (lane == 0) reinterpret_cast<unsigned long long *>(shacc)[9] += (unsigned long long)nacc;
-        for (int i = lane; i < N; i += 64) gsp[i] = sp[i];
+        for (int i = lane; i < PB / 4; i += 64) st4(gsp + 4 * i, ld4(sp + 4 * i));
         if (lane < 16) reinterpret_cast<double *>(in.acc + pth)[lane] = shacc[lane];
     }
 }
 
-size_t ising_lds_bytes(int L) { return (size_t)(IS_B / 64) * (128 + (((size_t)L * L + 15) & ~(size_t)15)); }
+size_t ising_lds_bytes(int L) { return (size_t)(IS_B / 64) * (128 + (size_t)ising_path_bytes(L)); }
 
 template <int LC>
 hipError_t launch_ising(const InstDev &in, int k0, int k1, int fresh, hipStream_t s)
@@ -184,5 +244,8 @@ const Variant *ising_variants(int *count)
 }
 
 size_t ising_variant_lds_bytes(int L) { return ising_lds_bytes(L); }
+
+size_t ising_spin_bytes(int L) { return (size_t)ising_path_bytes(L); }
+int ising_row_stride(int L) { return ising_row_bytes(L); }
 
 }  // namespace mmc

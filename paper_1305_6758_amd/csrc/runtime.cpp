@@ -100,7 +100,7 @@ struct mmc_ctx {
 
 size_t spin_bytes_of(const mmc_ctx *c, int L)
 {
-    if (c->cfg.model == MMC_MODEL_ISING2D) return (size_t)L * L;  // one byte per spin
+    if (c->cfg.model == MMC_MODEL_ISING2D) return mmc::ising_spin_bytes(L);  // padded byte rows
     return 3 * (size_t)L * L * L * (c->fp64 ? 8 : 4);
 }
 
@@ -805,9 +805,10 @@ int mmc_get_spins(const mmc_ctx *c, int path, double *xyz, size_t n_out)
     HIP_TRY(hipStreamSynchronize(c->stream));
     const size_t bytes = spin_bytes_of(c, L);
     if (c->cfg.model == MMC_MODEL_ISING2D) {
-        // [colour][y][x >> 1] bytes; the spin goes to the z component of site x + L y
+        // [colour][y][row stride] bytes b = (s + 1)/2 at x >> 1; s goes to the z component of x + L y
         if (n_out < 3 * (size_t)L * L) return fail(MMC_EINVAL, "spin output needs %zu doubles", 3 * (size_t)L * L);
-        std::vector<int8_t> raw(bytes);
+        const size_t RS = (size_t)mmc::ising_row_stride(L);
+        std::vector<uint8_t> raw(bytes);
         HIP_TRY(hipMemcpy(raw.data(), c->ws + in.off_spins + (size_t)path * bytes, bytes, hipMemcpyDeviceToHost));
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x) {
@@ -815,7 +816,7 @@ int mmc_get_spins(const mmc_ctx *c, int path, double *xyz, size_t n_out)
                 const int colour = (x + y) & 1;
                 xyz[3 * i + 0] = 0.0;
                 xyz[3 * i + 1] = 0.0;
-                xyz[3 * i + 2] = (double)raw[(size_t)colour * L * HL + (size_t)y * HL + (x >> 1)];
+                xyz[3 * i + 2] = 2.0 * raw[(size_t)colour * L * RS + (size_t)y * RS + (x >> 1)] - 1.0;
             }
         return MMC_OK;
     }
