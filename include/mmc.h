@@ -28,7 +28,9 @@
  *     the per-path output of Sec. 2.2.
  *
  * Errors: every call returns a status (mmc_status) or NULL and never aborts; the reason of
- * the last failure on the calling thread is in mmc_last_error(). Contexts are
+ * the last failure on the calling thread is in mmc_last_error(). With the environment
+ * variable MMC_LOG set to a positive number the library reports its kernel choices (plan,
+ * tuning) on stderr. Contexts are
  * thread-compatible: one context must not be used by two threads at once.
  * Ownership: the caller owns every host buffer it passes in; the library owns its contexts
  * and, unless mmc_bind() supplies memory, the device memory they use.
@@ -166,10 +168,13 @@ int mmc_last_status(void);
 size_t mmc_workspace_bytes(const mmc_ctx *ctx);
 
 /* Hands the context caller-owned device memory of at least mmc_workspace_bytes() bytes,
- * 256-byte aligned, and a HIP stream (NULL: the null stream). The memory must outlive
- * the context and must not be used by anyone else meanwhile. Without this call the first
- * run allocates its own memory with hipMalloc and uses the null stream. Only valid before
- * the first run. */
+ * 256-byte aligned, and the caller's HIP stream (NULL: the null stream). The memory must
+ * outlive the context and must not be used by anyone else meanwhile. The library always
+ * launches on a stream of its own (default priority); with a bound stream every run first
+ * waits for the work already queued on it and the bound stream then waits for the run (events
+ * on both sides), so work the caller queues on its stream is ordered with the runs. Without
+ * this call the first run allocates its own memory with hipMalloc and orders against nothing.
+ * Only valid before the first run. */
 int mmc_bind(mmc_ctx *ctx, void *dev_ptr, size_t bytes, void *hip_stream);
 
 /* Chooses the kernel variant (placement, block, lanes per path) by timing every candidate
@@ -201,6 +206,12 @@ int mmc_results(const mmc_ctx *ctx, mmc_path_result *out, int n_out);
  * k < trace_sweeps; rows of sweeps not run yet are NaN. n_out = number of doubles in out,
  * at least n_paths * trace_sweeps * 4. */
 int mmc_trace(const mmc_ctx *ctx, double *out, size_t n_out);
+
+/* Largest | |S_i| - 1 | over every site of every path (Heisenberg model): the drift of the
+ * spin length that FP32 renormalisation bounds; NaN if any spin is NaN. Host computation on
+ * a copy of the spins. MMC_EUNSUPPORTED for batches and the Ising model, MMC_ESTATE before the
+ * first run. */
+int mmc_spin_norm_deviation(const mmc_ctx *ctx, double *max_dev);
 
 /* Copies the current spins of one path as FP64, xyz[3*i + a] for site id i (x fastest). */
 int mmc_get_spins(const mmc_ctx *ctx, int path, double *xyz, size_t n_out);

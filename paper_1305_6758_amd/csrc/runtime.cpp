@@ -27,6 +27,29 @@ namespace {
 thread_local std::string g_last_error;
 thread_local int g_last_status = MMC_OK;
 
+// Diagnostics on stderr when the environment variable MMC_LOG is a positive number.
+int log_level()
+{
+    static int level = -1;
+    if (level < 0) {
+        const char *e = getenv("MMC_LOG");
+        level = e ? atoi(e) : 0;
+        if (level < 0) level = 0;
+    }
+    return level;
+}
+
+void mmc_log(const char *fmt, ...)
+{
+    if (log_level() <= 0) return;
+    va_list ap;
+    va_start(ap, fmt);
+    fprintf(stderr, "[mmc] ");
+    vfprintf(stderr, fmt, ap);
+    fprintf(stderr, "\n");
+    va_end(ap);
+}
+
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -518,6 +541,9 @@ int plan_single(mmc_ctx *c)
     std::vector<int> cand = single_candidates(c, in.L);
     if (cand.empty()) return fail(MMC_EUNSUPPORTED, "no kernel variant for L=%d with this configuration", in.L);
     in.variant = cand[0];
+    int nv;
+    mmc_log("plan L=%d paths=%d: %zu candidate(s), first %s", in.L, in.n_paths, cand.size(),
+            single_table(c, &nv)[in.variant].name);
     return MMC_OK;
 }
 
@@ -671,6 +697,7 @@ int mmc_tune(mmc_ctx *c)
     if (best_ms >= 1e30) return fail(MMC_EHIP, "every tuning candidate failed to launch");
     in.variant = best;
     c->tuned = true;
+    mmc_log("tuned L=%d paths=%d: %s (%.3f ms for %d sweeps)", in.L, in.n_paths, vs[best].name, best_ms, sweeps);
     drop_graphs(c);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = vs[best].name;
@@ -789,6 +816,37 @@ int mmc_trace(const mmc_ctx *c, double *out, size_t n_out)
     if (!c->ws || c->sweeps_done == 0) return fail(MMC_ESTATE, "nothing has run yet");
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(out, c->ws + in.off_trace, need * sizeof(double), hipMemcpyDeviceToHost));
+    return MMC_OK;
+}
+
+int mmc_spin_norm_deviation(const mmc_ctx *c, double *max_dev)
+{
+    if (!c || !max_dev) return fail(MMC_EINVAL, "null argument");
+    if (c->batch) return fail(MMC_EUNSUPPORTED, "no resident spins on a batch");
+    if (c->cfg.model != MMC_MODEL_HEISENBERG3D) return fail(MMC_EUNSUPPORTED, "Ising spins are +-1 by construction");
+    if (!c->ws || c->sweeps_done == 0) return fail(MMC_ESTATE, "nothing has run yet");
+    const Instance &in = c->inst[0];
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const size_t bytes = (size_t)in.n_paths * spin_bytes_of(c, in.L);
+    std::vector<char> raw(bytes);
+    HIP_TRY(hipMemcpy(raw.data(), c->ws + in.off_spins, bytes, hipMemcpyDeviceToHost));
+    // [path][colour][component][N/2]: |S|^2 of site h of colour c gathers three words
+    const size_t HALF = (size_t)in.L * in.L * in.L / 2;
+    double worst = 0.0;
+    for (size_t p = 0; p < (size_t)in.n_paths; ++p)
+        for (size_t col = 0; col < 2; ++col)
+            for (size_t h = 0; h < HALF; ++h) {
+                double r2 = 0.0;
+                for (size_t a = 0; a < 3; ++a) {
+                    const size_t w = ((p * 2 + col) * 3 + a) * HALF + h;
+                    const double v = c->fp64 ? reinterpret_cast<const double *>(raw.data())[w]
+                                             : (double)reinterpret_cast<const float *>(raw.data())[w];
+                    r2 += v * v;
+                }
+                const double d = fabs(sqrt(r2) - 1.0);
+                if (!(d <= worst)) worst = d;  // a NaN spin makes the deviation NaN
+            }
+    *max_dev = worst;
     return MMC_OK;
 }
 

@@ -76,6 +76,7 @@ _SIGNATURES = [
     ("mmc_results", C.c_int, [_P, C.POINTER(mmc_path_result), C.c_int]),
     ("mmc_trace", C.c_int, [_P, C.POINTER(C.c_double), C.c_size_t]),
     ("mmc_get_spins", C.c_int, [_P, C.c_int, C.POINTER(C.c_double), C.c_size_t]),
+    ("mmc_spin_norm_deviation", C.c_int, [_P, C.POINTER(C.c_double)]),
     ("mmc_stats", C.c_int, [_P, C.POINTER(mmc_stats_t)]),
     ("mmc_stats_from_results", C.c_int, [C.POINTER(mmc_path_result), C.c_int, C.c_int, C.c_double,
                                          C.POINTER(mmc_stats_t)]),
@@ -222,6 +223,12 @@ def mmc_trace(ctx, n_paths, trace_sweeps):
     out = np.empty((n_paths, trace_sweeps, 4))
     _check(lib().mmc_trace(ctx, out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
     return out
+
+
+def mmc_spin_norm_deviation(ctx):
+    d = C.c_double()
+    _check(lib().mmc_spin_norm_deviation(ctx, C.byref(d)))
+    return d.value
 
 
 def mmc_get_spins(ctx, path, L, dim=3):

@@ -311,3 +311,34 @@ def test_thermalisation_and_table_drivers_fp64():
             for key, x in (("r_H", o["final_e"]), ("r_Mx", fm[:, 0]), ("r_My", fm[:, 1]), ("r_Mz", fm[:, 2]),
                            ("r_absMz", np.abs(fm[:, 2]))):
                 assert abs(row[key] - S.distribution_coefficient(x)) < 1e-9, (prop, i, key)
+
+
+def test_spin_norm_diagnostic_and_renormalisation(tmp_path):
+    """Failure detection: a spin whose length is corrupted in a checkpoint is flagged by
+    mmc_spin_norm_deviation after loading; FP32 renormalisation at the next boundary repairs
+    it; an untouched run stays within FP32 rounding of unit length."""
+    import ctypes
+    from paper_1305_6758_amd import mmc
+    L, n = 8, 2
+    cfg = mmc.config(precision=mmc.MMC_FP32, renorm_every=4)
+    ctx = mmc.mmc_create_ex(L, 1.2, 1.0, n, 3, 10, 1234, cfg)
+    f = tmp_path / "ck.bin"
+    try:
+        mmc.mmc_run_sweeps(ctx, 3)
+        assert mmc.mmc_spin_norm_deviation(ctx) < 1e-6
+        mmc.mmc_save(ctx, str(f))
+    finally:
+        mmc.mmc_destroy(ctx)
+    raw = bytearray(f.read_bytes())
+    head = 8 + 4 + 8 + 8 + 4 + 4 + 4 + 8 + ctypes.sizeof(mmc.mmc_config) + 4 + 64 + 8
+    x = np.frombuffer(bytes(raw[head:head + 4]), dtype=np.float32)[0]
+    raw[head:head + 4] = np.float32(3.0 * x + 0.5).tobytes()  # site 0 of path 0, x component
+    f.write_bytes(bytes(raw))
+    ctx = mmc.mmc_load(str(f))
+    try:
+        say("case corrupted spin")
+        assert mmc.mmc_spin_norm_deviation(ctx) > 0.1
+        mmc.mmc_run_sweeps(ctx, 2)  # sweeps 3 and 4: renormalisation at the start of sweep 4
+        assert mmc.mmc_spin_norm_deviation(ctx) < 1e-6
+    finally:
+        mmc.mmc_destroy(ctx)
