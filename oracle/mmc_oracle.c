@@ -11,7 +11,7 @@
  *   - Hamiltonian, eq. (ham), Sec. 2.1: H = -(J/2) sum_n sum_lambda S_n . S_{n+lambda},
  *     lambda running over the nearest neighbours, J = 1 fixes the energy scale.
  *   - Spherical parametrisation of unit spins, Sec. 2.1.
- *   - Sec. 2.2: every simulation path (SP) starts from a random ("infinite temperature")
+ *   - Sec. 2.2: every simulation path (SP) starts from a random (infinite-temperature)
  *     state, is swept with single-spin Metropolis moves, and outputs
  *     {M^x, M^y, M^z, H} per lattice site from its final state; a lattice sweep (LS) is
  *     L^3 Metropolis attempts.

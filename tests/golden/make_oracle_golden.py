@@ -2,7 +2,7 @@
 
 Calls only the FP64 CPU oracle (oracle/) and the input recipes; the GPU engine is never
 involved. The full-size parity tests compare the engine's paths with these files, so the
-GPU machine does not rerun hours of oracle work. Paths sampled: the first K of each instance
+parity tests do not rerun hours of oracle work. Paths sampled: the first K of each instance
 (same counter streams on both sides: path index and instance id select the stream).
 
 Usage: python tests/golden/make_oracle_golden.py [workload ...] [--threads N]
