@@ -6,8 +6,9 @@
 // j = x >> 1, each row padded to RS = 4 ceil((L/2 + 1) / 4) bytes so that the four sites of a
 // quad (j = 4 jq ... 4 jq + 3) form one aligned dword; byte L/2 of a row repeats byte 0 (the
 // periodic x-neighbour of the last site), refreshed after every half-sweep. A workgroup of
-// four waves holds four paths (L = 60: 2 KB each); the workgroup barrier between half-sweeps
-// only orders each wave's LDS traffic.
+// four waves holds four paths (L = 60: 3856 bytes each). A wave sweeps its own path alone: the
+// LDS operations of one wave execute in order, so a wave-scope fence (no workgroup barrier)
+// separates its half-sweeps and the four waves run decoupled.
 //
 // A quad is updated with packed byte arithmetic: the number of up neighbours n of its four
 // sites is the sum of four dwords (the other colour's rows y - 1, y + 1 and the row y shifted
@@ -34,6 +35,15 @@ __device__ __forceinline__ int wave_isum(int v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Orders one wave's LDS accesses before its later ones (the hardware keeps a wave's LDS
+// operations in order; the fence keeps the compiler from moving accesses across).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __host__ __device__ constexpr int ising_row_bytes(int L) { return 4 * ((L / 2 + 4) / 4); }
@@ -174,9 +184,9 @@ __global__ __launch_bounds__(IS_B) void k_ising(InstDev in, int k0, int k1, int 
     for (int k = k0; k < k1; ++k) {
         int msum = 0, esum = 0;
         if (active) ising_half<LC>(in, ac, sp, L, 0, (uint32_t)k, path, lane, msum, esum, nacc);
-        __syncthreads();
+        wave_sync();
         if (active) ising_half<LC>(in, ac, sp, L, 1, (uint32_t)k, path, lane, msum, esum, nacc);
-        __syncthreads();
+        wave_sync();
         const bool meas = k >= in.n_therm || k < in.trace_sweeps || k == k1 - 1;
         if (meas && active) {
             msum = wave_isum(msum);

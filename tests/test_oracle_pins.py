@@ -503,3 +503,22 @@ def test_trace_statistics_against_scipy():
     rows = S.trace_statistics(O.run_paths(4, 1.2, n_therm=1, n_meas=0, path_end=30, init="mixed", trace_sweeps=1,
                                           seed=3)["trace"], 1, 2)
     assert rows[0, 0] > 0.9
+
+
+@pytest.mark.parametrize("N,K,sweep", [(4, 1.0, "checkerboard"), (4, 2.0, "checkerboard"), (3, 2.0, "typewriter"),
+                                       (6, 2.0, "random_site")])
+def test_periodic_ring_exact(N, K, sweep):
+    """Periodic classical Heisenberg ring of N spins, solvable at any N: expanding each bond's
+    weight exp(K S.S') in Legendre polynomials with modified spherical Bessel coefficients
+    i_l(K), Z = sum_l (2l + 1) i_l(K)^N and <S_i . S_i+1> = sum_l (2l+1) i_l^(N-1) i_l' / Z.
+    Pins the periodic wrap with the loop it closes (the value differs from the open chain's
+    coth K - 1/K by many standard errors at these N); odd N with a sequential sweep."""
+    from scipy.special import spherical_in
+    l = np.arange(80)
+    i, d = spherical_in(l, K), spherical_in(l, K, derivative=True)
+    exact = ((2 * l + 1) * i ** (N - 1) * d).sum() / ((2 * l + 1) * i ** N).sum()
+    r = O.run_paths(N, 1.0 / K, n_therm=100, n_meas=600, path_end=3000, dim=1, periodic=True, sweep=sweep, seed=31)
+    m, se = S.mean_se(-np.asarray(r["e_mean"]))  # e = -J <S_i . S_i+1> per site, J = 1
+    assert within_4sigma(m, se, exact)
+    if N <= 4:
+        assert abs(exact - langevin(K)) > 10 * se
