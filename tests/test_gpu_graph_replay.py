@@ -1,0 +1,126 @@
+"""Replays of the engine's captured HIP graphs. A context captures its sweep range once and
+launches the same graph executable again after mmc_reset (and a batch on every mmc_batch_run);
+every replay must start from the same zeroed queue head, accumulators and fresh spins. The
+replays here are separated by unrelated device work (torch kernels, a reduction over many
+blocks, another context's run) and host synchronisations, and each replay's per-path results
+must equal the first launch's bit for bit. The first launch itself is checked against the
+oracle where it is exact (FP64, Ising)."""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import assert_results_close, oracle_run
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e", "final_m", "n_accept")
+PLACE_AUTO, PLACE_LDS, PLACE_HBM, PLACE_PLAIN, PLACE_WINDOW = 0, 1, 2, 3, 4
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def eager_work(mmc, rep):
+    """Unrelated device work on torch's stream, then a short run of another context."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(rep)
+    x = torch.randn(1 << 22, device="cuda", generator=g)
+    y = torch.zeros(1 << 20, device="cuda")
+    y.add_(x[: 1 << 20] * x[1 << 20: 2 << 20])
+    s = float(y.sum())  # a reduction over many blocks
+    assert math.isfinite(s)
+    torch.cuda.synchronize()
+    other = mmc.mmc_create_ex(8, 1.1 + 0.1 * rep, 1.0, 3, 2, 2, 99 + rep,
+                              mmc.config(precision=mmc.MMC_FP32, placement=PLACE_LDS, block=256, lanes_per_path=64))
+    try:
+        mmc.mmc_run(other)
+    finally:
+        mmc.mmc_destroy(other)
+
+
+def assert_same(a, b, what):
+    for k in KEYS:
+        x, y = np.asarray(a[k]), np.asarray(b[k])
+        assert np.array_equal(x, y, equal_nan=x.dtype.kind == "f"), (what, k)
+
+
+CASES = [
+    # (L, T, n_paths, n_therm, n_meas, precision, placement, block, lanes, model)
+    (8, 1.3, 5, 3, 4, "fp64", PLACE_LDS, 256, 64, 0),
+    (8, 1.3, 5, 3, 4, "fp64", PLACE_PLAIN, 0, 0, 0),
+    (16, 1.443, 7, 4, 4, "fp32", PLACE_LDS, 512, 512, 0),
+    (20, 1.2, 3, 2, 3, "fp32", PLACE_HBM, 512, 512, 0),
+    (24, 1.5, 3, 3, 3, "fp32", PLACE_WINDOW, 0, 0, 0),
+    (20, 2.3, 6, 5, 5, "ising", PLACE_AUTO, 0, 0, 1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"L{c[0]}-{c[5]}-place{c[6]}")
+def test_single_instance_graph_replays(case):
+    from paper_1305_6758_amd import mmc
+    L, T, n, nt, nm, prec, pl, b, g, model = case
+    say("case replay", case)
+    cfg = mmc.config(precision=mmc.MMC_FP32 if prec == "fp32" else mmc.MMC_FP64, placement=pl, block=b,
+                     lanes_per_path=g, model=model)
+    ctx = mmc.mmc_create_ex(L, T, 1.0, n, nt, nm, 1234, cfg)
+    try:
+        mmc.mmc_run(ctx)
+        first = mmc.mmc_results(ctx, n)
+        spins = [mmc.mmc_get_spins(ctx, p, L, 2 if model == 1 else 3) for p in range(n)]
+        say("plan", mmc.mmc_plan(ctx))
+        for rep in range(3):
+            eager_work(mmc, rep)
+            mmc.mmc_reset(ctx)
+            mmc.mmc_run(ctx)
+            assert_same(mmc.mmc_results(ctx, n), first, f"replay {rep}")
+        # a split run captures other graphs; afterwards the full-range graph still replays
+        mmc.mmc_reset(ctx)
+        mmc.mmc_run_sweeps(ctx, 2)
+        mmc.mmc_run_sweeps(ctx, nt + nm - 2)
+        split = mmc.mmc_results(ctx, n)
+        if pl == PLACE_WINDOW and prec == "fp32":
+            # the window kernel deals a pass's stages to waves by the pass length, so other pass
+            # boundaries sum the FP32 measurement partials in another order; the trajectory
+            # (accept counts, spins) is unchanged
+            assert np.array_equal(split["n_accept"], first["n_accept"])
+            assert all(np.array_equal(mmc.mmc_get_spins(ctx, p, L), spins[p]) for p in range(n))
+            for k in ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e", "final_m"):
+                assert np.max(np.abs(split[k] - first[k])) < 1e-5, k
+        else:
+            assert_same(split, first, "split run")
+        eager_work(mmc, 7)
+        mmc.mmc_reset(ctx)
+        mmc.mmc_run(ctx)
+        assert_same(mmc.mmc_results(ctx, n), first, "replay after split")
+        for p in range(n):
+            assert np.array_equal(mmc.mmc_get_spins(ctx, p, L, 2 if model == 1 else 3), spins[p]), p
+    finally:
+        mmc.mmc_destroy(ctx)
+    if model == 1:
+        ora = O.ising_run_paths(L, T, n_therm=nt, n_meas=nm, seed=1234, path_end=n)
+        assert np.array_equal(first["n_accept"], ora["n_accept"])
+        assert np.max(np.abs(first["e_mean"] - ora["e_mean"])) <= 1e-15
+    elif prec == "fp64":
+        assert_results_close(first, oracle_run(L, T, n, nt, nm), 1e-12)
+
+
+def test_batch_graph_replays():
+    """An uneven FP32 batch: the work-queue head is cleared by a fill kernel inside the graph,
+    so each replay hands out the same items from the start."""
+    from paper_1305_6758_amd import mmc
+    insts = [(8, 1.5, 1.0, 9, 3, 3), (16, 1.443, 1.0, 3, 2, 4), (12, 2.0, 1.0, 4, 4, 2), (6, 0.9, -1.0, 5, 2, 2)]
+    say("case batch replay")
+    ctx = mmc.mmc_batch_create(insts, 1234, mmc.config(precision=mmc.MMC_FP32))
+    try:
+        mmc.mmc_batch_run(ctx)
+        first = [mmc.mmc_batch_results(ctx, i, x[3]) for i, x in enumerate(insts)]
+        for rep in range(3):
+            eager_work(mmc, rep)
+            mmc.mmc_batch_run(ctx)
+            for i, x in enumerate(insts):
+                assert_same(mmc.mmc_batch_results(ctx, i, x[3]), first[i], f"replay {rep} instance {i}")
+    finally:
+        mmc.mmc_destroy(ctx)
