@@ -152,15 +152,18 @@ def run_batched(instances, steps, warmup):
     return wall, kernel_ms, results, stats, plan
 
 
-def run_single(instance, steps, warmup, placement):
-    """A one-instance workload on the tuned single-instance FP32 engine (spins resident in
-    device memory between launches): every step reruns all sweeps from the random start."""
+def run_single(instance, steps, warmup, placement, variant=None):
+    """A one-instance workload on the tuned (or pinned) single-instance FP32 engine (spins
+    resident in device memory between launches): every step reruns all sweeps from the random
+    start."""
     import torch
     from paper_1305_6758_amd import mmc
     L, T, p, nt, nm = instance
     ctx = mmc.mmc_create_ex(L, T, 1.0, p, nt, nm, 1234, mmc.config(precision=mmc.MMC_FP32, placement=placement))
     kernel_ms = []
     try:
+        if variant:
+            mmc.mmc_set_variant(ctx, variant)
         mmc.mmc_tune(ctx)
         plan = mmc.mmc_plan(ctx)
         log("plan:", plan)
@@ -315,6 +318,8 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--placement", default="auto", choices=["auto", "lds", "hbm", "window"],
                     help="one-instance workloads: spin placement of the single-instance engine")
+    ap.add_argument("--variant", default=None,
+                    help="one-instance workloads: pin the kernel variant by name instead of tuning")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     a = ap.parse_args()
@@ -348,10 +353,13 @@ def main():
 
     from paper_1305_6758_amd import mmc as _m
     single = len(instances) == 1
+    if a.variant and not single:
+        print("--variant applies to one-instance workloads only", file=sys.stderr)
+        sys.exit(2)
     if single:
         place = {"auto": _m.MMC_PLACE_AUTO, "lds": _m.MMC_PLACE_LDS, "hbm": _m.MMC_PLACE_HBM,
                  "window": _m.MMC_PLACE_WINDOW}[a.placement]
-        wall, kernel_ms, results, stats, plan = run_single(instances[0], steps, warmup, place)
+        wall, kernel_ms, results, stats, plan = run_single(instances[0], steps, warmup, place, a.variant)
     else:
         wall, kernel_ms, results, stats, plan = run_batched(instances, steps, warmup)
     value = upd_step * steps / wall
@@ -362,7 +370,7 @@ def main():
     variants = plan.split(";", 1)[1].split() if ";" in plan else [plan]
     hbm_upd = sum(p * L ** 3 * (nt + nm) for (L, T, p, nt, nm), v in zip(instances, variants) if "-hbm-" in v)
     kernel_name = "k_batch<float>" if not single else (
-        "k_window<float>" if "-win-" in plan else "k_resident<float>")
+        "k_window<float>" if "win-" in plan else "k_resident<float>")
 
     golden_path = os.path.join(ROOT, "tests", "golden", f"oracle_{a.workload}.json")
     parity = None

@@ -88,8 +88,10 @@ typedef enum { MMC_MODEL_HEISENBERG3D = 0, MMC_MODEL_ISING2D = 1 } mmc_model;
 /* Where a path's spins live during a sweep. LDS: the whole lattice of one path in the
  * workgroup's LDS. HBM: spins in device memory, one workgroup per path, sweeps inside
  * one launch. WINDOW: spins in device memory, each workgroup (one path) running several
- * sweeps per pass through a sliding window of z-planes in LDS (compiled for L = 24, 30, 32
- * in FP32 and 12, 16 in FP64). PLAIN: the plain FP64 engine, one launch per half-sweep and
+ * sweeps per pass, the half-sweeps pipelined over z-planes: either through a sliding window
+ * of planes in LDS (compiled for L = 24, 30, 32 in FP32 and 12, 16 in FP64) or with every
+ * plane left in device memory and reused through the caches (L = 32, 48, 64 in FP32; 16, 24
+ * in FP64). PLAIN: the plain FP64 engine, one launch per half-sweep and
  * one thread per site (FP64 only). AUTO: the tuner decides. */
 typedef enum {
     MMC_PLACE_AUTO = 0,
@@ -182,6 +184,15 @@ int mmc_bind(mmc_ctx *ctx, void *dev_ptr, size_t bytes, void *hip_stream);
  * the JSON file named by the environment variable MMC_TUNE_CACHE if set) has an entry.
  * Called by the first run when needed; leaves the context in its initial state. */
 int mmc_tune(mmc_ctx *ctx);
+
+/* Pins the kernel variant of a single-instance context by the name mmc_plan reports, in
+ * place of the tuner's choice. Spins and accept counts are the same under every variant;
+ * FP32 per-path sums follow the variant's reduction order, so a pinned variant reproduces
+ * them bit for bit whatever the tuner would pick on another machine. Only valid before the
+ * first run. MMC_EINVAL: NULL argument, unknown name, or a variant that does not fit this
+ * context (its L, precision, placement, block, lanes and the device's LDS);
+ * MMC_EUNSUPPORTED: a batch context or the plain engine; MMC_ESTATE: the context has run. */
+int mmc_set_variant(mmc_ctx *ctx, const char *name);
 
 /* Runs all remaining sweeps (from the initial random state on the first call). The HIP
  * work of one run is one captured hipGraph launch. Blocks until done unless cfg.async. */

@@ -717,9 +717,9 @@ hipError_t launch_resident(const InstDev &in, int k0, int k1, int fresh, hipStre
 // Renormalisation boundaries (FP32) always start a pass: the pass normalises every site
 // when it first loads its plane, as the resident kernels do at the start of that sweep.
 template <typename T>
-__host__ __device__ constexpr size_t win_lds_bytes(int L, int B, int D)
+__host__ __device__ constexpr size_t win_lds_bytes(int L, int B, int D, bool gm = false)
 {
-    return (size_t)(4 * D + 4) * 3 * (size_t)L * L * sizeof(T) + 128 + (size_t)D * (B / 64) * 16 * sizeof(T);
+    return (gm ? 0 : (size_t)(4 * D + 4) * 3 * (size_t)L * L * sizeof(T)) + 128 + (size_t)D * (B / 64) * 16 * sizeof(T);
 }
 
 __device__ __forceinline__ int wrap_mod(int v, int n)
@@ -849,11 +849,12 @@ __device__ __forceinline__ void flush_partials(T *red, int d, bool meas, int wav
 // Sweeps [k0, k1) of one path (the whole workgroup, B lanes) with spins in device memory
 // (g.sp). win: LDS window of 4D + 4 plane slots; red: LDS [D][B/64 waves][4 rows][4]
 // measurement partials.
-template <typename T, int LC, int B, int D>
+template <typename T, int LC, int B, int D, bool GM>
 __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const InstDev &in, int k0, int k1, bool fresh,
                                                 T *win, T *red)
 {
     constexpr int L = LC, HL = L / 2, PLANE = L * L / 2, SLOT = 6 * PLANE, NW = 4 * D + 4, W = B / 64;
+    constexpr int HALF = L * PLANE;
     static_assert(L > 4 * D + 4, "the two copies of a plane must not meet in the window");
     const double Nd = (double)L * L * L;
     const int n_therm = in.n_therm, trace_sweeps = in.trace_sweeps, renorm_every = in.renorm_every;
@@ -886,7 +887,12 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
         T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);  // this wave's partials of sweep acc_d
         int acc_d = -1;
         bool acc_meas = false;
-        if (g.active) {
+        if constexpr (GM) {
+            // planes stay in device memory: normalise the whole lattice before the pass
+            if constexpr (std::is_same<T, float>::value) {
+                if (rn && g.active) renorm_path<B>(g.sp, L, tid);
+            }
+        } else if (g.active) {
 #pragma unroll 1
             for (int v = -1; v <= 2; ++v) {
                 PlaneRegs<T, LC, B> r;
@@ -900,12 +906,13 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
         for (int tau = 0; tau <= tau_end; ++tau) {
             // the plane whose last use was the previous step goes back to device memory
             const int vout = tau - 2 * NST;
-            if (vout >= 0 && g.active) plane_writeback<T, LC, B>(win + wrap_mod(vout, NW) * SLOT, g.sp, wrap_mod(vout, L), tid);
+            if (!GM && vout >= 0 && g.active)
+                plane_writeback<T, LC, B>(win + wrap_mod(vout, NW) * SLOT, g.sp, wrap_mod(vout, L), tid);
             // prefetch of the plane first used four steps later (stored into the window next step)
             const int vin = tau + 3, vnext = tau + 4;
-            const bool have_in = vin <= vhi && g.active;
+            const bool have_in = !GM && vin <= vhi && g.active;
             PlaneRegs<T, LC, B> nxt;
-            if (vnext <= vhi && g.active) plane_load<T, LC, B>(nxt, g.sp, wrap_mod(vnext, L), tid, rn && vnext < L);
+            if (!GM && vnext <= vhi && g.active) plane_load<T, LC, B>(nxt, g.sp, wrap_mod(vnext, L), tid, rn && vnext < L);
             // a sweep whose odd stage ended two steps ago is complete (its partials reached the
             // LDS slots at the start of the previous step): its measurement
             const int jf = tau - 2 - (L - 1);
@@ -970,10 +977,24 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
             const int v = tau - 2 * stage, c = stage & 1, d = stage >> 1;
             const int k = ks + d;
             const int zp = wrap_mod(v, L);
-            const int sv = wrap_mod(v, NW);
-            const int dm = (wrap_mod(v - 1, NW) - sv) * SLOT, dp = (wrap_mod(v + 1, NW) - sv) * SLOT;
-            T *own = win + sv * SLOT + c * 3 * PLANE;
-            const T *oth = win + sv * SLOT + (1 - c) * 3 * PLANE;
+            // own / oth: this plane's spins of each colour; component stride CS; dm / dp: the
+            // offsets of the z-1 / z+1 planes (window slots, or device-memory planes)
+            constexpr int CS = GM ? HALF : PLANE;
+            int dm, dp;
+            T *own;
+            const T *oth;
+            if constexpr (GM) {
+                dm = (wrap_mod(v - 1, L) - zp) * PLANE;
+                dp = (wrap_mod(v + 1, L) - zp) * PLANE;
+                own = g.sp + c * 3 * HALF + zp * PLANE;
+                oth = g.sp + (1 - c) * 3 * HALF + zp * PLANE;
+            } else {
+                const int sv = wrap_mod(v, NW);
+                dm = (wrap_mod(v - 1, NW) - sv) * SLOT;
+                dp = (wrap_mod(v + 1, NW) - sv) * SLOT;
+                own = win + sv * SLOT + c * 3 * PLANE;
+                oth = win + sv * SLOT + (1 - c) * 3 * PLANE;
+            }
             if (g.active) {
 #pragma unroll 2
                 for (int s = rank * 64 + wl; s < PLANE; s += nw * 64) {
@@ -988,11 +1009,11 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
                     st.nb[3] = s + (y == L - 1 ? -(L - 1) * HL : HL);
                     st.nb[4] = s + dm;
                     st.nb[5] = s + dp;
-                    update_site<T>(g, own, oth, PLANE, c != 0, st, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+                    update_site<T>(g, own, oth, CS, c != 0, st, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
                 }
             }
             if (have_in) plane_to_lds<T, LC, B>(cur, win + wrap_mod(vin, NW) * SLOT, tid);
-            cur = nxt;
+            if constexpr (!GM) cur = nxt;
             __syncthreads();
         }
         // the last sweep's measurement (the loop reaches the completion step of every other
@@ -1041,7 +1062,7 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
                 }
             }
         }
-        if (g.active) {
+        if (!GM && g.active) {
 #pragma unroll 1
             for (int v = tau_end + 1 - 2 * NST; v <= L + NST - 2; ++v)
                 plane_writeback<T, LC, B>(win + wrap_mod(v, NW) * SLOT, g.sp, wrap_mod(v, L), tid);
@@ -1053,11 +1074,12 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
     __syncthreads();
 }
 
-// One path per workgroup (B lanes), spins in device memory at gsp, window in LDS.
-template <typename T, int LC, int B, int D>
+// One path per workgroup (B lanes), spins in device memory at gsp, window in LDS (GM: the
+// planes stay in device memory, LDS holds only the measurement partials).
+template <typename T, int LC, int B, int D, bool GM>
 __device__ __forceinline__ void wg_run_win(const InstDev &in, int path, int k0, int k1, bool fresh, char *smem, T *gsp)
 {
-    constexpr int NW = 4 * D + 4;
+    constexpr int NW = GM ? 0 : 4 * D + 4;
     GroupCtx<T> g;
     g.L = in.L;
     g.lane = threadIdx.x;
@@ -1073,33 +1095,34 @@ __device__ __forceinline__ void wg_run_win(const InstDev &in, int path, int k0, 
     g.red = red;
     g.sp = gsp;
     load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
-    path_sweeps_win<T, LC, B, D>(g, in, k0, k1, fresh, win, red);
+    path_sweeps_win<T, LC, B, D, GM>(g, in, k0, k1, fresh, win, red);
     store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
 }
 
-template <typename T, int B, int D>
+template <typename T, int B, int D, bool GM>
 constexpr int win_waves(int L)
 {
-    const int wgs = (int)((size_t)160 * 1024 / win_lds_bytes<T>(L, B, D));
-    const int w = (wgs < 1 ? 1 : wgs) * (B / 64) / 4, cap = sizeof(T) == 8 ? 2 : 8;
+    const int wgs = (int)((size_t)160 * 1024 / win_lds_bytes<T>(L, B, D, GM));
+    const int cap = sizeof(T) == 8 ? 2 : (GM ? 4 : 8);
+    const int w = (wgs < 1 ? 1 : wgs) * (B / 64) / 4;
     return w < 1 ? 1 : (w > cap ? cap : w);
 }
 
-template <typename T, int LC, int B, int D>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(win_waves<T, B, D>(LC))))
+template <typename T, int LC, int B, int D, bool GM>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(win_waves<T, B, D, GM>(LC))))
 void k_window(InstDev in, int k0, int k1, int fresh)
 {
     extern __shared__ __align__(16) char smem[];
     const int path = blockIdx.x;
-    wg_run_win<T, LC, B, D>(in, path, k0, k1, fresh != 0, smem,
-                            reinterpret_cast<T *>(in.spins) + (size_t)path * 3 * LC * LC * LC);
+    wg_run_win<T, LC, B, D, GM>(in, path, k0, k1, fresh != 0, smem,
+                                reinterpret_cast<T *>(in.spins) + (size_t)path * 3 * LC * LC * LC);
 }
 
-template <typename T, int LC, int B, int D>
+template <typename T, int LC, int B, int D, bool GM>
 hipError_t launch_window(const InstDev &in, int k0, int k1, int fresh, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_window<T, LC, B, D>), dim3(in.n_paths), dim3(B), win_lds_bytes<T>(LC, B, D), s, in, k0, k1,
-                       fresh);
+    hipLaunchKernelGGL((k_window<T, LC, B, D, GM>), dim3(in.n_paths), dim3(B), win_lds_bytes<T>(LC, B, D, GM), s, in,
+                       k0, k1, fresh);
     return hipGetLastError();
 }
 
@@ -1325,9 +1348,9 @@ __global__ void k_set_int(int *p, int v) { *p = v; }
             (LC ? lds_layout_bytes<TT>(LC, B, G, LDS) : 0), &launch_resident<TT, LC, G, B, MAP, LDS>,           \
             (const void *)&k_resident<TT, LC, G, B, MAP, LDS>, 0},
 
-#define MMC_WIN(TT, LC, B, D, NAME)                                                                   \
-    Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, 0, B, B, win_lds_bytes<TT>(LC, B, D),          \
-            &launch_window<TT, LC, B, D>, (const void *)&k_window<TT, LC, B, D>, D},
+#define MMC_WIN(TT, LC, B, D, GM, NAME)                                                               \
+    Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, 0, B, B, win_lds_bytes<TT>(LC, B, D, GM),      \
+            &launch_window<TT, LC, B, D, GM>, (const void *)&k_window<TT, LC, B, D, GM>, D},
 
 static const Variant k_variants[] = {
     // FP32, spins in LDS
@@ -1349,11 +1372,16 @@ static const Variant k_variants[] = {
     MMC_RES(float, 64, 1024, 1024, COLZ, false, "f32-hbm-L64-g1024-b1024")
     MMC_RES(float, 0, 512, 512, FLAT, false, "f32-hbm-any-g512-b512")
     // FP32, spins in device memory, z-pipelined window in LDS
-    MMC_WIN(float, 24, 512, 2, "f32-win-L24-d2-b512")
-    MMC_WIN(float, 24, 1024, 3, "f32-win-L24-d3-b1024")
-    MMC_WIN(float, 30, 1024, 2, "f32-win-L30-d2-b1024")
-    MMC_WIN(float, 32, 512, 2, "f32-win-L32-d2-b512")
-    MMC_WIN(float, 32, 1024, 2, "f32-win-L32-d2-b1024")
+    MMC_WIN(float, 24, 512, 2, false, "f32-win-L24-d2-b512")
+    MMC_WIN(float, 24, 1024, 3, false, "f32-win-L24-d3-b1024")
+    MMC_WIN(float, 30, 1024, 2, false, "f32-win-L30-d2-b1024")
+    MMC_WIN(float, 32, 512, 2, false, "f32-win-L32-d2-b512")
+    MMC_WIN(float, 32, 1024, 2, false, "f32-win-L32-d2-b1024")
+    // FP32, spins in device memory, z-pipelined schedule with every plane in device memory
+    // (reuse through the caches)
+    MMC_WIN(float, 32, 1024, 2, true, "f32-gwin-L32-d2-b1024")
+    MMC_WIN(float, 48, 1024, 1, true, "f32-gwin-L48-d1-b1024")
+    MMC_WIN(float, 64, 1024, 1, true, "f32-gwin-L64-d1-b1024")
     // FP64, spins in LDS
     MMC_RES(double, 8, 64, 256, COLZ, true, "f64-lds-L8-g64-b256")
     MMC_RES(double, 8, 256, 256, COLZ, true, "f64-lds-L8-g256-b256")
@@ -1366,8 +1394,10 @@ static const Variant k_variants[] = {
     MMC_RES(double, 64, 1024, 1024, COLZ, false, "f64-hbm-L64-g1024-b1024")
     MMC_RES(double, 0, 512, 512, FLAT, false, "f64-hbm-any-g512-b512")
     // FP64, window (small lattices: parity of the pipelined schedule with the oracle)
-    MMC_WIN(double, 12, 256, 1, "f64-win-L12-d1-b256")
-    MMC_WIN(double, 16, 256, 2, "f64-win-L16-d2-b256")
+    MMC_WIN(double, 12, 256, 1, false, "f64-win-L12-d1-b256")
+    MMC_WIN(double, 16, 256, 2, false, "f64-win-L16-d2-b256")
+    MMC_WIN(double, 16, 256, 2, true, "f64-gwin-L16-d2-b256")
+    MMC_WIN(double, 24, 512, 3, true, "f64-gwin-L24-d3-b512")
 };
 #undef MMC_RES
 #undef MMC_WIN

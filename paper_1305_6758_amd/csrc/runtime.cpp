@@ -705,6 +705,28 @@ int mmc_tune(mmc_ctx *c)
     return MMC_OK;
 }
 
+int mmc_set_variant(mmc_ctx *c, const char *name)
+{
+    if (!c || !name) return fail(MMC_EINVAL, "null argument");
+    if (c->batch) return fail(MMC_EUNSUPPORTED, "mmc_set_variant is for single-instance contexts");
+    if (c->sweeps_done) return fail(MMC_ESTATE, "the context has already run");
+    int rc = prepare(c);
+    if (rc) return rc;
+    Instance &in = c->inst[0];
+    if (in.plain) return fail(MMC_EUNSUPPORTED, "the plain engine has no kernel variants");
+    int n;
+    const mmc::Variant *vs = single_table(c, &n);
+    for (int i : single_candidates(c, in.L))
+        if (strcmp(vs[i].name, name) == 0) {
+            in.variant = i;
+            c->tuned = true;
+            drop_graphs(c);
+            mmc_log("variant pinned: %s", name);
+            return MMC_OK;
+        }
+    return fail(MMC_EINVAL, "variant '%s' does not fit this context (L=%d)", name, in.L);
+}
+
 static int run_to(mmc_ctx *c, int k_end, bool wait)
 {
     int rc = prepare(c);

@@ -68,6 +68,7 @@ _SIGNATURES = [
     ("mmc_workspace_bytes", C.c_size_t, [_P]),
     ("mmc_bind", C.c_int, [_P, _P, C.c_size_t, _P]),
     ("mmc_tune", C.c_int, [_P]),
+    ("mmc_set_variant", C.c_int, [_P, C.c_char_p]),
     ("mmc_run", C.c_int, [_P]),
     ("mmc_run_sweeps", C.c_int, [_P, C.c_int]),
     ("mmc_sync", C.c_int, [_P]),
@@ -166,6 +167,10 @@ def mmc_bind(ctx, dev_ptr, nbytes, stream_handle):
 
 def mmc_tune(ctx):
     return _check(lib().mmc_tune(ctx))
+
+
+def mmc_set_variant(ctx, name):
+    return _check(lib().mmc_set_variant(ctx, name.encode()))
 
 
 def mmc_run(ctx):

@@ -8,7 +8,7 @@ RESULT_KEYS = ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e"
 
 def engine_run(L, T, n_paths, n_therm, n_meas, *, J=1.0, seed=1234, fp64=True, placement=0, block=0,
                lanes=0, init=0, trace=0, instance_id=0, renorm_every=0, spins_of=(), torch_ws=False, proposal=0,
-               model=0):
+               model=0, variant=None):
     """Runs one instance on the GPU engine; returns (results dict, trace or None, {path: spins},
     plan string, ms)."""
     from paper_1305_6758_amd import mmc
@@ -20,6 +20,8 @@ def engine_run(L, T, n_paths, n_therm, n_meas, *, J=1.0, seed=1234, fp64=True, p
     try:
         if torch_ws:
             ws = mmc.Workspace(ctx)
+        if variant is not None:
+            mmc.mmc_set_variant(ctx, variant)
         mmc.mmc_run(ctx)
         res = mmc.mmc_results(ctx, n_paths)
         tr = mmc.mmc_trace(ctx, n_paths, trace) if trace else None

@@ -1,10 +1,11 @@
-"""Parity of the z-pipelined window kernels (spins in device memory, several sweeps per pass
-through a sliding window of z-planes in LDS).
+"""Parity of the z-pipelined window kernels (spins in device memory, several sweeps per pass,
+the half-sweeps of a pass pipelined over z-planes), in both forms: planes staged through a
+sliding window in LDS ("win"), and planes left in device memory ("gwin").
 
-  - FP64 (L = 12, 16): trajectories, traces, accept counts and final spins match the oracle
-    to 1e-12 -- odd sweep counts (a last pass shorter than the others), every start, runs
-    split at arbitrary sweeps and a nonzero instance id;
-  - FP32 (L = 24, 30, 32): final spins and accept counts equal those of the device-memory
+  - FP64 (L = 12, 16, 24): trajectories, traces, accept counts and final spins match the
+    oracle to 1e-12 -- odd sweep counts (a last pass shorter than the others), every start,
+    runs split at arbitrary sweeps and a nonzero instance id;
+  - FP32 (L = 24 ... 64): final spins and accept counts equal those of the device-memory
     kernels bit for bit (same per-site arithmetic and neighbour values, renormalisation
     boundaries included), energies and magnetisations to FP32 rounding of the sums.
 """
@@ -23,29 +24,37 @@ def say(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("L", [12, 16])
-def test_window_fp64_matches_oracle(L):
+FP64_VARIANTS = [(12, "f64-win-L12-d1-b256"), (16, "f64-win-L16-d2-b256"), (16, "f64-gwin-L16-d2-b256"),
+                 (24, "f64-gwin-L24-d3-b512")]
+
+
+@pytest.mark.parametrize("L,variant", FP64_VARIANTS)
+def test_window_fp64_matches_oracle(L, variant):
     for (n, nt, nm, init, inst) in [(5, 3, 4, 0, 0), (4, 0, 7, 2, 3), (3, 5, 0, 3, 1)]:
-        say(f"case window fp64 L={L} n={n} sweeps={nt}+{nm} init={init} instance={inst}")
+        if L > 16:
+            n = 2
+        say(f"case window fp64 {variant} n={n} sweeps={nt}+{nm} init={init} instance={inst}")
         ora = oracle_run(L, 1.3, n, nt, nm, init=["sphere", "angles", "ordered", "mixed"][init], trace=nt + nm,
                          instance_id=inst, want_spins=True)
         eng, tr, sp, plan, _ = engine_run(L, 1.3, n, nt, nm, placement=PLACE_WINDOW, init=init, trace=nt + nm,
-                                          instance_id=inst, spins_of=range(n))
-        assert plan.startswith("f64-win-"), plan
+                                          instance_id=inst, spins_of=range(n), variant=variant)
+        assert plan.startswith(variant), plan
         assert_results_close(eng, ora, TOL64)
         assert max_abs_diff(tr, ora["trace"]) <= TOL64
         for p in range(n):
             assert max_abs_diff(sp[p], ora["spins"][p]) <= TOL64
 
 
-def test_window_fp64_split_runs():
+@pytest.mark.parametrize("variant", ["f64-win-L16-d2-b256", "f64-gwin-L16-d2-b256"])
+def test_window_fp64_split_runs(variant):
     """Sweeps run in chunks of 3, 1, 4 and the rest equal one uninterrupted run."""
     from paper_1305_6758_amd import mmc
     L, n, nt, nm = 16, 4, 5, 6
-    say("case window fp64 split")
-    full, _, sp_full, _, _ = engine_run(L, 0.9, n, nt, nm, placement=PLACE_WINDOW, spins_of=range(n))
+    say(f"case window fp64 split {variant}")
+    full, _, sp_full, _, _ = engine_run(L, 0.9, n, nt, nm, placement=PLACE_WINDOW, spins_of=range(n), variant=variant)
     ctx = mmc.mmc_create_ex(L, 0.9, 1.0, n, nt, nm, 1234, mmc.config(precision=mmc.MMC_FP64, placement=PLACE_WINDOW))
     try:
+        mmc.mmc_set_variant(ctx, variant)
         for k in (3, 1, 4):
             mmc.mmc_run_sweeps(ctx, k)
         mmc.mmc_run(ctx)
@@ -59,18 +68,39 @@ def test_window_fp64_split_runs():
         mmc.mmc_destroy(ctx)
 
 
-@pytest.mark.parametrize("L,block", [(24, 512), (24, 1024), (30, 1024), (32, 512), (32, 1024)])
-def test_window_fp32_equals_device_memory_kernels(L, block):
+FP32_VARIANTS = [(24, "f32-win-L24-d2-b512"), (24, "f32-win-L24-d3-b1024"), (30, "f32-win-L30-d2-b1024"),
+                 (32, "f32-win-L32-d2-b512"), (32, "f32-win-L32-d2-b1024"), (32, "f32-gwin-L32-d2-b1024"),
+                 (48, "f32-gwin-L48-d1-b1024"), (64, "f32-gwin-L64-d1-b1024")]
+
+
+@pytest.mark.parametrize("L,variant", FP32_VARIANTS)
+def test_window_fp32_equals_device_memory_kernels(L, variant):
     n, nt, nm = 3, 7, 6
     for renorm in (5, 0):
-        say(f"case window fp32 L={L} block={block} renorm_every={renorm}")
+        say(f"case window fp32 {variant} renorm_every={renorm}")
         ref, _, sp_ref, plan_ref, _ = engine_run(L, 1.2, n, nt, nm, fp64=False, placement=PLACE_HBM, block=512,
                                                  lanes=512, renorm_every=renorm, spins_of=range(n))
-        eng, _, sp, plan, _ = engine_run(L, 1.2, n, nt, nm, fp64=False, placement=PLACE_WINDOW, block=block,
-                                         lanes=block, renorm_every=renorm, spins_of=range(n))
-        assert plan.startswith("f32-win-"), plan
+        eng, _, sp, plan, _ = engine_run(L, 1.2, n, nt, nm, fp64=False, placement=PLACE_WINDOW,
+                                         renorm_every=renorm, spins_of=range(n), variant=variant)
+        assert plan.startswith(variant), plan
         assert np.array_equal(eng["n_accept"], ref["n_accept"]), (plan, plan_ref)
         for p in range(n):
             assert np.array_equal(sp[p], sp_ref[p]), (plan, plan_ref, p)
         for k in ("e_mean", "absm_mean", "m4_mean", "final_e"):
             assert max_abs_diff(eng[k], ref[k]) < 1e-5, (plan, k)
+
+
+def test_set_variant_rejects_what_does_not_fit():
+    from paper_1305_6758_amd import mmc
+    ctx = mmc.mmc_create_ex(32, 1.2, 1.0, 2, 1, 1, 1234, mmc.config(precision=mmc.MMC_FP32))
+    try:
+        for bad in ("f32-gwin-L64-d1-b1024", "f64-gwin-L16-d2-b256", "no-such-variant"):
+            with pytest.raises(mmc.MMCError):
+                mmc.mmc_set_variant(ctx, bad)
+        mmc.mmc_set_variant(ctx, "f32-gwin-L32-d2-b1024")
+        mmc.mmc_run(ctx)
+        assert mmc.mmc_plan(ctx).startswith("f32-gwin-L32-d2-b1024")
+        with pytest.raises(mmc.MMCError):
+            mmc.mmc_set_variant(ctx, "f32-hbm-L32-g512-b512")
+    finally:
+        mmc.mmc_destroy(ctx)
