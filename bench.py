@@ -238,9 +238,34 @@ def cpu_baseline(instances, init="sphere", proposal="sphere", trace=False, ising
     dt = time.perf_counter() - t0
     upd = n * per_path
     full = "all " if sweeps == nt + nm else f"the first {sweeps} of the "
+    # the same oracle on one core: the first path, sweeps bounded to about 2e7 updates
+    s1 = min(sweeps, max(1, int(2e7 / N)))
+    m1 = round(s1 * nm / (nt + nm)) if nt + nm else 0
+    t1 = time.perf_counter()
+    if ising:
+        O.ising_run_paths(L, T, n_therm=s1 - m1, n_meas=m1, seed=1234, path_begin=0, path_end=1, instance=idx,
+                          init=init, n_threads=1)
+    else:
+        O.run_paths(L, T, n_therm=s1 - m1, n_meas=m1, seed=1234, path_begin=0, path_end=1, instance=idx,
+                    n_threads=1, init=init, proposal=proposal)
+    d1 = time.perf_counter() - t1
     return {"value": upd / dt, "unit": "spin updates/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} paths of the L={L}, T={T:g} instance (instance {idx}), {full}"
-                      f"{nt}+{nm} sweeps ({nt_s}+{nm_s}): {upd:.3e} updates in {dt:.1f} s"}
+                      f"{nt}+{nm} sweeps ({nt_s}+{nm_s}): {upd:.3e} updates in {dt:.1f} s",
+            "single_core": {"value": N * s1 / d1, "unit": "spin updates/s",
+                            "sample": f"path 0 of the same instance, {s1 - m1}+{m1} sweeps on one thread"},
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def binder_summary(instances, results):

@@ -424,8 +424,11 @@ int mmco_run_paths(const mmco_params *p, int path_begin, int path_end, mmco_path
     int64_t N = n_sites(p);
     int n = path_end - path_begin;
 #ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
-#pragma omp parallel for schedule(dynamic, 1)
+    /* a thread count for this call only (the process-wide default stays as it was) */
+    const int nthr = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
+#else
+    (void)n_threads;
 #endif
     for (int t = 0; t < n; ++t) {
         mmco_state st;
@@ -519,8 +522,11 @@ int mmco_ising_run_paths(int L, double T, double J, int n_therm, int n_meas, uin
     const double beta = isinf(T) ? 0.0 : 1.0 / T;
     const int n = path_end - path_begin;
 #ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
-#pragma omp parallel for schedule(dynamic, 1)
+    /* a thread count for this call only (the process-wide default stays as it was) */
+    const int nthr = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr)
+#else
+    (void)n_threads;
 #endif
     for (int t = 0; t < n; ++t) {
         const uint32_t path = (uint32_t)(path_begin + t);
