@@ -396,7 +396,13 @@ int ensure_memory(mmc_ctx *c)
     int rc = ensure_device(c);
     if (rc) return rc;
     if (c->ws) return MMC_OK;
-    HIP_TRY(hipMalloc(&c->ws, c->ws_bytes));
+    hipError_t e = hipMalloc(&c->ws, c->ws_bytes);
+    if (e == hipErrorOutOfMemory) {
+        c->ws = nullptr;
+        (void)hipGetLastError();  // not sticky: clear it for the caller's next HIP call
+        return fail(MMC_ENOMEM, "device memory: %zu bytes do not fit", c->ws_bytes);
+    }
+    if (e != hipSuccess) return fail(MMC_EHIP, "hipMalloc of %zu bytes: %s", c->ws_bytes, hipGetErrorString(e));
     c->own_ws = true;
     return MMC_OK;
 }

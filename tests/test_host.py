@@ -55,6 +55,9 @@ def test_arguments_validated_without_gpu():
     try:
         assert mmc.mmc_workspace_bytes(ctx) > 4 * 3 * 512 * 4
         assert mmc.mmc_sweeps_done(ctx) == 0
+        lib = mmc.lib()
+        assert lib.mmc_set_variant(ctx, None) == mmc.MMC_EINVAL
+        assert lib.mmc_set_variant(None, b"f32-lds-L8-g64-b256") == mmc.MMC_EINVAL
     finally:
         mmc.mmc_destroy(ctx)
     mmc.mmc_destroy(None)
