@@ -257,6 +257,24 @@ def cpu_baseline(instances, init="sphere", proposal="sphere", trace=False, ising
             "cpu_model": cpu_model()}
 
 
+def fp32_vs_fp64(instances, r32, r64):
+    """Per instance and observable: the FP32 and FP64 population means over all paths (same
+    seeds, trajectories apart after the first flipped decision), their difference, the 4-sigma
+    bound of the two standard errors, and the difference relative to the FP64 mean."""
+    import numpy as np
+    rows = []
+    for (L, T, *_), a, b in zip(instances, r32, r64):
+        row = {"L": L, "T": T}
+        for key in ("e_mean", "absm_mean", "m2_mean", "m4_mean"):
+            x, y = np.asarray(a[key], dtype=np.float64), np.asarray(b[key], dtype=np.float64)
+            mx, my = float(x.mean()), float(y.mean())
+            bound = 4.0 * float(np.hypot(x.std(ddof=1) / np.sqrt(x.size), y.std(ddof=1) / np.sqrt(y.size)))
+            row[key] = {"fp32": mx, "fp64": my, "diff": mx - my, "bound_4sigma": bound,
+                        "rel_diff": (mx - my) / abs(my) if my else None, "within": abs(mx - my) <= bound}
+        rows.append(row)
+    return rows
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -451,6 +469,8 @@ def main():
             with open(golden_path) as f:
                 ok, rows = four_sigma_vs_oracle(presults, json.load(f))
             out["fp64_plain"]["agree_4sigma"] = ok
+        if len(instances) <= 16:
+            out["fp32_vs_fp64"] = fp32_vs_fp64(instances, results, presults)
     if not a.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(instances)
     print(json.dumps(out), flush=True)

@@ -687,9 +687,10 @@ int mmc_tune(mmc_ctx *c)
                 }
     }
     if (c->sweeps_done) return fail(MMC_ESTATE, "tuning needs a context that has not run yet");
-    // ~0.2 G updates per candidate
+    // ~0.2 G updates per candidate, in whole passes of every window depth (1, 2, 3 sweeps): a
+    // short last pass would charge a window variant a pipeline fill the long run does not pay
     const double per_sweep = (double)in.L * in.L * in.L * in.n_paths;
-    const int sweeps = (int)std::min(64.0, std::max(2.0, 2e8 / per_sweep));
+    const int sweeps = 6 * (int)ceil(std::min(64.0, std::max(2.0, 2e8 / per_sweep)) / 6.0);
     int best = cand[0];
     double best_ms = 1e30;
     for (int i : cand) {
