@@ -185,13 +185,15 @@ int mmc_bind(mmc_ctx *ctx, void *dev_ptr, size_t bytes, void *hip_stream);
  * Called by the first run when needed; leaves the context in its initial state. */
 int mmc_tune(mmc_ctx *ctx);
 
-/* Pins the kernel variant of a single-instance context by the name mmc_plan reports, in
- * place of the tuner's choice. Spins and accept counts are the same under every variant;
+/* Pins the kernel variant of a context by the name mmc_plan reports, in place of the
+ * tuner's choice; on a batch, the named batch variant for every instance it serves (call it
+ * before mmc_bind). Spins and accept counts are the same under every variant;
  * FP32 per-path sums follow the variant's reduction order, so a pinned variant reproduces
  * them bit for bit whatever the tuner would pick on another machine. Only valid before the
  * first run. MMC_EINVAL: NULL argument, unknown name, or a variant that does not fit this
  * context (its L, precision, placement, block, lanes and the device's LDS);
- * MMC_EUNSUPPORTED: a batch context or the plain engine; MMC_ESTATE: the context has run. */
+ * MMC_EUNSUPPORTED: the plain engine; MMC_ESTATE: the context has run (or, for a batch, is
+ * bound). */
 int mmc_set_variant(mmc_ctx *ctx, const char *name);
 
 /* Runs all remaining sweeps (from the initial random state on the first call). The HIP
@@ -286,7 +288,10 @@ void mmc_destroy(mmc_ctx *ctx);
  * from a device work queue. Each instance uses Philox instance word = its index in inst[]
  * (cfg->instance_id is ignored). Precision from cfg (FP32 default). Spin state exists only
  * for items in flight, so mmc_get_spins, mmc_trace, mmc_run_sweeps and mmc_save are not
- * available on a batch. */
+ * available on a batch. Needs the GPU: creation plans the launch from the device's occupancy
+ * and runs the batch autotuner, which times every batch kernel variant that fits each L
+ * (placement LDS or device memory as cfg->placement allows, lanes per path, site map) on a
+ * trial batch of that L and keeps the fastest (cached like mmc_tune's choices). */
 mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, const mmc_config *cfg);
 
 /* Runs the whole batch (all sweeps of all instances). */

@@ -78,6 +78,7 @@ struct Instance {
     // plan
     int variant = -1;  // index into mmc::variants() (single) or mmc::batch_variants() (batch)
     bool plain = false;
+    bool pinned = false;  // batch: variant fixed by mmc_set_variant, not tuned
     // device views (offsets into the workspace)
     size_t off_spins = 0, off_acc = 0, off_trace = 0;
 };
@@ -117,6 +118,7 @@ struct mmc_ctx {
     size_t off_inst = 0, off_var = 0, off_items = 0, off_head = 0, off_slots = 0;
     size_t slot_bytes = 0;
     int n_slots = 0, n_items = 0;
+    int max_slots = 0;  // resident workgroups the device holds (occupancy)
     std::vector<mmc::BatchItem> items;
     bool tuned = false;
 };
@@ -318,7 +320,7 @@ std::vector<int> single_candidates(const mmc_ctx *c, int L)
     return out;
 }
 
-std::vector<int> batch_candidates(int fp64, int L, int placement)
+std::vector<int> batch_candidates(int fp64, int L, int placement, bool keep_generic = false)
 {
     int n;
     const mmc::Variant *vs = mmc::batch_variants(fp64, &n);
@@ -333,6 +335,7 @@ std::vector<int> batch_candidates(int fp64, int L, int placement)
         if (placement == MMC_PLACE_WINDOW) continue;  // no batch form yet
         out.push_back(i);
     }
+    if (keep_generic) return out;
     bool have_exact = false;
     for (int i : out) have_exact |= vs[i].L == L;
     if (have_exact) out.erase(std::remove_if(out.begin(), out.end(), [&](int i) { return vs[i].L == 0; }), out.end());
@@ -712,11 +715,31 @@ int mmc_tune(mmc_ctx *c)
     return MMC_OK;
 }
 
+static void batch_plan(mmc_ctx *c);
+
 int mmc_set_variant(mmc_ctx *c, const char *name)
 {
     if (!c || !name) return fail(MMC_EINVAL, "null argument");
-    if (c->batch) return fail(MMC_EUNSUPPORTED, "mmc_set_variant is for single-instance contexts");
     if (c->sweeps_done) return fail(MMC_ESTATE, "the context has already run");
+    if (c->batch) {
+        // every instance whose L the named batch variant serves
+        if (c->ws) return fail(MMC_ESTATE, "pin batch variants before mmc_bind and the first run");
+        int nv;
+        const mmc::Variant *vs = mmc::batch_variants(c->fp64, &nv);
+        int hits = 0;
+        for (Instance &in : c->inst)
+            for (int v : batch_candidates(c->fp64, in.L, c->cfg.placement, true))
+                if (strcmp(vs[v].name, name) == 0) {
+                    in.variant = v;
+                    in.pinned = true;
+                    ++hits;
+                }
+        if (!hits) return fail(MMC_EINVAL, "batch variant '%s' fits no instance of this batch", name);
+        drop_graphs(c);
+        batch_plan(c);
+        mmc_log("batch variant pinned: %s (%d instance(s))", name, hits);
+        return MMC_OK;
+    }
     int rc = prepare(c);
     if (rc) return rc;
     Instance &in = c->inst[0];
@@ -1086,6 +1109,125 @@ void mmc_destroy(mmc_ctx *c)
 }
 
 // ---------------------------------------------------------------- batch
+// Work list (items of paths_per_item paths, largest first: longest-processing-time order),
+// resident workgroups, HBM slot size and workspace layout of the batch's current variants.
+static void batch_plan(mmc_ctx *c)
+{
+    struct Work {
+        double cost;
+        mmc::BatchItem item;
+    };
+    std::vector<Work> work;
+    size_t slot = 0;
+    for (size_t i = 0; i < c->inst.size(); ++i) {
+        const Instance &in = c->inst[i];
+        const int ppi = mmc::batch_paths_per_item(c->fp64, in.variant);
+        slot = std::max(slot, mmc::batch_slot_bytes(c->fp64, in.variant, in.L));
+        for (int p = 0; p < in.n_paths; p += ppi) {
+            const int np = std::min(ppi, in.n_paths - p);
+            work.push_back({(double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * np, {(int)i, p}});
+        }
+    }
+    std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
+    c->items.clear();
+    for (auto &w : work) c->items.push_back(w.item);
+    c->n_items = (int)c->items.size();
+    c->n_slots = std::min(c->max_slots, c->n_items);
+    c->slot_bytes = align_up(slot);
+    c->ws_bytes = layout_batch(c);
+    c->ready = false;
+}
+
+// Kernel time (ms, best of two graph launches) of batch variant var on a trial batch: one
+// instance like proto with n_trial paths and `sweeps` measured sweeps, in a context of its own.
+static double batch_time_candidate(const mmc_ctx *c, const Instance &proto, int var, int n_trial, int sweeps)
+{
+    mmc_ctx *t = new mmc_ctx;
+    t->batch = true;
+    t->cfg = c->cfg;
+    t->cfg.async = 0;
+    t->seed = c->seed;
+    t->fp64 = c->fp64;
+    t->max_slots = c->max_slots;
+    Instance x = proto;
+    x.n_paths = n_trial;
+    x.n_therm = 0;
+    x.n_meas = sweeps;
+    x.variant = var;
+    x.pinned = true;
+    t->inst.push_back(x);
+    double best = 1e30;
+    if (ensure_device(t) == MMC_OK) {
+        batch_plan(t);
+        for (int rep = 0; rep < 2; ++rep) {
+            if (mmc_batch_run(t) != MMC_OK) {
+                best = 1e30;
+                break;
+            }
+            best = std::min(best, t->last_ms);
+        }
+    }
+    mmc_destroy(t);
+    return best;
+}
+
+// The batch's autotuner: for each L among the instances that are not pinned, every batch
+// variant that fits (placement, LDS budget; specific and generic site maps) runs a trial
+// batch of about 2e8 updates at that L and the fastest is taken for all of them. Choices are
+// cached per (device, precision, L, path count) like the single-instance tuner's.
+static int batch_tune(mmc_ctx *c)
+{
+    int nv;
+    const mmc::Variant *vs = mmc::batch_variants(c->fp64, &nv);
+    std::map<int, std::vector<int>> by_L;
+    for (size_t i = 0; i < c->inst.size(); ++i)
+        if (!c->inst[i].pinned) by_L[c->inst[i].L].push_back((int)i);
+    bool changed = false;
+    for (auto &kv : by_L) {
+        const int L = kv.first;
+        const std::vector<int> cand = batch_candidates(c->fp64, L, c->cfg.placement, true);
+        if (cand.size() < 2) continue;
+        long long paths = 0;
+        for (int i : kv.second) paths += c->inst[i].n_paths;
+        const std::string key = tune_key(true, c->fp64, L, (int)std::min<long long>(paths, 1 << 30));
+        int best = -1;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            tune_cache_load();
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end())
+                for (int v : cand)
+                    if (it->second == vs[v].name) best = v;
+        }
+        if (best < 0) {
+            int ppi_max = 1;
+            for (int v : cand) ppi_max = std::max(ppi_max, mmc::batch_paths_per_item(c->fp64, v));
+            const int n_trial = (int)std::min<long long>(paths, (long long)ppi_max * c->max_slots);
+            const double per_sweep = (double)L * L * L * n_trial;
+            const int sweeps = 6 * (int)ceil(std::min(64.0, std::max(6.0, 2e8 / per_sweep)) / 6.0);
+            double best_ms = 1e30;
+            for (int v : cand) {
+                const double ms = batch_time_candidate(c, c->inst[kv.second[0]], v, n_trial, sweeps);
+                mmc_log("batch tuning L=%d (%d trial paths, %d sweeps): %s %.3f ms", L, n_trial, sweeps, vs[v].name, ms);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = v;
+                }
+            }
+            if (best < 0) continue;  // no trial ran: keep the default
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key] = vs[best].name;
+            tune_cache_store();
+        }
+        for (int i : kv.second) {
+            changed |= c->inst[i].variant != best;
+            c->inst[i].variant = best;
+        }
+    }
+    if (changed) batch_plan(c);
+    return MMC_OK;
+}
+
 mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, const mmc_config *cfg)
 {
     if (!inst || n_inst < 1 || n_inst >= (1 << 24)) {
@@ -1160,30 +1302,12 @@ mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, c
     const size_t lds = mmc::batch_lds_bytes(c->fp64);
     int per_cu = (int)std::max<size_t>(1, (size_t)prop.maxSharedMemoryPerMultiProcessor / (lds + 1024));
     per_cu = std::min(per_cu, std::max(1, prop.maxThreadsPerMultiProcessor / mmc::batch_block()));
-    c->n_slots = std::max(1, per_cu * prop.multiProcessorCount);
-    // work list, largest first (longest-processing-time order)
-    struct Work {
-        double cost;
-        mmc::BatchItem item;
-    };
-    std::vector<Work> work;
-    size_t slot = 0;
-    for (size_t i = 0; i < c->inst.size(); ++i) {
-        const Instance &in = c->inst[i];
-        const int ppi = mmc::batch_paths_per_item(c->fp64, in.variant);
-        slot = std::max(slot, mmc::batch_slot_bytes(c->fp64, in.variant, in.L));
-        for (int p = 0; p < in.n_paths; p += ppi) {
-            const int np = std::min(ppi, in.n_paths - p);
-            work.push_back({(double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * np, {(int)i, p}});
-        }
+    c->max_slots = std::max(1, per_cu * prop.multiProcessorCount);
+    batch_plan(c);
+    if (batch_tune(c) != MMC_OK) {
+        mmc_destroy(c);
+        return nullptr;
     }
-    std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
-    for (auto &w : work) c->items.push_back(w.item);
-    c->n_items = (int)c->items.size();
-    c->n_slots = std::min(c->n_slots, c->n_items);
-    c->slot_bytes = align_up(slot);
-    c->ws_bytes = layout_batch(c);
-    c->ready = false;
     return c;
 }
 

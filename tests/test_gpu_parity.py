@@ -229,6 +229,8 @@ def test_batch_fp32_equals_single_instance_runs():
     say("case batch fp32 vs single")
     ctx = mmc.mmc_batch_create(insts, 1234, mmc.config(precision=mmc.MMC_FP32))
     try:
+        for name in ("f32-lds-L8-g64", "f32-lds-L16-g512"):
+            mmc.mmc_set_variant(ctx, name)
         mmc.mmc_batch_run(ctx)
         got = [mmc.mmc_batch_results(ctx, i, x[3]) for i, x in enumerate(insts)]
     finally:
@@ -238,6 +240,43 @@ def test_batch_fp32_equals_single_instance_runs():
         one, *_ = engine_run(L, T, n, nt, nm, fp64=False, placement=pl, block=b, lanes=g, instance_id=i)
         for k in ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e", "n_accept"):
             assert np.array_equal(got[i][k], one[k]), (L, k)
+
+
+def test_batch_autotuner_and_pinned_variants():
+    """The batch autotuner times the batch variants that fit each L at creation; whatever it
+    picks, and with every instance pinned to the generic device-memory variant instead, FP64
+    paths match the oracle and spins and accept counts agree between the two plans."""
+    from paper_1305_6758_amd import mmc
+    insts = [(8, 1.4, 1.0, 6, 2, 3), (16, 1.2, 1.0, 3, 2, 2), (6, 2.0, -1.0, 4, 3, 1), (12, 1.0, 1.0, 2, 1, 3)]
+    plans, res = [], []
+    for pin in (None, "f64-hbm-any-g512"):
+        say(f"case batch autotuner, pin {pin}")
+        ctx = mmc.mmc_batch_create(insts, 77, mmc.config(precision=mmc.MMC_FP64))
+        try:
+            if pin:
+                mmc.mmc_set_variant(ctx, pin)
+            plans.append(mmc.mmc_plan(ctx))
+            mmc.mmc_batch_run(ctx)
+            res.append([mmc.mmc_batch_results(ctx, i, x[3]) for i, x in enumerate(insts)])
+            with pytest.raises(mmc.MMCError):
+                mmc.mmc_set_variant(ctx, "f64-hbm-any-g512")  # after the first run
+        finally:
+            mmc.mmc_destroy(ctx)
+        say("plan", plans[-1])
+    assert plans[1].count("f64-hbm-any-g512") == len(insts), plans[1]
+    for i, (L, T, J, n, nt, nm) in enumerate(insts):
+        ora = oracle_run(L, T, n, nt, nm, J=J, seed=77, instance_id=i)
+        assert_results_close(res[0][i], ora, TOL64)
+        assert_results_close(res[1][i], ora, TOL64)
+        assert np.array_equal(res[0][i]["n_accept"], res[1][i]["n_accept"])
+    ctx = mmc.mmc_batch_create(insts, 77, mmc.config(precision=mmc.MMC_FP64))
+    try:
+        with pytest.raises(mmc.MMCError):
+            mmc.mmc_set_variant(ctx, "f64-lds-L8-g128-no-such")
+        with pytest.raises(mmc.MMCError):
+            mmc.mmc_set_variant(ctx, "f32-lds-L16-g512")  # an FP32 variant in an FP64 batch
+    finally:
+        mmc.mmc_destroy(ctx)
 
 
 def test_invalid_arguments_rejected():
