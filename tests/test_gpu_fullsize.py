@@ -168,3 +168,32 @@ def test_L64():
     for key in ("e_mean", "absm_mean"):
         ok, d, b = four_sigma_ok(r32, ora, key)
         assert ok, f"{key}: |FP32 - oracle| = {d:.3e} > {b:.3e}"
+
+
+@pytest.mark.timeout(600)
+def test_ising_binder_full_size_sampled_paths_bit_exact():
+    """The 2-D Ising cumulant workload at its full size (L = 60 and 50, 5 * 10^4 single-output
+    paths, 3 * 10^4 sweeps, the contexts the experiment driver creates): integer spins and
+    decisions, so sampled paths from both ends of the path range equal the oracle's exactly
+    (accept counts, final m and e, moments)."""
+    from oracle import oracle as O
+    from paper_1305_6758_amd import mmc
+    from paper_1305_6758_amd.experiments import SEED
+    n, sweeps = 5 * 10 ** 4, 3 * 10 ** 4
+    for (L, T, inst) in [(60, 2.264, 0), (50, 2.268, 3)]:
+        say(f"case ising full size L={L} T={T} instance {inst}")
+        ctx = mmc.mmc_create_ex(L, T, 1.0, n, sweeps - 1, 1, SEED,
+                                mmc.config(model=mmc.MMC_MODEL_ISING2D, instance_id=inst))
+        try:
+            mmc.mmc_run(ctx)
+            say("plan", mmc.mmc_plan(ctx), f"{mmc.mmc_last_timing_ms(ctx):.0f} ms")
+            eng = mmc.mmc_results(ctx, n)
+        finally:
+            mmc.mmc_destroy(ctx)
+        for (a, b) in [(0, 3), (n - 2, n)]:
+            ora = O.ising_run_paths(L, T, n_therm=sweeps - 1, n_meas=1, seed=SEED, path_begin=a, path_end=b,
+                                    instance=inst)
+            assert np.array_equal(eng["n_accept"][a:b], ora["n_accept"]), (L, a)
+            for k in ("e_mean", "absm_mean", "m2_mean", "m4_mean", "final_e"):
+                assert np.max(np.abs(eng[k][a:b] - ora[k])) <= 1e-15, (L, a, k)
+            assert np.max(np.abs(eng["final_m"][a:b] - ora["final_m"])) <= 1e-15, (L, a)
