@@ -121,6 +121,19 @@ def test_edge_cases_fp64():
     assert_results_close(eng, ora, TOL64)
 
 
+@pytest.mark.parametrize("L", [100, 128])
+def test_large_lattices_fp64(L):
+    """Sides beyond the workloads' (generic device-memory variant, L = 100 with 50-site rows of a
+    colour and L = 128 with 2^21 sites): two paths, three sweeps, match the oracle to 1e-12."""
+    say(f"case large lattice L={L}")
+    ora = oracle_run(L, 1.3, 2, 2, 1, want_spins=True)
+    eng, _, sp, plan, _ = engine_run(L, 1.3, 2, 2, 1, placement=PLACE_HBM, spins_of=(0, 1))
+    say("plan", plan)
+    assert_results_close(eng, ora, TOL64)
+    for p in (0, 1):
+        assert max_abs_diff(sp[p], ora["spins"][p]) <= TOL64
+
+
 def test_fp32_statistics_L8():
     """FP32 engine against the FP64 oracle, L = 8, T = 1.5: <e> and <|m|> within 4 standard
     errors; |S| stays 1 to FP32 accuracy."""
