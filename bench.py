@@ -18,6 +18,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--
 """
 import argparse
 import json
+import re
 import math
 import os
 import sys
@@ -51,7 +52,14 @@ UPDATE_OPS_F32 = {
     "v_fma_f32": 5.5, "v_mul_f32": 4, "v_sqrt_f32": 1, "v_sin_f32": 1, "v_cos_f32": 1, "v_exp_f32": 1,
     "v_add_f32": 18, "v_cmp_lt_f32": 1, "v_cndmask_b32": 3,
 }
-SLOTS_PER_UPDATE_F32 = sum(n * VALU_PEAK / OP_RATES[op] for op, n in UPDATE_OPS_F32.items())
+# Summed class by class these cost 153.9 lane-slots; the classes partly overlap in the
+# hardware, so the ceiling is measured instead: the same 81.5 instructions per update (163 per
+# two updates, checked in the compiled loop) on independent chains with no memory traffic run
+# at 5.874e11 updates/s on one MI355X (`opbench` "update_mix"), i.e. 133.9 lane-slots of the
+# peak per update.
+SUMMED_SLOTS_PER_UPDATE_F32 = sum(n * VALU_PEAK / OP_RATES[op] for op, n in UPDATE_OPS_F32.items())
+UPDATE_MIX_UPDATES_PER_S = 5.8744e11
+SLOTS_PER_UPDATE_F32 = VALU_PEAK / UPDATE_MIX_UPDATES_PER_S
 # 2-D Ising update (per site): a quarter of one Philox4x32-10 call (one call serves four
 # sites); the field (3 adds), a = s h (multiply), the threshold index (2) and the
 # always-accept flag (2), the threshold select (4 cndmask) and compare, the flipped spin
@@ -62,6 +70,8 @@ UPDATE_OPS_ISING = {
     "v_cndmask_b32": 5.0, "v_cmp_lt_f32": 1.0,
 }
 OP_RATES.update({"v_add_u32": 5.2908e13, "v_mul_lo_u32": 3.4925e13})
+# (summed class by class: like the FP32 update's summed cost, an upper estimate of the cost, so
+# the Ising VALU fraction is an upper estimate too)
 SLOTS_PER_UPDATE_ISING = sum(n * VALU_PEAK / OP_RATES[op] for op, n in UPDATE_OPS_ISING.items())
 # resident FP64 spins the plain engine may hold (its comparison is skipped above this)
 PLAIN_FP64_MAX_BYTES = 64 << 30
@@ -412,7 +422,9 @@ def main():
     # colour 12 B per half-sweep); when they carry most of the updates the kernel is bound by HBM
     variants = plan.split(";", 1)[1].split() if ";" in plan else [plan]
     hbm_upd = sum(p * L ** 3 * (nt + nm) for (L, T, p, nt, nm), v in zip(instances, variants) if "-hbm-" in v)
-    kernel_name = "k_batch<float>" if not single else (
+    # the batch runs one persistent kernel per variant in use: name them by their variants
+    launched = re.findall(r"\[(\S+) workgroups=", plan)
+    kernel_name = ("k_batch<float> " + " + ".join(launched)) if not single else (
         "k_window<float>" if "win-" in plan else "k_resident<float>")
 
     golden_path = os.path.join(ROOT, "tests", "golden", f"oracle_{a.workload}.json")
@@ -446,7 +458,8 @@ def main():
                      "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(a.workload),
                      "kernel": kernel_name, "kernel_ms": kms,
                      "lane_slots_per_update": SLOTS_PER_UPDATE_F32,
-                     "ceiling_updates_per_s": VALU_PEAK / SLOTS_PER_UPDATE_F32},
+                     "ceiling_updates_per_s": VALU_PEAK / SLOTS_PER_UPDATE_F32,
+                     "ceiling_source": "measured: the update's instruction mix alone (opbench update_mix)"},
         "parity": parity,
     }
     if hbm_upd * 2 > upd_step:

@@ -51,8 +51,7 @@ struct BatchItem {
 
 struct BatchDev {
     const InstDev *inst;     // [n_inst]
-    const int *variant;      // [n_inst] index into the batch kernel's variant list
-    const BatchItem *items;  // [n_items], largest first
+    const BatchItem *items;  // [n_items] of one variant, largest first
     int n_items;
     unsigned int *head;      // work-queue head (zeroed before each launch)
     char *slots;             // HBM spin slots, slot_bytes per resident workgroup
@@ -73,6 +72,8 @@ struct Variant {
     hipError_t (*launch)(const InstDev &in, int k0, int k1, int fresh, hipStream_t s);
     const void *kernel;  // the __global__ function (resident variants)
     int window;          // sweeps per pass of the z-pipelined window variants, 0 otherwise
+    // batch variants: the variant's persistent kernel over a queue of items
+    hipError_t (*launch_batch)(const BatchDev &b, int grid, size_t lds, hipStream_t s);
 };
 
 // Variants usable by resident runs, and by the batch kernel (fixed block size).
@@ -84,8 +85,9 @@ int ising_row_stride(int L);     // bytes per row: [colour][y][row stride], byte
 const Variant *batch_variants(int fp64, int *count);  // index = BatchDev::variant value
 size_t variant_lds_bytes(const Variant &v, int L);             // dynamic LDS at side L
 int batch_block();                                      // threads per workgroup in the batch kernel
-size_t batch_lds_bytes(int fp64);
-hipError_t launch_batch(const BatchDev &b, int fp64, int grid, hipStream_t s);
+// The persistent kernel of one batch variant, with lds bytes of dynamic LDS per workgroup.
+hipError_t launch_batch(const BatchDev &b, int fp64, int variant, int grid, size_t lds, hipStream_t s);
+int batch_blocks_per_cu(int fp64, int variant, size_t lds);  // resident workgroups per CU; 0 if unknown
 int batch_paths_per_item(int fp64, int variant);
 size_t batch_slot_bytes(int fp64, int variant, int L);  // HBM slot bytes needed (0 for LDS)
 

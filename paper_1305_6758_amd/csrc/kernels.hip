@@ -1150,8 +1150,14 @@ constexpr int BATCH_B = 512;
     X(double, 32, 512, COLZ, false, "f64-hbm-L32-g512") \
     X(double, 0, 512, FLAT, false, "f64-hbm-any-g512")
 
-template <typename T>
-__global__ __launch_bounds__(BATCH_B) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchDev bd)
+// The persistent batch kernel of one variant: workgroups take (instance, path group) items
+// of the variant from its queue until the queue is empty. One kernel per variant (a batch
+// launches those of the variants it uses one after another) lets each be compiled for its
+// own occupancy, as the single-instance kernels are: the device-memory variants need more
+// registers than the LDS ones.
+template <typename T, int LC, int G, int MAP, bool LDS>
+__global__ __launch_bounds__(BATCH_B) __attribute__((amdgpu_waves_per_eu(target_waves<T>(LC, BATCH_B, G, LDS))))
+void k_batch(BatchDev bd)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int item_sh;
@@ -1164,18 +1170,15 @@ __global__ __launch_bounds__(BATCH_B) __attribute__((amdgpu_waves_per_eu(4))) vo
         if (it >= bd.n_items) break;  // uniform: every wave leaves once the queue is empty
         const BatchItem item = bd.items[it];
         const InstDev &in = bd.inst[item.inst];
-        const int total = in.n_therm + in.n_meas;
-        int v = bd.variant[item.inst];
-        int idx = 0;
-#define MMC_BATCH_CASE(TT, LC, G, MAP, LDS, NAME) \
-    if constexpr (std::is_same<T, TT>::value) {   \
-        if (v == idx) wg_run<TT, LC, G, BATCH_B, MAP, LDS>(in, item.path0, 0, total, true, smem, slot, false); \
-        ++idx;                                    \
+        wg_run<T, LC, G, BATCH_B, MAP, LDS>(in, item.path0, 0, in.n_therm + in.n_meas, true, smem, slot, false);
     }
-        MMC_BATCH_VARIANTS_F32(MMC_BATCH_CASE)
-        MMC_BATCH_VARIANTS_F64(MMC_BATCH_CASE)
-#undef MMC_BATCH_CASE
-    }
+}
+
+template <typename T, int LC, int G, int MAP, bool LDS>
+hipError_t launch_batch_v(const BatchDev &b, int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_batch<T, LC, G, MAP, LDS>), dim3(grid), dim3(BATCH_B), lds, s, b);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ plain FP64 engine
@@ -1410,7 +1413,8 @@ const Variant *variants(int *count)
 
 #define MMC_BV(TT, LC, G, MAP, LDS, NAME)                                                            \
     Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, LDS ? 1 : 0, BATCH_B, G,               \
-            (LC ? lds_layout_bytes<TT>(LC, BATCH_B, G, LDS) : 0), nullptr, nullptr, 0},
+            (LC ? lds_layout_bytes<TT>(LC, BATCH_B, G, LDS) : 0), nullptr,                             \
+            (const void *)&k_batch<TT, LC, G, MAP, LDS>, 0, &launch_batch_v<TT, LC, G, MAP, LDS>},
 static const Variant k_batch_f32[] = {MMC_BATCH_VARIANTS_F32(MMC_BV)};
 static const Variant k_batch_f64[] = {MMC_BATCH_VARIANTS_F64(MMC_BV)};
 #undef MMC_BV
@@ -1433,18 +1437,6 @@ size_t variant_lds_bytes(const Variant &v, int L)
     return v.fp64 ? lds_layout_bytes<double>(L, v.block, v.lanes, v.lds) : lds_layout_bytes<float>(L, v.block, v.lanes, v.lds);
 }
 
-// Fixed LDS of the batch kernel: the largest footprint of its LDS variants compiled for one
-// L (generic LDS variants accept any L whose footprint fits this size).
-size_t batch_lds_bytes(int fp64)
-{
-    int n;
-    const Variant *v = batch_variants(fp64, &n);
-    size_t m = 0;
-    for (int i = 0; i < n; ++i)
-        if (v[i].lds && v[i].L) m = std::max(m, v[i].lds_bytes);
-    return m;
-}
-
 int batch_paths_per_item(int fp64, int variant)
 {
     int n;
@@ -1460,12 +1452,20 @@ size_t batch_slot_bytes(int fp64, int variant, int L)
     return (size_t)(v[variant].block / v[variant].lanes) * 3 * (size_t)L * L * L * (fp64 ? 8 : 4);
 }
 
-hipError_t launch_batch(const BatchDev &b, int fp64, int grid, hipStream_t s)
+int batch_blocks_per_cu(int fp64, int variant, size_t lds)
 {
-    const size_t lds = batch_lds_bytes(fp64);
-    if (fp64) hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(BATCH_B), lds, s, b);
-    else hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(BATCH_B), lds, s, b);
-    return hipGetLastError();
+    int n;
+    const Variant *v = batch_variants(fp64, &n);
+    int blocks = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, v[variant].kernel, BATCH_B, lds);
+    return e == hipSuccess ? blocks : 0;
+}
+
+hipError_t launch_batch(const BatchDev &b, int fp64, int variant, int grid, size_t lds, hipStream_t s)
+{
+    int n;
+    const Variant *v = batch_variants(fp64, &n);
+    return v[variant].launch_batch(b, grid, lds, s);
 }
 
 // Raises every sweep kernel's dynamic-LDS limit to what the device allows per workgroup
@@ -1490,8 +1490,11 @@ hipError_t prepare_kernels(int max_lds)
     for (int i = 0; i < n; ++i) raise_lds_limit(vs[i].kernel, max_lds);
     const Variant *is = ising_variants(&n);
     for (int i = 0; i < n; ++i) raise_lds_limit(is[i].kernel, max_lds);
-    raise_lds_limit((const void *)&k_batch<float>, max_lds);
-    raise_lds_limit((const void *)&k_batch<double>, max_lds);
+    for (int fp64 = 0; fp64 < 2; ++fp64) {
+        int nb;
+        const Variant *bv = batch_variants(fp64, &nb);
+        for (int i = 0; i < nb; ++i) raise_lds_limit(bv[i].kernel, max_lds);
+    }
     done = 1;
     return hipSuccess;
 }

@@ -53,6 +53,98 @@ OPBENCH_KERNEL(k_sqrt_f32, float, 2.0f + c, asm volatile("v_sqrt_f32 %0, %0" : "
 OPBENCH_KERNEL(k_fma_f64, double, 1.0 + c, asm volatile("v_fma_f64 %0, %0, %1, %1" : "+v"(x[c]) : "v"(yd)))
 OPBENCH_KERNEL(k_add_f64, double, 1.0 + c, asm volatile("v_add_f64 %0, %0, %1" : "+v"(x[c]) : "v"(yd)))
 
+// The algorithmic VALU instructions of two FP32 Metropolis updates (81.5 each: Philox4x32-10
+// with its wave-uniform half on the scalar unit, three uniforms, the proposal, the local
+// field, the energy change and test, the new-spin select and the fused measurement, one fma
+// of which falls on odd sites only), in the order an update issues them, on independent
+// register chains: no memory traffic and no dependency beyond each chain's own, so the rate
+// is the ALU ceiling of the update's instruction mix, whatever the classes' overlap.
+__global__ __launch_bounds__(256) void k_update_mix(uint32_t *sink, int iters)
+{
+    const uint32_t t = threadIdx.x + blockIdx.x * 256u;
+    const uint32_t yb = t * 0x9E3779B9u + 1u;
+    const float yf = 1.0f + 1e-7f * (float)(t & 7);
+    uint64_t m[4];
+    uint32_t b[4], al[2], cm[3];
+    float sb[4], fm[4], mu[2], ad[4], tr[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        m[c] = t + c;
+        b[c] = t ^ (c * 77u);
+        sb[c] = 1.0f + c;
+        fm[c] = 0.5f + c;
+        ad[c] = 2.0f + c;
+        tr[c] = 0.25f + 0.1f * c;
+    }
+    al[0] = t; al[1] = t + 9u; cm[0] = t; cm[1] = t + 3u; cm[2] = t + 5u; mu[0] = 1.5f; mu[1] = 2.5f;
+    // 64-bit product-accumulate as the compiler writes it (carry to a dead scalar pair); the
+    // empty asm keeps each one in place
+    auto mad = [&](uint64_t &x) {
+        x = (uint64_t)yb * (uint32_t)(x >> 32) + x;
+        asm volatile("" : "+v"(x));
+    };
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            // Philox: 18 64-bit products, 15 three-way and 4 two-way xors
+#pragma unroll
+            for (int r = 0; r < 9; ++r) {
+                mad(m[(2 * r) & 3]);
+                asm volatile("v_bitop3_b32 %0, %0, %1, %0 bitop3:0x96" : "+v"(b[r & 3]) : "v"(yb));
+                mad(m[(2 * r + 1) & 3]);
+                if (r < 6) asm volatile("v_bitop3_b32 %0, %0, %1, %0 bitop3:0x96" : "+v"(b[(r + 2) & 3]) : "v"(yb));
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) asm volatile("v_xor_b32 %0, %0, %1" : "+v"(b[c]) : "v"(yb));
+            // three uniforms (alignbit + subtract) and z = 2u - 1
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                asm volatile("v_alignbit_b32 %0, %1, %0, 9" : "+v"(al[c & 1]) : "v"(yb));
+                asm volatile("v_sub_f32 %0, %0, %1" : "+v"(sb[c]) : "v"(yf));
+            }
+            asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(fm[0]) : "v"(yf));
+            // proposal: fma, sqrt, sin, cos, two products
+            asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(fm[1]) : "v"(yf));
+            asm volatile("v_sqrt_f32 %0, %0" : "+v"(tr[0]));
+            asm volatile("v_sin_f32 %0, %0" : "+v"(tr[1]));
+            asm volatile("v_cos_f32 %0, %0" : "+v"(tr[2]));
+            asm volatile("v_mul_f32 %0, %0, %1" : "+v"(mu[0]) : "v"(yf));
+            asm volatile("v_mul_f32 %0, %0, %1" : "+v"(mu[1]) : "v"(yf));
+            // local field: 15 additions
+#pragma unroll
+            for (int c = 0; c < 15; ++c) asm volatile("v_add_f32 %0, %0, %1" : "+v"(ad[c & 3]) : "v"(yf));
+            // energy change and test: 3 subtractions, product, 2 fma, product, exp2, compare
+#pragma unroll
+            for (int c = 0; c < 3; ++c) asm volatile("v_sub_f32 %0, %0, %1" : "+v"(sb[3 - c]) : "v"(yf));
+            asm volatile("v_mul_f32 %0, %0, %1" : "+v"(mu[0]) : "v"(yf));
+            asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(fm[2]) : "v"(yf));
+            asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(fm[3]) : "v"(yf));
+            asm volatile("v_mul_f32 %0, %0, %1" : "+v"(mu[1]) : "v"(yf));
+            asm volatile("v_exp_f32 %0, %0" : "+v"(tr[3]));
+            // compare and the new-spin select on its mask (as the compiler writes them)
+            const bool acc = tr[3] < yf;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                uint32_t v = acc ? cm[c] : yb;
+                asm volatile("" : "+v"(v));
+                cm[c] = v;
+            }
+            // measurement: 3 additions, and 3 fma on the odd one of the two updates
+#pragma unroll
+            for (int c = 0; c < 3; ++c) asm volatile("v_add_f32 %0, %0, %1" : "+v"(ad[(c + 1) & 3]) : "v"(yf));
+            if (u == 1) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(fm[c]) : "v"(yf));
+            }
+        }
+    }
+    uint32_t h = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) h ^= (uint32_t)m[c] ^ b[c] ^ (uint32_t)sb[c] ^ (uint32_t)fm[c] ^ (uint32_t)ad[c] ^ (uint32_t)tr[c];
+    h ^= al[0] ^ al[1] ^ cm[0] ^ cm[1] ^ cm[2] ^ (uint32_t)mu[0] ^ (uint32_t)mu[1];
+    if (h == 0x12345678u) sink[t] = h;
+}
+
 struct Op {
     const char *name;
     void (*fn)(uint32_t *, int);
@@ -66,6 +158,7 @@ const Op k_ops[] = {
     {"v_mul_lo_u32", k_mul_lo_u32},   {"v_mad_u64_u32", k_mad_u64_u32}, {"v_cvt_f32_u32", k_cvt_f32_u32},
     {"v_exp_f32", k_exp_f32},         {"v_sin_f32", k_sin_f32},         {"v_cos_f32", k_cos_f32},
     {"v_sqrt_f32", k_sqrt_f32},       {"v_fma_f64", k_fma_f64},         {"v_add_f64", k_add_f64},
+    {"update_mix", k_update_mix},
 };
 
 }  // namespace
@@ -76,7 +169,8 @@ int mmc_opbench_count(void) { return (int)(sizeof(k_ops) / sizeof(k_ops[0])); }
 
 const char *mmc_opbench_name(int i) { return (i >= 0 && i < mmc_opbench_count()) ? k_ops[i].name : nullptr; }
 
-// Instructions per second (wave-level instructions x 64 lanes) of op i; *ms = kernel time.
+// Instructions per second (wave-level instructions x 64 lanes) of op i -- for "update_mix",
+// updates per second; *ms = kernel time.
 // Returns 0 on success, -1 on a bad index, -3 on a HIP error.
 int mmc_opbench_run(int i, int iters, double *lane_ops_per_s, double *ms)
 {
@@ -102,7 +196,9 @@ int mmc_opbench_run(int i, int iters, double *lane_ops_per_s, double *ms)
     (void)hipFree(sink);
     if (e != hipSuccess) return -3;
     *ms = t;
-    *lane_ops_per_s = (double)blocks * 256.0 * CH * (double)iters / (t * 1e-3);
+    // the update mix: two updates per lane and iteration; a single class: CH instructions
+    const double per_iter = k_ops[i].fn == k_update_mix ? 2.0 : (double)CH;
+    *lane_ops_per_s = (double)blocks * 256.0 * per_iter * (double)iters / (t * 1e-3);
     return 0;
 }
 

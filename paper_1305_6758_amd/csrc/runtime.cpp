@@ -115,11 +115,20 @@ struct mmc_ctx {
     // single-instance extras
     size_t off_kdev = 0;
     // batch
-    size_t off_inst = 0, off_var = 0, off_items = 0, off_head = 0, off_slots = 0;
+    // one persistent launch per batch variant in use, in `order` (largest items first), each
+    // with its own work list, queue head (64 bytes apart), resident workgroups and LDS size;
+    // the device-memory variants' launches share one slot area (they run one after another)
+    struct Launch {
+        int variant = 0;
+        std::vector<mmc::BatchItem> items;
+        size_t off_items = 0, lds = 0;
+        int n_slots = 0;
+    };
+    std::vector<Launch> launches;
+    size_t off_inst = 0, off_head = 0, off_slots = 0;
     size_t slot_bytes = 0;
-    int n_slots = 0, n_items = 0;
-    int max_slots = 0;  // resident workgroups the device holds (occupancy)
-    std::vector<mmc::BatchItem> items;
+    int slot_count = 0;  // workgroup slots of device-memory spins
+    int n_cu = 0;
     bool tuned = false;
 };
 
@@ -324,7 +333,7 @@ std::vector<int> batch_candidates(int fp64, int L, int placement, bool keep_gene
 {
     int n;
     const mmc::Variant *vs = mmc::batch_variants(fp64, &n);
-    const size_t lds_budget = mmc::batch_lds_bytes(fp64);
+    const size_t lds_budget = (size_t)device_lds_limit();
     std::vector<int> out;
     for (int i = 0; i < n; ++i) {
         const mmc::Variant &v = vs[i];
@@ -383,14 +392,14 @@ size_t layout_batch(mmc_ctx *c)
     }
     c->off_inst = off;
     off = align_up(off + c->inst.size() * sizeof(mmc::InstDev));
-    c->off_var = off;
-    off = align_up(off + c->inst.size() * sizeof(int));
-    c->off_items = off;
-    off = align_up(off + (size_t)c->n_items * sizeof(mmc::BatchItem));
+    for (auto &l : c->launches) {
+        l.off_items = off;
+        off = align_up(off + l.items.size() * sizeof(mmc::BatchItem));
+    }
     c->off_head = off;
-    off = align_up(off + 64);
+    off = align_up(off + 64 * std::max<size_t>(1, c->launches.size()));
     c->off_slots = off;
-    off = align_up(off + (size_t)c->n_slots * c->slot_bytes);
+    off = align_up(off + (size_t)c->slot_count * c->slot_bytes);
     return off;
 }
 
@@ -1078,9 +1087,14 @@ int mmc_plan(const mmc_ctx *c, char *buf, size_t n)
     int nv;
     if (c->batch) {
         const mmc::Variant *vs = mmc::batch_variants(c->fp64, &nv);
-        char b[160];
-        snprintf(b, sizeof b, "batch block=%d slots=%d items=%d;", mmc::batch_block(), c->n_slots, c->n_items);
+        char b[200];
+        snprintf(b, sizeof b, "batch block=%d launches=%zu", mmc::batch_block(), c->launches.size());
         s += b;
+        for (const auto &l : c->launches) {
+            snprintf(b, sizeof b, " [%s workgroups=%d items=%zu]", vs[l.variant].name, l.n_slots, l.items.size());
+            s += b;
+        }
+        s += ";";
         for (size_t i = 0; i < c->inst.size(); ++i) {
             snprintf(b, sizeof b, " L%d:%s", c->inst[i].L, c->inst[i].variant >= 0 ? vs[c->inst[i].variant].name : "?");
             s += b;
@@ -1117,22 +1131,45 @@ static void batch_plan(mmc_ctx *c)
         double cost;
         mmc::BatchItem item;
     };
-    std::vector<Work> work;
+    int nv;
+    const mmc::Variant *vs = mmc::batch_variants(c->fp64, &nv);
+    std::vector<std::vector<Work>> work(nv);
+    std::vector<size_t> lds(nv, 0);
     size_t slot = 0;
     for (size_t i = 0; i < c->inst.size(); ++i) {
         const Instance &in = c->inst[i];
-        const int ppi = mmc::batch_paths_per_item(c->fp64, in.variant);
-        slot = std::max(slot, mmc::batch_slot_bytes(c->fp64, in.variant, in.L));
+        const int v = in.variant;
+        const int ppi = mmc::batch_paths_per_item(c->fp64, v);
+        lds[v] = std::max(lds[v], mmc::variant_lds_bytes(vs[v], in.L));
+        if (!vs[v].lds) slot = std::max(slot, mmc::batch_slot_bytes(c->fp64, v, in.L));
         for (int p = 0; p < in.n_paths; p += ppi) {
             const int np = std::min(ppi, in.n_paths - p);
-            work.push_back({(double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * np, {(int)i, p}});
+            work[v].push_back({(double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * np, {(int)i, p}});
         }
     }
-    std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
-    c->items.clear();
-    for (auto &w : work) c->items.push_back(w.item);
-    c->n_items = (int)c->items.size();
-    c->n_slots = std::min(c->max_slots, c->n_items);
+    c->launches.clear();
+    c->slot_count = 0;
+    for (int v = 0; v < nv; ++v) {
+        if (work[v].empty()) continue;
+        std::stable_sort(work[v].begin(), work[v].end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
+        mmc_ctx::Launch l;
+        l.variant = v;
+        for (auto &w : work[v]) l.items.push_back(w.item);
+        l.lds = lds[v];
+        int per_cu = mmc::batch_blocks_per_cu(c->fp64, v, l.lds);
+        if (per_cu < 1) per_cu = 1;
+        l.n_slots = std::min((int)std::min<size_t>(l.items.size(), 1u << 30), per_cu * std::max(1, c->n_cu));
+        if (!vs[v].lds) c->slot_count = std::max(c->slot_count, l.n_slots);
+        c->launches.push_back(std::move(l));
+    }
+    // largest items first across the launches too
+    std::stable_sort(c->launches.begin(), c->launches.end(), [&](const mmc_ctx::Launch &a, const mmc_ctx::Launch &b) {
+        auto cost = [&](const mmc_ctx::Launch &l) {
+            const Instance &in = c->inst[l.items[0].inst];
+            return (double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * mmc::batch_paths_per_item(c->fp64, l.variant);
+        };
+        return cost(a) > cost(b);
+    });
     c->slot_bytes = align_up(slot);
     c->ws_bytes = layout_batch(c);
     c->ready = false;
@@ -1148,7 +1185,7 @@ static double batch_time_candidate(const mmc_ctx *c, const Instance &proto, int 
     t->cfg.async = 0;
     t->seed = c->seed;
     t->fp64 = c->fp64;
-    t->max_slots = c->max_slots;
+    t->n_cu = c->n_cu;
     Instance x = proto;
     x.n_paths = n_trial;
     x.n_therm = 0;
@@ -1200,9 +1237,13 @@ static int batch_tune(mmc_ctx *c)
                     if (it->second == vs[v].name) best = v;
         }
         if (best < 0) {
-            int ppi_max = 1;
-            for (int v : cand) ppi_max = std::max(ppi_max, mmc::batch_paths_per_item(c->fp64, v));
-            const int n_trial = (int)std::min<long long>(paths, (long long)ppi_max * c->max_slots);
+            // one wave of items on every candidate's resident workgroups
+            long long most = 1;
+            for (int v : cand) {
+                const int per_cu = std::max(1, mmc::batch_blocks_per_cu(c->fp64, v, mmc::variant_lds_bytes(vs[v], L)));
+                most = std::max(most, (long long)mmc::batch_paths_per_item(c->fp64, v) * per_cu * c->n_cu);
+            }
+            const int n_trial = (int)std::min<long long>(paths, most);
             const double per_sweep = (double)L * L * L * n_trial;
             const int sweeps = 6 * (int)ceil(std::min(64.0, std::max(6.0, 2e8 / per_sweep)) / 6.0);
             double best_ms = 1e30;
@@ -1299,10 +1340,8 @@ mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, c
         mmc_destroy(c);
         return nullptr;
     }
-    const size_t lds = mmc::batch_lds_bytes(c->fp64);
-    int per_cu = (int)std::max<size_t>(1, (size_t)prop.maxSharedMemoryPerMultiProcessor / (lds + 1024));
-    per_cu = std::min(per_cu, std::max(1, prop.maxThreadsPerMultiProcessor / mmc::batch_block()));
-    c->max_slots = std::max(1, per_cu * prop.multiProcessorCount);
+    // each launch's resident workgroups come from the occupancy calculator (registers, LDS)
+    c->n_cu = prop.multiProcessorCount;
     batch_plan(c);
     if (batch_tune(c) != MMC_OK) {
         mmc_destroy(c);
@@ -1314,32 +1353,35 @@ mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, c
 static int batch_upload(mmc_ctx *c)
 {
     std::vector<mmc::InstDev> d;
-    std::vector<int> var;
-    for (size_t i = 0; i < c->inst.size(); ++i) {
-        d.push_back(inst_dev(c, c->inst[i], (uint32_t)i));
-        var.push_back(c->inst[i].variant);
-    }
+    for (size_t i = 0; i < c->inst.size(); ++i) d.push_back(inst_dev(c, c->inst[i], (uint32_t)i));
     HIP_TRY(hipMemcpy(c->ws + c->off_inst, d.data(), d.size() * sizeof(mmc::InstDev), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->ws + c->off_var, var.data(), var.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->ws + c->off_items, c->items.data(), c->items.size() * sizeof(mmc::BatchItem), hipMemcpyHostToDevice));
+    for (const auto &l : c->launches)
+        HIP_TRY(hipMemcpy(c->ws + l.off_items, l.items.data(), l.items.size() * sizeof(mmc::BatchItem),
+                          hipMemcpyHostToDevice));
     return MMC_OK;
 }
 
+// The launches of the variants in use one after another on the stream (largest items
+// first); every queue head is cleared by one fill kernel before the first.
 static int batch_enqueue(mmc_ctx *c, hipStream_t s)
 {
-    hipError_t e = mmc::fill_zero(c->ws + c->off_head, 64, s);
+    hipError_t e = mmc::fill_zero(c->ws + c->off_head, 64 * std::max<size_t>(1, c->launches.size()), s);
     if (e != hipSuccess) return fail(MMC_EHIP, "queue reset: %s", hipGetErrorString(e));
-    mmc::BatchDev b;
-    b.inst = reinterpret_cast<const mmc::InstDev *>(c->ws + c->off_inst);
-    b.variant = reinterpret_cast<const int *>(c->ws + c->off_var);
-    b.items = reinterpret_cast<const mmc::BatchItem *>(c->ws + c->off_items);
-    b.n_items = c->n_items;
-    b.head = reinterpret_cast<unsigned int *>(c->ws + c->off_head);
-    b.slots = c->ws + c->off_slots;
-    b.slot_bytes = c->slot_bytes;
-    b.n_slots = c->n_slots;
-    e = mmc::launch_batch(b, c->fp64, c->n_slots, s);
-    if (e != hipSuccess) return fail(MMC_EHIP, "batch launch: %s", hipGetErrorString(e));
+    int nv;
+    const mmc::Variant *vs = mmc::batch_variants(c->fp64, &nv);
+    for (size_t k = 0; k < c->launches.size(); ++k) {
+        const auto &l = c->launches[k];
+        mmc::BatchDev b;
+        b.inst = reinterpret_cast<const mmc::InstDev *>(c->ws + c->off_inst);
+        b.items = reinterpret_cast<const mmc::BatchItem *>(c->ws + l.off_items);
+        b.n_items = (int)l.items.size();
+        b.head = reinterpret_cast<unsigned int *>(c->ws + c->off_head + 64 * k);
+        b.slots = c->ws + c->off_slots;  // LDS variants never touch it (slot_bytes 0)
+        b.slot_bytes = vs[l.variant].lds ? 0 : c->slot_bytes;
+        b.n_slots = l.n_slots;
+        e = mmc::launch_batch(b, c->fp64, l.variant, l.n_slots, l.lds, s);
+        if (e != hipSuccess) return fail(MMC_EHIP, "batch launch %s: %s", vs[l.variant].name, hipGetErrorString(e));
+    }
     return MMC_OK;
 }
 

@@ -42,6 +42,7 @@ def main():
                 break
             iters = int(iters * min(64.0, max(2.0, 1.2 * a.ms / max(ms.value, 1e-3))))
         rows[lib.mmc_opbench_name(i).decode()] = (rate.value, ms.value)
+    mix = rows.pop("update_mix")
     base = rows["v_add_f32"][0]
     props = torch.cuda.get_device_properties(0)
     print(f"device: {props.name} {props.gcnArchName}, {props.multi_processor_count} CUs")
@@ -50,7 +51,12 @@ def main():
     print(f"{'instruction':16s} {'lane-ops/s':>12s} {'slots':>7s} {'ms':>8s}")
     for k, (r, ms) in rows.items():
         print(f"{k:16s} {r:12.4e} {base / r:7.2f} {ms:8.2f}")
-    print(json.dumps({k: {"lane_ops_per_s": r, "slots": base / r} for k, (r, _) in rows.items()}))
+    peak = 7.86432e13  # published FP32 vector rate / 2 FLOP per lane operation
+    print(f"update mix (81.5 algorithmic VALU instructions per FP32 update): {mix[0]:.4e} updates/s "
+          f"({mix[1]:.2f} ms) = {peak / mix[0]:.1f} lane-slots of the {peak:.4g} lane-op/s peak per update")
+    out = {k: {"lane_ops_per_s": r, "slots": base / r} for k, (r, _) in rows.items()}
+    out["update_mix"] = {"updates_per_s": mix[0], "lane_slots_per_update": peak / mix[0]}
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":
