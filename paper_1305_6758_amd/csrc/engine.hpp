@@ -51,7 +51,8 @@ struct BatchItem {
 
 struct BatchDev {
     const InstDev *inst;     // [n_inst]
-    const BatchItem *items;  // [n_items] of one variant, largest first
+    const int *variant;      // [n_inst] batch variant of each instance (the shared device-memory kernel)
+    const BatchItem *items;  // [n_items] of one launch, largest first
     int n_items;
     unsigned int *head;      // work-queue head (zeroed before each launch)
     char *slots;             // HBM spin slots, slot_bytes per resident workgroup

@@ -1181,6 +1181,46 @@ hipError_t launch_batch_v(const BatchDev &b, int grid, size_t lds, hipStream_t s
     return hipGetLastError();
 }
 
+// The device-memory variants share one persistent kernel: their items form one queue, largest
+// first across all of them, so the long items of the largest lattices start first and the
+// short ones fill the tail (memory-bound work, where the shared register budget costs little).
+template <typename T>
+__global__ __launch_bounds__(BATCH_B) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_mem(BatchDev bd)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int item_sh;
+    T *slot = reinterpret_cast<T *>(bd.slots + (size_t)blockIdx.x * bd.slot_bytes);
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = (int)atomicAdd(bd.head, 1u);
+        __syncthreads();
+        const int it = item_sh;
+        __syncthreads();
+        if (it >= bd.n_items) break;  // uniform: every wave leaves once the queue is empty
+        const BatchItem item = bd.items[it];
+        const InstDev &in = bd.inst[item.inst];
+        const int total = in.n_therm + in.n_meas;
+        const int v = bd.variant[item.inst];
+        int idx = 0;
+#define MMC_BATCH_MEM_CASE(TT, LC, G, MAP, LDS, NAME)                                                        \
+    if constexpr (std::is_same<T, TT>::value) {                                                              \
+        if constexpr (!LDS) {                                                                                \
+            if (v == idx) wg_run<TT, LC, G, BATCH_B, MAP, false>(in, item.path0, 0, total, true, smem, slot, false); \
+        }                                                                                                    \
+        ++idx;                                                                                               \
+    }
+        MMC_BATCH_VARIANTS_F32(MMC_BATCH_MEM_CASE)
+        MMC_BATCH_VARIANTS_F64(MMC_BATCH_MEM_CASE)
+#undef MMC_BATCH_MEM_CASE
+    }
+}
+
+template <typename T>
+hipError_t launch_batch_mem(const BatchDev &b, int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_mem<T>, dim3(grid), dim3(BATCH_B), lds, s, b);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ plain FP64 engine
 // One thread per site of one colour, spins in device memory, one launch per half-sweep;
 // the sweep index lives in device memory so one captured sweep can be replayed.
@@ -1411,10 +1451,12 @@ const Variant *variants(int *count)
     return k_variants;
 }
 
+// LDS variants: a persistent kernel each; device-memory variants: the shared one
 #define MMC_BV(TT, LC, G, MAP, LDS, NAME)                                                            \
     Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, LDS ? 1 : 0, BATCH_B, G,               \
             (LC ? lds_layout_bytes<TT>(LC, BATCH_B, G, LDS) : 0), nullptr,                             \
-            (const void *)&k_batch<TT, LC, G, MAP, LDS>, 0, &launch_batch_v<TT, LC, G, MAP, LDS>},
+            LDS ? (const void *)&k_batch<TT, LC, G, MAP, true> : (const void *)&k_batch_mem<TT>, 0,     \
+            LDS ? &launch_batch_v<TT, LC, G, MAP, true> : &launch_batch_mem<TT>},
 static const Variant k_batch_f32[] = {MMC_BATCH_VARIANTS_F32(MMC_BV)};
 static const Variant k_batch_f64[] = {MMC_BATCH_VARIANTS_F64(MMC_BV)};
 #undef MMC_BV

@@ -109,6 +109,11 @@ struct mmc_ctx {
     bool own_ws = false;
     bool ready = false;  // memory and plan in place
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_in = nullptr, ev_out = nullptr;
+    // batch: a stream and a join event per launch after the first (default priority), so the
+    // captured graph runs the variants' persistent kernels side by side
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
     double last_ms = 0;
     int sweeps_done = 0;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -119,15 +124,18 @@ struct mmc_ctx {
     // with its own work list, queue head (64 bytes apart), resident workgroups and LDS size;
     // the device-memory variants' launches share one slot area (they run one after another)
     struct Launch {
-        int variant = 0;
+        int variant = 0;  // a variant of the launch's kernel (the first; the shared
+                          // device-memory kernel serves several)
+        std::string name;
         std::vector<mmc::BatchItem> items;
         size_t off_items = 0, lds = 0;
-        int n_slots = 0;
+        int n_slots = 0;                       // resident workgroups (the grid)
+        double updates = 0;                    // Metropolis attempts of its items
+        size_t off_slots = 0, slot_bytes = 0;  // device-memory variants: this launch's spin slots
     };
     std::vector<Launch> launches;
-    size_t off_inst = 0, off_head = 0, off_slots = 0;
-    size_t slot_bytes = 0;
-    int slot_count = 0;  // workgroup slots of device-memory spins
+    size_t off_inst = 0, off_var = 0, off_head = 0, off_slots = 0;
+    size_t slot_area = 0;  // bytes of all launches' slots (the launches run side by side)
     int n_cu = 0;
     bool tuned = false;
 };
@@ -392,6 +400,8 @@ size_t layout_batch(mmc_ctx *c)
     }
     c->off_inst = off;
     off = align_up(off + c->inst.size() * sizeof(mmc::InstDev));
+    c->off_var = off;
+    off = align_up(off + c->inst.size() * sizeof(int));
     for (auto &l : c->launches) {
         l.off_items = off;
         off = align_up(off + l.items.size() * sizeof(mmc::BatchItem));
@@ -399,7 +409,7 @@ size_t layout_batch(mmc_ctx *c)
     c->off_head = off;
     off = align_up(off + 64 * std::max<size_t>(1, c->launches.size()));
     c->off_slots = off;
-    off = align_up(off + (size_t)c->slot_count * c->slot_bytes);
+    off = align_up(off + c->slot_area);
     return off;
 }
 
@@ -1091,7 +1101,7 @@ int mmc_plan(const mmc_ctx *c, char *buf, size_t n)
         snprintf(b, sizeof b, "batch block=%d launches=%zu", mmc::batch_block(), c->launches.size());
         s += b;
         for (const auto &l : c->launches) {
-            snprintf(b, sizeof b, " [%s workgroups=%d items=%zu]", vs[l.variant].name, l.n_slots, l.items.size());
+            snprintf(b, sizeof b, " [%s workgroups=%d items=%zu]", l.name.c_str(), l.n_slots, l.items.size());
             s += b;
         }
         s += ";";
@@ -1118,6 +1128,9 @@ void mmc_destroy(mmc_ctx *c)
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    for (hipEvent_t e : c->ev_join) (void)hipEventDestroy(e);
+    for (hipStream_t a : c->aux) (void)hipStreamDestroy(a);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1133,44 +1146,63 @@ static void batch_plan(mmc_ctx *c)
     };
     int nv;
     const mmc::Variant *vs = mmc::batch_variants(c->fp64, &nv);
-    std::vector<std::vector<Work>> work(nv);
-    std::vector<size_t> lds(nv, 0);
-    size_t slot = 0;
+    // one launch per kernel: each LDS variant has its own, the device-memory variants share one
+    std::vector<const void *> kern;
+    std::vector<std::vector<Work>> work;
+    std::vector<size_t> lds, slot;
+    std::vector<int> first;
+    std::vector<std::string> names;
     for (size_t i = 0; i < c->inst.size(); ++i) {
         const Instance &in = c->inst[i];
         const int v = in.variant;
+        size_t g = std::find(kern.begin(), kern.end(), vs[v].kernel) - kern.begin();
+        if (g == kern.size()) {
+            kern.push_back(vs[v].kernel);
+            work.emplace_back();
+            lds.push_back(0);
+            slot.push_back(0);
+            first.push_back(v);
+            names.push_back("");
+        }
+        if (names[g].find(vs[v].name) == std::string::npos) names[g] += (names[g].empty() ? "" : "+") + std::string(vs[v].name);
         const int ppi = mmc::batch_paths_per_item(c->fp64, v);
-        lds[v] = std::max(lds[v], mmc::variant_lds_bytes(vs[v], in.L));
-        if (!vs[v].lds) slot = std::max(slot, mmc::batch_slot_bytes(c->fp64, v, in.L));
+        lds[g] = std::max(lds[g], mmc::variant_lds_bytes(vs[v], in.L));
+        if (!vs[v].lds) slot[g] = std::max(slot[g], mmc::batch_slot_bytes(c->fp64, v, in.L));
         for (int p = 0; p < in.n_paths; p += ppi) {
             const int np = std::min(ppi, in.n_paths - p);
-            work[v].push_back({(double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * np, {(int)i, p}});
+            work[g].push_back({(double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * np, {(int)i, p}});
         }
     }
     c->launches.clear();
-    c->slot_count = 0;
-    for (int v = 0; v < nv; ++v) {
-        if (work[v].empty()) continue;
-        std::stable_sort(work[v].begin(), work[v].end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
+    for (size_t g = 0; g < kern.size(); ++g) {
+        std::stable_sort(work[g].begin(), work[g].end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
         mmc_ctx::Launch l;
-        l.variant = v;
-        for (auto &w : work[v]) l.items.push_back(w.item);
-        l.lds = lds[v];
-        int per_cu = mmc::batch_blocks_per_cu(c->fp64, v, l.lds);
+        l.variant = first[g];
+        l.name = names[g];
+        for (auto &w : work[g]) {
+            l.items.push_back(w.item);
+            l.updates += w.cost;
+        }
+        l.lds = lds[g];
+        int per_cu = mmc::batch_blocks_per_cu(c->fp64, first[g], l.lds);
         if (per_cu < 1) per_cu = 1;
         l.n_slots = std::min((int)std::min<size_t>(l.items.size(), 1u << 30), per_cu * std::max(1, c->n_cu));
-        if (!vs[v].lds) c->slot_count = std::max(c->slot_count, l.n_slots);
+        l.slot_bytes = align_up(slot[g]);
         c->launches.push_back(std::move(l));
     }
     // largest items first across the launches too
     std::stable_sort(c->launches.begin(), c->launches.end(), [&](const mmc_ctx::Launch &a, const mmc_ctx::Launch &b) {
         auto cost = [&](const mmc_ctx::Launch &l) {
             const Instance &in = c->inst[l.items[0].inst];
-            return (double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * mmc::batch_paths_per_item(c->fp64, l.variant);
+            return (double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * mmc::batch_paths_per_item(c->fp64, in.variant);
         };
         return cost(a) > cost(b);
     });
-    c->slot_bytes = align_up(slot);
+    c->slot_area = 0;
+    for (auto &l : c->launches) {
+        l.off_slots = c->slot_area;
+        c->slot_area += (size_t)l.n_slots * l.slot_bytes;
+    }
     c->ws_bytes = layout_batch(c);
     c->ready = false;
 }
@@ -1353,34 +1385,59 @@ mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, c
 static int batch_upload(mmc_ctx *c)
 {
     std::vector<mmc::InstDev> d;
-    for (size_t i = 0; i < c->inst.size(); ++i) d.push_back(inst_dev(c, c->inst[i], (uint32_t)i));
+    std::vector<int> var;
+    for (size_t i = 0; i < c->inst.size(); ++i) {
+        d.push_back(inst_dev(c, c->inst[i], (uint32_t)i));
+        var.push_back(c->inst[i].variant);
+    }
     HIP_TRY(hipMemcpy(c->ws + c->off_inst, d.data(), d.size() * sizeof(mmc::InstDev), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->ws + c->off_var, var.data(), var.size() * sizeof(int), hipMemcpyHostToDevice));
     for (const auto &l : c->launches)
         HIP_TRY(hipMemcpy(c->ws + l.off_items, l.items.data(), l.items.size() * sizeof(mmc::BatchItem),
                           hipMemcpyHostToDevice));
     return MMC_OK;
 }
 
-// The launches of the variants in use one after another on the stream (largest items
-// first); every queue head is cleared by one fill kernel before the first.
+// The launches (largest items first): the first on the context's stream, each further one on
+// a stream of its own forked from it and joined back, so the kernels run side by side and
+// compute-bound LDS work overlaps the memory-bound device-memory kernel. Where the LDS
+// launches carry under a tenth of the updates they start after the device-memory kernel
+// instead: side by side they would hold CU resources from the kernel on the critical path
+// for longer than their share is worth. The kernels share no data but the read-only
+// instance and variant tables, and each works its own queue to the end.
 static int batch_enqueue(mmc_ctx *c, hipStream_t s)
 {
     hipError_t e = mmc::fill_zero(c->ws + c->off_head, 64 * std::max<size_t>(1, c->launches.size()), s);
     if (e != hipSuccess) return fail(MMC_EHIP, "queue reset: %s", hipGetErrorString(e));
     int nv;
     const mmc::Variant *vs = mmc::batch_variants(c->fp64, &nv);
+    double total = 0, in_lds = 0;
+    for (const auto &l : c->launches) {
+        total += l.updates;
+        if (vs[l.variant].lds) in_lds += l.updates;
+    }
+    const bool after_memory = !vs[c->launches[0].variant].lds && in_lds < 0.1 * total;
     for (size_t k = 0; k < c->launches.size(); ++k) {
         const auto &l = c->launches[k];
+        hipStream_t sk = k ? c->aux[k - 1] : s;
+        // fork point: before the first launch, or after it when the rest waits for it
+        if (c->launches.size() > 1 && k == (after_memory ? 1 : 0)) HIP_TRY(hipEventRecord(c->ev_fork, s));
+        if (k) HIP_TRY(hipStreamWaitEvent(sk, c->ev_fork, 0));
         mmc::BatchDev b;
         b.inst = reinterpret_cast<const mmc::InstDev *>(c->ws + c->off_inst);
+        b.variant = reinterpret_cast<const int *>(c->ws + c->off_var);
         b.items = reinterpret_cast<const mmc::BatchItem *>(c->ws + l.off_items);
         b.n_items = (int)l.items.size();
         b.head = reinterpret_cast<unsigned int *>(c->ws + c->off_head + 64 * k);
-        b.slots = c->ws + c->off_slots;  // LDS variants never touch it (slot_bytes 0)
-        b.slot_bytes = vs[l.variant].lds ? 0 : c->slot_bytes;
+        b.slots = c->ws + c->off_slots + l.off_slots;  // LDS variants: slot_bytes 0, never touched
+        b.slot_bytes = l.slot_bytes;
         b.n_slots = l.n_slots;
-        e = mmc::launch_batch(b, c->fp64, l.variant, l.n_slots, l.lds, s);
-        if (e != hipSuccess) return fail(MMC_EHIP, "batch launch %s: %s", vs[l.variant].name, hipGetErrorString(e));
+        e = mmc::launch_batch(b, c->fp64, l.variant, l.n_slots, l.lds, sk);
+        if (e != hipSuccess) return fail(MMC_EHIP, "batch launch %s: %s", l.name.c_str(), hipGetErrorString(e));
+    }
+    for (size_t k = 1; k < c->launches.size(); ++k) {
+        HIP_TRY(hipEventRecord(c->ev_join[k - 1], c->aux[k - 1]));
+        HIP_TRY(hipStreamWaitEvent(s, c->ev_join[k - 1], 0));
     }
     return MMC_OK;
 }
@@ -1394,6 +1451,15 @@ int mmc_batch_run(mmc_ctx *c)
         if (rc) return rc;
         rc = batch_upload(c);
         if (rc) return rc;
+        if (!c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        while (c->aux.size() + 1 < c->launches.size()) {
+            hipStream_t a = nullptr;
+            hipEvent_t e = nullptr;
+            HIP_TRY(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+            c->aux.push_back(a);
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            c->ev_join.push_back(e);
+        }
         c->ready = true;
     }
     GraphKey key{0, 0, 1};
