@@ -124,3 +124,47 @@ def test_batch_graph_replays():
                 assert_same(mmc.mmc_batch_results(ctx, i, x[3]), first[i], f"replay {rep} instance {i}")
     finally:
         mmc.mmc_destroy(ctx)
+
+
+MIXED = {
+    # device-memory work dominates (98%): the LDS launches start after the device-memory kernel
+    "lds-after-memory": ([(24, 1.3, 1.0, 40, 3, 3), (8, 1.5, 1.0, 9, 3, 3), (12, 2.0, 1.0, 4, 2, 2)],
+                         {"fp64": ["f64-hbm-any-g512", "f64-lds-L8-g128", "f64-lds-L12-g512"],
+                          "fp32": ["f32-hbm-any-g512", "f32-lds-L8-g64", "f32-lds-L12-g256"]}),
+    # LDS work is a large share: the launches run side by side (the later pin wins where both fit)
+    "side-by-side": ([(20, 1.4, 1.0, 6, 3, 3), (30, 1.45, 1.0, 3, 3, 2), (16, 1.2, 1.0, 5, 2, 2)],
+                     {"fp64": ["f64-hbm-any-g512", "f64-lds-any-g512"],
+                      "fp32": ["f32-hbm-any-g512", "f32-lds-any-g512"]}),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MIXED))
+def test_mixed_batch_launch_schedules(name):
+    """Batches that mix LDS and device-memory variants (one kernel per LDS variant, the
+    device-memory variants in one shared-queue kernel, on forked streams in one graph): FP64
+    paths match the oracle, and FP32 graph replays with device work in between equal the
+    first launch bit for bit."""
+    from paper_1305_6758_amd import mmc
+    insts, pins = MIXED[name]
+    for prec in ("fp64", "fp32"):
+        say(f"case mixed batch {name} {prec}")
+        ctx = mmc.mmc_batch_create(insts, 1234, mmc.config(precision=mmc.MMC_FP64 if prec == "fp64" else mmc.MMC_FP32))
+        try:
+            for v in pins[prec]:
+                mmc.mmc_set_variant(ctx, v)
+            mmc.mmc_batch_run(ctx)
+            plan = mmc.mmc_plan(ctx)
+            say("plan", plan)
+            assert "-lds-" in plan and "-hbm-" in plan, plan
+            first = [mmc.mmc_batch_results(ctx, i, x[3]) for i, x in enumerate(insts)]
+            if prec == "fp64":
+                for i, (L, T, J, n, nt, nm) in enumerate(insts):
+                    assert_results_close(first[i], oracle_run(L, T, n, nt, nm, J=J, instance_id=i), 1e-12)
+            else:
+                for rep in range(3):
+                    eager_work(mmc, rep)
+                    mmc.mmc_batch_run(ctx)
+                    for i, x in enumerate(insts):
+                        assert_same(mmc.mmc_batch_results(ctx, i, x[3]), first[i], f"replay {rep} instance {i}")
+        finally:
+            mmc.mmc_destroy(ctx)
