@@ -1134,6 +1134,7 @@ constexpr int BATCH_B = 512;
     X(float, 8, 64, COLZ, true, "f32-lds-L8-g64")    \
     X(float, 12, 256, FLAT, true, "f32-lds-L12-g256") \
     X(float, 16, 512, COLZ, true, "f32-lds-L16-g512") \
+    X(float, 20, 512, FLAT, true, "f32-lds-L20-g512") \
     X(float, 0, 512, FLAT, true, "f32-lds-any-g512")  \
     X(float, 16, 512, COLZ, false, "f32-hbm-L16-g512") \
     X(float, 24, 512, FLAT, false, "f32-hbm-L24-g512") \
@@ -1400,6 +1401,7 @@ static const Variant k_variants[] = {
     MMC_RES(float, 8, 64, 256, COLZ, true, "f32-lds-L8-g64-b256")
     MMC_RES(float, 8, 128, 256, COLZ, true, "f32-lds-L8-g128-b256")
     MMC_RES(float, 8, 256, 256, COLZ, true, "f32-lds-L8-g256-b256")
+    MMC_RES(float, 10, 256, 256, COLZ, true, "f32-lds-L10-g256-b256")
     MMC_RES(float, 12, 128, 256, FLAT, true, "f32-lds-L12-g128-b256")
     MMC_RES(float, 12, 256, 256, FLAT, true, "f32-lds-L12-g256-b256")
     MMC_RES(float, 16, 256, 256, COLZ, true, "f32-lds-L16-g256-b256")

@@ -304,7 +304,7 @@ bool variant_fits(const mmc::Variant &v, int fp64, int L, int lds_limit)
     return true;
 }
 
-std::vector<int> single_candidates(const mmc_ctx *c, int L)
+std::vector<int> single_candidates(const mmc_ctx *c, int L, bool keep_generic = false)
 {
     int n;
     const mmc::Variant *vs = single_table(c, &n);
@@ -330,6 +330,7 @@ std::vector<int> single_candidates(const mmc_ctx *c, int L)
         if (c->cfg.lanes_per_path && v.lanes != c->cfg.lanes_per_path) continue;
         out.push_back(i);
     }
+    if (keep_generic) return out;
     // a generic variant only when no variant is compiled for this L
     bool have_exact = false;
     for (int i : out) have_exact |= vs[i].L == L;
@@ -765,7 +766,7 @@ int mmc_set_variant(mmc_ctx *c, const char *name)
     if (in.plain) return fail(MMC_EUNSUPPORTED, "the plain engine has no kernel variants");
     int n;
     const mmc::Variant *vs = single_table(c, &n);
-    for (int i : single_candidates(c, in.L))
+    for (int i : single_candidates(c, in.L, true))
         if (strcmp(vs[i].name, name) == 0) {
             in.variant = i;
             c->tuned = true;
