@@ -1136,7 +1136,6 @@ constexpr int BATCH_B = 512;
     X(float, 16, 512, COLZ, true, "f32-lds-L16-g512") \
     X(float, 20, 512, FLAT, true, "f32-lds-L20-g512") \
     X(float, 0, 512, FLAT, true, "f32-lds-any-g512")  \
-    X(float, 16, 512, COLZ, false, "f32-hbm-L16-g512") \
     X(float, 24, 512, FLAT, false, "f32-hbm-L24-g512") \
     X(float, 32, 512, COLZ, false, "f32-hbm-L32-g512") \
     X(float, 48, 512, FLAT, false, "f32-hbm-L48-g512") \
@@ -1147,7 +1146,6 @@ constexpr int BATCH_B = 512;
     X(double, 8, 128, COLZ, true, "f64-lds-L8-g128")   \
     X(double, 12, 512, FLAT, true, "f64-lds-L12-g512") \
     X(double, 0, 512, FLAT, true, "f64-lds-any-g512")  \
-    X(double, 16, 512, COLZ, false, "f64-hbm-L16-g512") \
     X(double, 32, 512, COLZ, false, "f64-hbm-L32-g512") \
     X(double, 0, 512, FLAT, false, "f64-hbm-any-g512")
 
