@@ -285,6 +285,37 @@ def fp32_vs_fp64(instances, r32, r64):
     return rows
 
 
+def tune_only(name):
+    """Creates the workload's contexts as its run would and tunes them, without running."""
+    from paper_1305_6758_amd import mmc
+    from paper_1305_6758_amd.workloads import EXPERIMENTS, WORKLOADS, experiment_instances
+    cfg = mmc.config(precision=mmc.MMC_FP32)
+    if name in WORKLOADS:
+        instances = WORKLOADS[name]["instances"]
+        if len(instances) == 1:
+            L, T, p, nt, nm = instances[0]
+            ctx = mmc.mmc_create_ex(L, T, 1.0, p, nt, nm, 1234, cfg)
+            try:
+                mmc.mmc_tune(ctx)
+                log("tuned:", mmc.mmc_plan(ctx))
+            finally:
+                mmc.mmc_destroy(ctx)
+        else:
+            ctx = mmc.mmc_batch_create([(L, T, 1.0, p, nt, nm) for (L, T, p, nt, nm) in instances], 1234, cfg)
+            log("tuned:", mmc.mmc_plan(ctx)[:200])
+            mmc.mmc_destroy(ctx)
+        return
+    spec = EXPERIMENTS[name]
+    if spec.get("fp64") or spec.get("model", 0) == 1 or spec["kind"].startswith("ising"):
+        return  # the plain FP64 engine and the Ising kernels have no variants to choose between
+    for (L, T, p, nt, nm) in experiment_instances(spec):
+        ctx = mmc.mmc_create_ex(L, T, 1.0, p, nt, nm, 1234, cfg)
+        try:
+            mmc.mmc_tune(ctx)
+        finally:
+            mmc.mmc_destroy(ctx)
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -373,12 +404,15 @@ def main():
                     help="one-instance workloads: spin placement of the single-instance engine")
     ap.add_argument("--variant", default=None,
                     help="one-instance workloads: pin the kernel variant by name instead of tuning")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="run the tuners of the workload's contexts (their choices go to the MMC_TUNE_CACHE "
+                         "file when set) and exit, so that a later (profiled) run launches only its steps")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs paths on a single MI355X; "
-              "multi-GPU runs are not part of it (paths would shard by index, see the design notes).",
+        print("bench.py measures one GPU: the engine runs its paths on a single MI355X; several GPUs "
+              "would each take a contiguous range of path indices, which is not built here.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -386,6 +420,9 @@ def main():
     if a.workload not in WORKLOADS and a.workload not in EXPERIMENTS:
         print(f"unknown workload {a.workload}; one of {sorted(WORKLOADS) + sorted(EXPERIMENTS)}", file=sys.stderr)
         sys.exit(2)
+    if a.tune_only:
+        tune_only(a.workload)
+        return
     if a.workload in EXPERIMENTS:
         spec = EXPERIMENTS[a.workload]
         line, instances = run_experiment(a.workload, spec, a.steps or 1)
