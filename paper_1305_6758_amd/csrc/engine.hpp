@@ -85,7 +85,6 @@ size_t ising_spin_bytes(int L);  // bytes of one path's state in device memory
 int ising_row_stride(int L);     // bytes per row: [colour][y][row stride], byte j = x >> 1
 const Variant *batch_variants(int fp64, int *count);  // index = BatchDev::variant value
 size_t variant_lds_bytes(const Variant &v, int L);             // dynamic LDS at side L
-int batch_block();                                      // threads per workgroup in the batch kernel
 // The persistent kernel of one batch variant, with lds bytes of dynamic LDS per workgroup.
 hipError_t launch_batch(const BatchDev &b, int fp64, int variant, int grid, size_t lds, hipStream_t s);
 int batch_blocks_per_cu(int fp64, int variant, size_t lds);  // resident workgroups per CU; 0 if unknown

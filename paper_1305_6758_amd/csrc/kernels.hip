@@ -1129,33 +1129,36 @@ hipError_t launch_window(const InstDev &in, int k0, int k1, int fresh, hipStream
 // ------------------------------------------------------------------ persistent batch kernel
 constexpr int BATCH_B = 512;
 
-// Variant lists of the batch kernel (block BATCH_B). Index = BatchDev::variant value.
-#define MMC_BATCH_VARIANTS_F32(X)                  \
-    X(float, 8, 64, COLZ, true, "f32-lds-L8-g64")    \
-    X(float, 12, 256, FLAT, true, "f32-lds-L12-g256") \
-    X(float, 16, 512, COLZ, true, "f32-lds-L16-g512") \
-    X(float, 20, 512, FLAT, true, "f32-lds-L20-g512") \
-    X(float, 0, 512, FLAT, true, "f32-lds-any-g512")  \
-    X(float, 24, 512, FLAT, false, "f32-hbm-L24-g512") \
-    X(float, 32, 512, COLZ, false, "f32-hbm-L32-g512") \
-    X(float, 48, 512, FLAT, false, "f32-hbm-L48-g512") \
-    X(float, 64, 512, COLZ, false, "f32-hbm-L64-g512") \
-    X(float, 0, 512, FLAT, false, "f32-hbm-any-g512")
+// Variant lists of the batch kernels: (type, L or 0 for any, lanes per path, block, site map,
+// in LDS, name). Index = BatchDev::variant value. Device-memory variants run in the shared
+// kernel, whose block is BATCH_B; an LDS variant has a kernel, and a block, of its own.
+#define MMC_BATCH_VARIANTS_F32(X)                        \
+    X(float, 8, 64, 512, COLZ, true, "f32-lds-L8-g64")       \
+    X(float, 12, 256, 512, FLAT, true, "f32-lds-L12-g256")   \
+    X(float, 16, 512, 512, COLZ, true, "f32-lds-L16-g512")   \
+    X(float, 20, 512, 512, FLAT, true, "f32-lds-L20-g512")   \
+    X(float, 20, 1024, 1024, COLZ, true, "f32-lds-L20-g1024") \
+    X(float, 0, 512, 512, FLAT, true, "f32-lds-any-g512")    \
+    X(float, 24, 512, 512, FLAT, false, "f32-hbm-L24-g512")  \
+    X(float, 32, 512, 512, COLZ, false, "f32-hbm-L32-g512")  \
+    X(float, 48, 512, 512, FLAT, false, "f32-hbm-L48-g512")  \
+    X(float, 64, 512, 512, COLZ, false, "f32-hbm-L64-g512")  \
+    X(float, 0, 512, 512, FLAT, false, "f32-hbm-any-g512")
 
-#define MMC_BATCH_VARIANTS_F64(X)                    \
-    X(double, 8, 128, COLZ, true, "f64-lds-L8-g128")   \
-    X(double, 12, 512, FLAT, true, "f64-lds-L12-g512") \
-    X(double, 0, 512, FLAT, true, "f64-lds-any-g512")  \
-    X(double, 32, 512, COLZ, false, "f64-hbm-L32-g512") \
-    X(double, 0, 512, FLAT, false, "f64-hbm-any-g512")
+#define MMC_BATCH_VARIANTS_F64(X)                          \
+    X(double, 8, 128, 512, COLZ, true, "f64-lds-L8-g128")   \
+    X(double, 12, 512, 512, FLAT, true, "f64-lds-L12-g512") \
+    X(double, 0, 512, 512, FLAT, true, "f64-lds-any-g512")  \
+    X(double, 32, 512, 512, COLZ, false, "f64-hbm-L32-g512") \
+    X(double, 0, 512, 512, FLAT, false, "f64-hbm-any-g512")
 
 // The persistent batch kernel of one variant: workgroups take (instance, path group) items
 // of the variant from its queue until the queue is empty. One kernel per variant (a batch
 // launches those of the variants it uses one after another) lets each be compiled for its
 // own occupancy, as the single-instance kernels are: the device-memory variants need more
 // registers than the LDS ones.
-template <typename T, int LC, int G, int MAP, bool LDS>
-__global__ __launch_bounds__(BATCH_B) __attribute__((amdgpu_waves_per_eu(target_waves<T>(LC, BATCH_B, G, LDS))))
+template <typename T, int LC, int G, int B, int MAP, bool LDS>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(target_waves<T>(LC, B, G, LDS))))
 void k_batch(BatchDev bd)
 {
     extern __shared__ __align__(16) char smem[];
@@ -1169,14 +1172,14 @@ void k_batch(BatchDev bd)
         if (it >= bd.n_items) break;  // uniform: every wave leaves once the queue is empty
         const BatchItem item = bd.items[it];
         const InstDev &in = bd.inst[item.inst];
-        wg_run<T, LC, G, BATCH_B, MAP, LDS>(in, item.path0, 0, in.n_therm + in.n_meas, true, smem, slot, false);
+        wg_run<T, LC, G, B, MAP, LDS>(in, item.path0, 0, in.n_therm + in.n_meas, true, smem, slot, false);
     }
 }
 
-template <typename T, int LC, int G, int MAP, bool LDS>
+template <typename T, int LC, int G, int B, int MAP, bool LDS>
 hipError_t launch_batch_v(const BatchDev &b, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_batch<T, LC, G, MAP, LDS>), dim3(grid), dim3(BATCH_B), lds, s, b);
+    hipLaunchKernelGGL((k_batch<T, LC, G, B, MAP, LDS>), dim3(grid), dim3(B), lds, s, b);
     return hipGetLastError();
 }
 
@@ -1200,9 +1203,10 @@ __global__ __launch_bounds__(BATCH_B) __attribute__((amdgpu_waves_per_eu(4))) vo
         const int total = in.n_therm + in.n_meas;
         const int v = bd.variant[item.inst];
         int idx = 0;
-#define MMC_BATCH_MEM_CASE(TT, LC, G, MAP, LDS, NAME)                                                        \
+#define MMC_BATCH_MEM_CASE(TT, LC, G, B, MAP, LDS, NAME)                                                     \
     if constexpr (std::is_same<T, TT>::value) {                                                              \
         if constexpr (!LDS) {                                                                                \
+            static_assert(B == BATCH_B, "the shared device-memory kernel has one block size");              \
             if (v == idx) wg_run<TT, LC, G, BATCH_B, MAP, false>(in, item.path0, 0, total, true, smem, slot, false); \
         }                                                                                                    \
         ++idx;                                                                                               \
@@ -1452,11 +1456,26 @@ const Variant *variants(int *count)
 }
 
 // LDS variants: a persistent kernel each; device-memory variants: the shared one
-#define MMC_BV(TT, LC, G, MAP, LDS, NAME)                                                            \
-    Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, LDS ? 1 : 0, BATCH_B, G,               \
-            (LC ? lds_layout_bytes<TT>(LC, BATCH_B, G, LDS) : 0), nullptr,                             \
-            LDS ? (const void *)&k_batch<TT, LC, G, MAP, true> : (const void *)&k_batch_mem<TT>, 0,     \
-            LDS ? &launch_batch_v<TT, LC, G, MAP, true> : &launch_batch_mem<TT>},
+// The kernel and launcher of a batch variant: its own kernel for an LDS variant, the shared
+// device-memory kernel otherwise (chosen at compile time, so no unused kernel is built).
+template <typename T, int LC, int G, int B, int MAP, bool LDS>
+constexpr const void *batch_kernel_of()
+{
+    if constexpr (LDS) return (const void *)&k_batch<T, LC, G, B, MAP, true>;
+    else return (const void *)&k_batch_mem<T>;
+}
+
+template <typename T, int LC, int G, int B, int MAP, bool LDS>
+constexpr auto batch_launcher_of()
+{
+    if constexpr (LDS) return &launch_batch_v<T, LC, G, B, MAP, true>;
+    else return &launch_batch_mem<T>;
+}
+
+#define MMC_BV(TT, LC, G, B, MAP, LDS, NAME)                                                         \
+    Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, LDS ? 1 : 0, B, G,                     \
+            (LC ? lds_layout_bytes<TT>(LC, B, G, LDS) : 0), nullptr,                                   \
+            batch_kernel_of<TT, LC, G, B, MAP, LDS>(), 0, batch_launcher_of<TT, LC, G, B, MAP, LDS>()},
 static const Variant k_batch_f32[] = {MMC_BATCH_VARIANTS_F32(MMC_BV)};
 static const Variant k_batch_f64[] = {MMC_BATCH_VARIANTS_F64(MMC_BV)};
 #undef MMC_BV
@@ -1470,8 +1489,6 @@ const Variant *batch_variants(int fp64, int *count)
     *count = (int)(sizeof(k_batch_f32) / sizeof(k_batch_f32[0]));
     return k_batch_f32;
 }
-
-int batch_block() { return BATCH_B; }
 
 size_t variant_lds_bytes(const Variant &v, int L)
 {
@@ -1499,7 +1516,7 @@ int batch_blocks_per_cu(int fp64, int variant, size_t lds)
     int n;
     const Variant *v = batch_variants(fp64, &n);
     int blocks = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, v[variant].kernel, BATCH_B, lds);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, v[variant].kernel, v[variant].block, lds);
     return e == hipSuccess ? blocks : 0;
 }
 

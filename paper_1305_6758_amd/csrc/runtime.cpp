@@ -1099,10 +1099,11 @@ int mmc_plan(const mmc_ctx *c, char *buf, size_t n)
     if (c->batch) {
         const mmc::Variant *vs = mmc::batch_variants(c->fp64, &nv);
         char b[200];
-        snprintf(b, sizeof b, "batch block=%d launches=%zu", mmc::batch_block(), c->launches.size());
+        snprintf(b, sizeof b, "batch launches=%zu", c->launches.size());
         s += b;
         for (const auto &l : c->launches) {
-            snprintf(b, sizeof b, " [%s workgroups=%d items=%zu]", l.name.c_str(), l.n_slots, l.items.size());
+            snprintf(b, sizeof b, " [%s block=%d workgroups=%d items=%zu]", l.name.c_str(), vs[l.variant].block,
+                     l.n_slots, l.items.size());
             s += b;
         }
         s += ";";
