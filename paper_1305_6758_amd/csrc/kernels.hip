@@ -133,7 +133,9 @@ struct GroupCtx {
     uint32_t path, key0, key1, ctr3;  // ctr3 = instance << 8 (tag added per use)
     bool active;                      // path < n_paths
     int lane;                         // 0 .. G-1
-    T *sp;                            // spins of this path while sweeping (LDS or device memory)
+    T *sp;                            // colour-0 spins of this path while sweeping (LDS or device memory)
+    T *sp1;                           // colour-1 spins (sp + 3 L^3 / 2, or device memory when only
+                                      // colour 0 is in LDS)
     double *shacc;                    // 16 doubles in LDS: the path's PathAcc while sweeping
     T *red;                           // LDS [16-lane rows of the group][4] measurement partials
 };
@@ -353,15 +355,18 @@ __device__ __forceinline__ LaneGeom make_lane_geom(int lane)
 //   z = z0 + DZ t with DZ = G / plane, else the lane owns columns lane + G t and every z
 //   (the wrap-around planes z = 0 and L-1 peeled off).
 //   FLAT (any L): lane owns half-indices lane + G s.
-template <typename T, int LC, int G, int MAP>
+template <typename T, int LC, int G, int MAP, bool SPLIT>
 __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, const LaneGeom &q, int c, uint32_t k,
                                            const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
                                            unsigned long long &nacc)
 {
     const int L = LC ? LC : g.L;
     const int HALF = L * L * L / 2;
-    T *own = g.sp + (c ? 3 * HALF : 0);
-    const T *oth = g.sp + (c ? 0 : 3 * HALF);
+    // (c is a constant after inlining, so each colour's address space is known statically;
+    // colour 1 follows colour 0 unless the colours are split between LDS and device memory)
+    T *const sp1 = SPLIT ? g.sp1 : g.sp + 3 * HALF;
+    T *own = c ? sp1 : g.sp;
+    const T *oth = c ? g.sp : sp1;
     const bool odd = c != 0;
     // The lane's site geometry and the sweep-independent part of its counters are cheap to
     // recompute here; an opaque lane index keeps the compiler from hoisting them for all of
@@ -450,10 +455,11 @@ __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, const LaneGeom 
 }
 
 // Initial state of Sec. 2.2 (Philox counter (id, 0, path, TAG_INIT)): the group's lanes take
-// the path's sites in a flat stride. Out of line (runs once): inlined, it crashes the
-// ROCm 7.2 optimizer (SimplifyCFG).
+// the path's sites in a flat stride. sp0 / sp1: colour-0 / colour-1 spins (sp1 null: colour 1
+// follows colour 0). Out of line (runs once): inlined, it crashes the ROCm 7.2 optimizer
+// (SimplifyCFG).
 template <typename T, int G>
-__device__ __attribute__((noinline)) void init_path(T *sp, int L, int lane, uint32_t path, uint32_t key0,
+__device__ __attribute__((noinline)) void init_path(T *sp0, T *sp1, int L, int lane, uint32_t path, uint32_t key0,
                                                     uint32_t key1, uint32_t ctr3, int init)
 {
     const int HALF = L * L * L / 2;
@@ -472,23 +478,23 @@ __device__ __attribute__((noinline)) void init_path(T *sp, int L, int lane, uint
             if (init == INIT_ANGLES) Arith<T>::angles(w.w0, w.w1, x, y, z);
             else Arith<T>::sphere(w.w0, w.w1, x, y, z);
         }
-        T *own = sp + c * 3 * HALF;
+        T *own = c ? (sp1 ? sp1 : sp0 + 3 * HALF) : sp0;
         own[h] = x;
         own[HALF + h] = y;
         own[2 * HALF + h] = z;
     }
 }
 
-// FP32 only: S <- S / |S| for every site of the path (each site touched by one lane). Out of
-// line (runs every renorm_every sweeps): inlined, it crashes the ROCm 7.2 optimizer
-// (SimplifyCFG).
+// FP32 only: S <- S / |S| for every site of the path (each site touched by one lane; sp0 and
+// sp1 as for init_path). Out of line (runs every renorm_every sweeps): inlined, it crashes the
+// ROCm 7.2 optimizer (SimplifyCFG).
 template <int G>
-__device__ __attribute__((noinline)) void renorm_path(float *sp, int L, int lane)
+__device__ __attribute__((noinline)) void renorm_path(float *sp0, float *sp1, int L, int lane)
 {
     const int HALF = L * L * L / 2;
     for (int t = lane; t < 2 * HALF; t += G) {
         const int c = t >= HALF, h = t - c * HALF;
-        float *own = sp + c * 3 * HALF;
+        float *own = c ? (sp1 ? sp1 : sp0 + 3 * HALF) : sp0;
         const float x = own[h], y = own[HALF + h], z = own[2 * HALF + h];
         const float r = __builtin_amdgcn_rsqf(fmaf(z, z, fmaf(y, y, x * x)));
         own[h] = x * r;
@@ -500,7 +506,7 @@ __device__ __attribute__((noinline)) void renorm_path(float *sp, int L, int lane
 // Sweeps [k0, k1) of one path group. All groups of the workgroup call this together (same
 // instance and sweep range), so __syncthreads() separates the half-sweeps of all of them.
 // Idle groups (path >= n_paths) and idle lanes still take every barrier.
-template <typename T, int LC, int G, int MAP>
+template <typename T, int LC, int G, int MAP, bool SPLIT>
 __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev &in, int k0, int k1, bool fresh)
 {
     const int L = LC ? LC : g.L;
@@ -516,7 +522,8 @@ __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev 
     constexpr int W = G / 64;  // waves per path group
     unsigned long long nacc = 0;  // this wave's accepted moves
 
-    if (g.active && fresh) init_path<T, G>(g.sp, L, g.lane, g.path, g.key0, g.key1, g.ctr3, in.init);
+    T *const sp1 = SPLIT ? g.sp1 : nullptr;  // colour-1 spins when they do not follow colour 0
+    if (g.active && fresh) init_path<T, G>(g.sp, sp1, L, g.lane, g.path, g.key0, g.key1, g.ctr3, in.init);
     __syncthreads();
     LaneGeom geom{};
     if constexpr (MAP == COLZ && ColzShape<LC, G>::FEW) {
@@ -528,14 +535,14 @@ __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev 
     for (int k = k0; k < k1; ++k) {
         if constexpr (std::is_same<T, float>::value) {
             if (renorm_every > 0 && k > 0 && k % renorm_every == 0) {
-                if (g.active) renorm_path<G>(g.sp, L, g.lane);
+                if (g.active) renorm_path<G>(g.sp, sp1, L, g.lane);
                 __syncthreads();
             }
         }
         T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);
-        if (g.active) half_sweep<T, LC, G, MAP>(g, geom, 0, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+        if (g.active) half_sweep<T, LC, G, MAP, SPLIT>(g, geom, 0, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
         __syncthreads();
-        if (g.active) half_sweep<T, LC, G, MAP>(g, geom, 1, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+        if (g.active) half_sweep<T, LC, G, MAP, SPLIT>(g, geom, 1, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
         const bool meas = k >= n_therm || k < trace_sweeps || k == k1 - 1;
         if (meas) {
             // sums over each 16-lane row; one lane per row leaves its row's four partials
@@ -616,12 +623,18 @@ __device__ __attribute__((noinline)) void copy_spins(T *__restrict__ dst, const 
     for (int t = lane; t < n; t += G) dst[t] = src[t];
 }
 
-// LDS bytes of one workgroup: spins (LDS placement), accumulators, reduction slots (four
-// partials per 16-lane row).
+// Where a path's spins live while it sweeps: all in device memory, all in LDS, or colour 0
+// in LDS and colour 1 in device memory (sides whose lattice is too large for LDS but half of
+// it is not: 22 <= L <= 30 in FP32).
+enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2 };
+
+// LDS bytes of one workgroup: spins (all of them, or colour 0), accumulators, reduction
+// slots (four partials per 16-lane row).
 template <typename T>
-__host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, bool in_lds)
+__host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, int pl)
 {
-    return (in_lds ? (size_t)(B / G) * 3 * (size_t)L * L * L * sizeof(T) : 0) + (size_t)(B / G) * 128 +
+    const size_t ns = 3 * (size_t)L * L * L * sizeof(T);
+    return (size_t)(B / G) * (pl == PL_LDS ? ns : pl == PL_SPLIT ? ns / 2 : 0) + (size_t)(B / G) * 128 +
            (size_t)(B / 16) * 4 * sizeof(T);
 }
 
@@ -629,11 +642,13 @@ __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, bool 
 // path0 + group. gbase: device memory of path path0's spins (group g at gbase + g * 3 L^3):
 // the instance's resident array (resident = true: LDS spins are loaded from and stored back
 // to it) or a batch slot. The caller passes the base explicitly: a select between the two
-// crashes the ROCm 7.2 optimizer (SimplifyCFG).
-template <typename T, int LC, int G, int B, int MAP, bool IN_LDS>
+// crashes the ROCm 7.2 optimizer (SimplifyCFG). PL: a Place; with PL_SPLIT colour 1 is swept
+// in place in device memory and only colour 0 is copied to and from LDS.
+template <typename T, int LC, int G, int B, int MAP, int PL>
 __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int k1, bool fresh, char *smem, T *gbase,
                                        bool resident)
 {
+    constexpr bool IN_LDS = PL != PL_MEM;
     constexpr int P = B / G;
     const int L = LC ? LC : in.L;
     const size_t NS = 3 * (size_t)L * L * L;  // spin words per path
@@ -649,18 +664,21 @@ __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int
     g.active = (int)g.path < in.n_paths;
     char *p = smem;
     T *lds_spins = reinterpret_cast<T *>(p);
-    if (IN_LDS) p += P * NS * sizeof(T);
+    // spin words of a path held in LDS
+    const size_t NL = PL == PL_LDS ? NS : PL == PL_SPLIT ? NS / 2 : 0;
+    p += P * NL * sizeof(T);
     g.shacc = reinterpret_cast<double *>(p) + 16 * group;
     p += P * 128;
     g.red = reinterpret_cast<T *>(p) + 16 * (group * (G / 64));
     T *gsp = gbase + (size_t)group * NS;
-    g.sp = IN_LDS ? lds_spins + (size_t)group * NS : gsp;
+    g.sp = IN_LDS ? lds_spins + (size_t)group * NL : gsp;
+    g.sp1 = PL == PL_LDS ? g.sp + NS / 2 : gsp + NS / 2;
 
     load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
-    if (IN_LDS && !fresh && g.active) copy_spins<G>(g.sp, gsp, (int)NS, g.lane);
+    if (IN_LDS && !fresh && g.active) copy_spins<G>(g.sp, gsp, (int)NL, g.lane);
     // (path_sweeps begins with a barrier)
-    path_sweeps<T, LC, G, MAP>(g, in, k0, k1, fresh);
-    if (IN_LDS && resident && g.active) copy_spins<G>(gsp, g.sp, (int)NS, g.lane);
+    path_sweeps<T, LC, G, MAP, PL == PL_SPLIT>(g, in, k0, k1, fresh);
+    if (IN_LDS && resident && g.active) copy_spins<G>(gsp, g.sp, (int)NL, g.lane);
     store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
 }
 
@@ -668,32 +686,32 @@ __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int
 // many workgroups as the 160 KiB of LDS per CU holds, 4 SIMDs per CU, at most 8 waves per
 // SIMD (4 in FP64); 4 (FP64: 2) for spins in device memory.
 template <typename T>
-constexpr int target_waves(int L, int B, int G, bool in_lds)
+constexpr int target_waves(int L, int B, int G, int pl)
 {
     const int fp64 = sizeof(T) == 8;  // FP64 values take register pairs
-    if (!in_lds || L == 0) return fp64 ? 2 : 4;
-    const int wgs = (int)((size_t)160 * 1024 / lds_layout_bytes<T>(L, B, G, true));
+    if (pl == PL_MEM || L == 0) return fp64 ? 2 : 4;
+    const int wgs = (int)((size_t)160 * 1024 / lds_layout_bytes<T>(L, B, G, pl));
     const int w = wgs * (B / 64) / 4, cap = fp64 ? 4 : 8;
     return w < 1 ? 1 : (w > cap ? cap : w);
 }
 
-template <typename T, int LC, int G, int B, int MAP, bool IN_LDS>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(target_waves<T>(LC, B, G, IN_LDS))))
+template <typename T, int LC, int G, int B, int MAP, int PL>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(target_waves<T>(LC, B, G, PL))))
 void k_resident(InstDev in, int k0, int k1, int fresh)
 {
     extern __shared__ __align__(16) char smem[];
     const int L = LC ? LC : in.L;
     const int path0 = blockIdx.x * (B / G);
-    wg_run<T, LC, G, B, MAP, IN_LDS>(in, path0, k0, k1, fresh != 0, smem,
+    wg_run<T, LC, G, B, MAP, PL>(in, path0, k0, k1, fresh != 0, smem,
                                      reinterpret_cast<T *>(in.spins) + (size_t)path0 * 3 * L * L * L, true);
 }
 
-template <typename T, int LC, int G, int B, int MAP, bool IN_LDS>
+template <typename T, int LC, int G, int B, int MAP, int PL>
 hipError_t launch_resident(const InstDev &in, int k0, int k1, int fresh, hipStream_t s)
 {
     const int L = LC ? LC : in.L;
-    const size_t lds = lds_layout_bytes<T>(L, B, G, IN_LDS);
-    auto kern = k_resident<T, LC, G, B, MAP, IN_LDS>;
+    const size_t lds = lds_layout_bytes<T>(L, B, G, PL);
+    auto kern = k_resident<T, LC, G, B, MAP, PL>;
     const int grid = (in.n_paths + (B / G) - 1) / (B / G);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(B), lds, s, in, k0, k1, fresh);
     return hipGetLastError();
@@ -867,7 +885,7 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
     const int tid = g.lane, wave = tid >> 6, wl = tid & 63;
     unsigned long long nacc = 0;
 
-    if (g.active && fresh) init_path<T, B>(g.sp, L, tid, g.path, g.key0, g.key1, g.ctr3, in.init);
+    if (g.active && fresh) init_path<T, B>(g.sp, nullptr, L, tid, g.path, g.key0, g.key1, g.ctr3, in.init);
     __syncthreads();
     for (int ks = k0; ks < k1;) {
         int Dp = k1 - ks < D ? k1 - ks : D;
@@ -890,7 +908,7 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
         if constexpr (GM) {
             // planes stay in device memory: normalise the whole lattice before the pass
             if constexpr (std::is_same<T, float>::value) {
-                if (rn && g.active) renorm_path<B>(g.sp, L, tid);
+                if (rn && g.active) renorm_path<B>(g.sp, nullptr, L, tid);
             }
         } else if (g.active) {
 #pragma unroll 1
@@ -1130,35 +1148,39 @@ hipError_t launch_window(const InstDev &in, int k0, int k1, int fresh, hipStream
 constexpr int BATCH_B = 512;
 
 // Variant lists of the batch kernels: (type, L or 0 for any, lanes per path, block, site map,
-// in LDS, name). Index = BatchDev::variant value. Device-memory variants run in the shared
+// Place, name). Index = BatchDev::variant value. Device-memory variants run in the shared
 // kernel, whose block is BATCH_B; an LDS variant has a kernel, and a block, of its own.
-#define MMC_BATCH_VARIANTS_F32(X)                        \
-    X(float, 8, 64, 512, COLZ, true, "f32-lds-L8-g64")       \
-    X(float, 12, 256, 512, FLAT, true, "f32-lds-L12-g256")   \
-    X(float, 16, 512, 512, COLZ, true, "f32-lds-L16-g512")   \
-    X(float, 20, 512, 512, FLAT, true, "f32-lds-L20-g512")   \
-    X(float, 20, 1024, 1024, COLZ, true, "f32-lds-L20-g1024") \
-    X(float, 0, 512, 512, FLAT, true, "f32-lds-any-g512")    \
-    X(float, 24, 512, 512, FLAT, false, "f32-hbm-L24-g512")  \
-    X(float, 32, 512, 512, COLZ, false, "f32-hbm-L32-g512")  \
-    X(float, 48, 512, 512, FLAT, false, "f32-hbm-L48-g512")  \
-    X(float, 64, 512, 512, COLZ, false, "f32-hbm-L64-g512")  \
-    X(float, 0, 512, 512, FLAT, false, "f32-hbm-any-g512")
+#define MMC_BATCH_VARIANTS_F32(X)                                 \
+    X(float, 8, 64, 512, COLZ, PL_LDS, "f32-lds-L8-g64")              \
+    X(float, 12, 256, 512, FLAT, PL_LDS, "f32-lds-L12-g256")          \
+    X(float, 16, 512, 512, COLZ, PL_LDS, "f32-lds-L16-g512")          \
+    X(float, 20, 512, 512, FLAT, PL_LDS, "f32-lds-L20-g512")          \
+    X(float, 20, 1024, 1024, COLZ, PL_LDS, "f32-lds-L20-g1024")       \
+    X(float, 0, 512, 512, FLAT, PL_LDS, "f32-lds-any-g512")           \
+    X(float, 24, 1024, 1024, FLAT, PL_SPLIT, "f32-split-L24-g1024")   \
+    X(float, 30, 1024, 1024, COLZ, PL_SPLIT, "f32-split-L30-g1024")   \
+    X(float, 0, 1024, 1024, FLAT, PL_SPLIT, "f32-split-any-g1024")    \
+    X(float, 24, 512, 512, FLAT, PL_MEM, "f32-hbm-L24-g512")          \
+    X(float, 32, 512, 512, COLZ, PL_MEM, "f32-hbm-L32-g512")          \
+    X(float, 48, 512, 512, FLAT, PL_MEM, "f32-hbm-L48-g512")          \
+    X(float, 64, 512, 512, COLZ, PL_MEM, "f32-hbm-L64-g512")          \
+    X(float, 0, 512, 512, FLAT, PL_MEM, "f32-hbm-any-g512")
 
-#define MMC_BATCH_VARIANTS_F64(X)                          \
-    X(double, 8, 128, 512, COLZ, true, "f64-lds-L8-g128")   \
-    X(double, 12, 512, 512, FLAT, true, "f64-lds-L12-g512") \
-    X(double, 0, 512, 512, FLAT, true, "f64-lds-any-g512")  \
-    X(double, 32, 512, 512, COLZ, false, "f64-hbm-L32-g512") \
-    X(double, 0, 512, 512, FLAT, false, "f64-hbm-any-g512")
+#define MMC_BATCH_VARIANTS_F64(X)                                 \
+    X(double, 8, 128, 512, COLZ, PL_LDS, "f64-lds-L8-g128")           \
+    X(double, 12, 512, 512, FLAT, PL_LDS, "f64-lds-L12-g512")         \
+    X(double, 0, 512, 512, FLAT, PL_LDS, "f64-lds-any-g512")          \
+    X(double, 0, 512, 512, FLAT, PL_SPLIT, "f64-split-any-g512")      \
+    X(double, 32, 512, 512, COLZ, PL_MEM, "f64-hbm-L32-g512")         \
+    X(double, 0, 512, 512, FLAT, PL_MEM, "f64-hbm-any-g512")
 
 // The persistent batch kernel of one variant: workgroups take (instance, path group) items
 // of the variant from its queue until the queue is empty. One kernel per variant (a batch
 // launches those of the variants it uses one after another) lets each be compiled for its
 // own occupancy, as the single-instance kernels are: the device-memory variants need more
 // registers than the LDS ones.
-template <typename T, int LC, int G, int B, int MAP, bool LDS>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(target_waves<T>(LC, B, G, LDS))))
+template <typename T, int LC, int G, int B, int MAP, int PL>
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(target_waves<T>(LC, B, G, PL))))
 void k_batch(BatchDev bd)
 {
     extern __shared__ __align__(16) char smem[];
@@ -1172,14 +1194,14 @@ void k_batch(BatchDev bd)
         if (it >= bd.n_items) break;  // uniform: every wave leaves once the queue is empty
         const BatchItem item = bd.items[it];
         const InstDev &in = bd.inst[item.inst];
-        wg_run<T, LC, G, B, MAP, LDS>(in, item.path0, 0, in.n_therm + in.n_meas, true, smem, slot, false);
+        wg_run<T, LC, G, B, MAP, PL>(in, item.path0, 0, in.n_therm + in.n_meas, true, smem, slot, false);
     }
 }
 
-template <typename T, int LC, int G, int B, int MAP, bool LDS>
+template <typename T, int LC, int G, int B, int MAP, int PL>
 hipError_t launch_batch_v(const BatchDev &b, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_batch<T, LC, G, B, MAP, LDS>), dim3(grid), dim3(B), lds, s, b);
+    hipLaunchKernelGGL((k_batch<T, LC, G, B, MAP, PL>), dim3(grid), dim3(B), lds, s, b);
     return hipGetLastError();
 }
 
@@ -1203,11 +1225,11 @@ __global__ __launch_bounds__(BATCH_B) __attribute__((amdgpu_waves_per_eu(4))) vo
         const int total = in.n_therm + in.n_meas;
         const int v = bd.variant[item.inst];
         int idx = 0;
-#define MMC_BATCH_MEM_CASE(TT, LC, G, B, MAP, LDS, NAME)                                                     \
+#define MMC_BATCH_MEM_CASE(TT, LC, G, B, MAP, PL, NAME)                                                      \
     if constexpr (std::is_same<T, TT>::value) {                                                              \
-        if constexpr (!LDS) {                                                                                \
+        if constexpr (PL == PL_MEM) {                                                                        \
             static_assert(B == BATCH_B, "the shared device-memory kernel has one block size");              \
-            if (v == idx) wg_run<TT, LC, G, BATCH_B, MAP, false>(in, item.path0, 0, total, true, smem, slot, false); \
+            if (v == idx) wg_run<TT, LC, G, BATCH_B, MAP, PL_MEM>(in, item.path0, 0, total, true, smem, slot, false); \
         }                                                                                                    \
         ++idx;                                                                                               \
     }
@@ -1389,10 +1411,10 @@ __global__ void k_set_int(int *p, int v) { *p = v; }
 }  // namespace
 
 // ------------------------------------------------------------------ variant tables
-#define MMC_RES(TT, LC, G, B, MAP, LDS, NAME)                                                         \
-    Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, LDS ? 1 : 0, B, G,                      \
-            (LC ? lds_layout_bytes<TT>(LC, B, G, LDS) : 0), &launch_resident<TT, LC, G, B, MAP, LDS>,           \
-            (const void *)&k_resident<TT, LC, G, B, MAP, LDS>, 0},
+#define MMC_RES(TT, LC, G, B, MAP, PL, NAME)                                                          \
+    Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, (int)(PL), B, G,                       \
+            (LC ? lds_layout_bytes<TT>(LC, B, G, PL) : 0), &launch_resident<TT, LC, G, B, MAP, PL>,            \
+            (const void *)&k_resident<TT, LC, G, B, MAP, PL>, 0},
 
 #define MMC_WIN(TT, LC, B, D, GM, NAME)                                                               \
     Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, 0, B, B, win_lds_bytes<TT>(LC, B, D, GM),      \
@@ -1400,24 +1422,28 @@ __global__ void k_set_int(int *p, int v) { *p = v; }
 
 static const Variant k_variants[] = {
     // FP32, spins in LDS
-    MMC_RES(float, 8, 64, 256, COLZ, true, "f32-lds-L8-g64-b256")
-    MMC_RES(float, 8, 128, 256, COLZ, true, "f32-lds-L8-g128-b256")
-    MMC_RES(float, 8, 256, 256, COLZ, true, "f32-lds-L8-g256-b256")
-    MMC_RES(float, 10, 256, 256, COLZ, true, "f32-lds-L10-g256-b256")
-    MMC_RES(float, 12, 128, 256, FLAT, true, "f32-lds-L12-g128-b256")
-    MMC_RES(float, 12, 256, 256, FLAT, true, "f32-lds-L12-g256-b256")
-    MMC_RES(float, 16, 256, 256, COLZ, true, "f32-lds-L16-g256-b256")
-    MMC_RES(float, 16, 512, 512, COLZ, true, "f32-lds-L16-g512-b512")
-    MMC_RES(float, 16, 1024, 1024, COLZ, true, "f32-lds-L16-g1024-b1024")
-    MMC_RES(float, 0, 256, 256, FLAT, true, "f32-lds-any-g256-b256")
+    MMC_RES(float, 8, 64, 256, COLZ, PL_LDS, "f32-lds-L8-g64-b256")
+    MMC_RES(float, 8, 128, 256, COLZ, PL_LDS, "f32-lds-L8-g128-b256")
+    MMC_RES(float, 8, 256, 256, COLZ, PL_LDS, "f32-lds-L8-g256-b256")
+    MMC_RES(float, 10, 256, 256, COLZ, PL_LDS, "f32-lds-L10-g256-b256")
+    MMC_RES(float, 12, 128, 256, FLAT, PL_LDS, "f32-lds-L12-g128-b256")
+    MMC_RES(float, 12, 256, 256, FLAT, PL_LDS, "f32-lds-L12-g256-b256")
+    MMC_RES(float, 16, 256, 256, COLZ, PL_LDS, "f32-lds-L16-g256-b256")
+    MMC_RES(float, 16, 512, 512, COLZ, PL_LDS, "f32-lds-L16-g512-b512")
+    MMC_RES(float, 16, 1024, 1024, COLZ, PL_LDS, "f32-lds-L16-g1024-b1024")
+    MMC_RES(float, 0, 256, 256, FLAT, PL_LDS, "f32-lds-any-g256-b256")
+    // colour 0 in LDS, colour 1 in device memory
+    MMC_RES(float, 24, 1024, 1024, FLAT, PL_SPLIT, "f32-split-L24-g1024-b1024")
+    MMC_RES(float, 30, 1024, 1024, COLZ, PL_SPLIT, "f32-split-L30-g1024-b1024")
+    MMC_RES(float, 0, 512, 512, FLAT, PL_SPLIT, "f32-split-any-g512-b512")
     // FP32, spins in device memory
-    MMC_RES(float, 24, 512, 512, FLAT, false, "f32-hbm-L24-g512-b512")
-    MMC_RES(float, 32, 512, 512, COLZ, false, "f32-hbm-L32-g512-b512")
-    MMC_RES(float, 32, 1024, 1024, COLZ, false, "f32-hbm-L32-g1024-b1024")
-    MMC_RES(float, 48, 512, 512, FLAT, false, "f32-hbm-L48-g512-b512")
-    MMC_RES(float, 64, 512, 512, COLZ, false, "f32-hbm-L64-g512-b512")
-    MMC_RES(float, 64, 1024, 1024, COLZ, false, "f32-hbm-L64-g1024-b1024")
-    MMC_RES(float, 0, 512, 512, FLAT, false, "f32-hbm-any-g512-b512")
+    MMC_RES(float, 24, 512, 512, FLAT, PL_MEM, "f32-hbm-L24-g512-b512")
+    MMC_RES(float, 32, 512, 512, COLZ, PL_MEM, "f32-hbm-L32-g512-b512")
+    MMC_RES(float, 32, 1024, 1024, COLZ, PL_MEM, "f32-hbm-L32-g1024-b1024")
+    MMC_RES(float, 48, 512, 512, FLAT, PL_MEM, "f32-hbm-L48-g512-b512")
+    MMC_RES(float, 64, 512, 512, COLZ, PL_MEM, "f32-hbm-L64-g512-b512")
+    MMC_RES(float, 64, 1024, 1024, COLZ, PL_MEM, "f32-hbm-L64-g1024-b1024")
+    MMC_RES(float, 0, 512, 512, FLAT, PL_MEM, "f32-hbm-any-g512-b512")
     // FP32, spins in device memory, z-pipelined window in LDS
     MMC_WIN(float, 24, 512, 2, false, "f32-win-L24-d2-b512")
     MMC_WIN(float, 24, 1024, 3, false, "f32-win-L24-d3-b1024")
@@ -1430,16 +1456,17 @@ static const Variant k_variants[] = {
     MMC_WIN(float, 48, 1024, 1, true, "f32-gwin-L48-d1-b1024")
     MMC_WIN(float, 64, 1024, 1, true, "f32-gwin-L64-d1-b1024")
     // FP64, spins in LDS
-    MMC_RES(double, 8, 64, 256, COLZ, true, "f64-lds-L8-g64-b256")
-    MMC_RES(double, 8, 256, 256, COLZ, true, "f64-lds-L8-g256-b256")
-    MMC_RES(double, 12, 256, 256, FLAT, true, "f64-lds-L12-g256-b256")
-    MMC_RES(double, 16, 512, 512, COLZ, true, "f64-lds-L16-g512-b512")
-    MMC_RES(double, 0, 256, 256, FLAT, true, "f64-lds-any-g256-b256")
+    MMC_RES(double, 8, 64, 256, COLZ, PL_LDS, "f64-lds-L8-g64-b256")
+    MMC_RES(double, 8, 256, 256, COLZ, PL_LDS, "f64-lds-L8-g256-b256")
+    MMC_RES(double, 12, 256, 256, FLAT, PL_LDS, "f64-lds-L12-g256-b256")
+    MMC_RES(double, 16, 512, 512, COLZ, PL_LDS, "f64-lds-L16-g512-b512")
+    MMC_RES(double, 0, 256, 256, FLAT, PL_LDS, "f64-lds-any-g256-b256")
+    MMC_RES(double, 0, 512, 512, FLAT, PL_SPLIT, "f64-split-any-g512-b512")
     // FP64, spins in device memory
-    MMC_RES(double, 16, 512, 512, COLZ, false, "f64-hbm-L16-g512-b512")
-    MMC_RES(double, 32, 512, 512, COLZ, false, "f64-hbm-L32-g512-b512")
-    MMC_RES(double, 64, 1024, 1024, COLZ, false, "f64-hbm-L64-g1024-b1024")
-    MMC_RES(double, 0, 512, 512, FLAT, false, "f64-hbm-any-g512-b512")
+    MMC_RES(double, 16, 512, 512, COLZ, PL_MEM, "f64-hbm-L16-g512-b512")
+    MMC_RES(double, 32, 512, 512, COLZ, PL_MEM, "f64-hbm-L32-g512-b512")
+    MMC_RES(double, 64, 1024, 1024, COLZ, PL_MEM, "f64-hbm-L64-g1024-b1024")
+    MMC_RES(double, 0, 512, 512, FLAT, PL_MEM, "f64-hbm-any-g512-b512")
     // FP64, window (small lattices: parity of the pipelined schedule with the oracle)
     MMC_WIN(double, 12, 256, 1, false, "f64-win-L12-d1-b256")
     MMC_WIN(double, 16, 256, 2, false, "f64-win-L16-d2-b256")
@@ -1458,24 +1485,24 @@ const Variant *variants(int *count)
 // LDS variants: a persistent kernel each; device-memory variants: the shared one
 // The kernel and launcher of a batch variant: its own kernel for an LDS variant, the shared
 // device-memory kernel otherwise (chosen at compile time, so no unused kernel is built).
-template <typename T, int LC, int G, int B, int MAP, bool LDS>
+template <typename T, int LC, int G, int B, int MAP, int PL>
 constexpr const void *batch_kernel_of()
 {
-    if constexpr (LDS) return (const void *)&k_batch<T, LC, G, B, MAP, true>;
+    if constexpr (PL != PL_MEM) return (const void *)&k_batch<T, LC, G, B, MAP, PL>;
     else return (const void *)&k_batch_mem<T>;
 }
 
-template <typename T, int LC, int G, int B, int MAP, bool LDS>
+template <typename T, int LC, int G, int B, int MAP, int PL>
 constexpr auto batch_launcher_of()
 {
-    if constexpr (LDS) return &launch_batch_v<T, LC, G, B, MAP, true>;
+    if constexpr (PL != PL_MEM) return &launch_batch_v<T, LC, G, B, MAP, PL>;
     else return &launch_batch_mem<T>;
 }
 
-#define MMC_BV(TT, LC, G, B, MAP, LDS, NAME)                                                         \
-    Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, LDS ? 1 : 0, B, G,                     \
-            (LC ? lds_layout_bytes<TT>(LC, B, G, LDS) : 0), nullptr,                                   \
-            batch_kernel_of<TT, LC, G, B, MAP, LDS>(), 0, batch_launcher_of<TT, LC, G, B, MAP, LDS>()},
+#define MMC_BV(TT, LC, G, B, MAP, PL, NAME)                                                          \
+    Variant{NAME, std::is_same<TT, double>::value ? 1 : 0, LC, (int)(PL), B, G,                      \
+            (LC ? lds_layout_bytes<TT>(LC, B, G, PL) : 0), nullptr,                                    \
+            batch_kernel_of<TT, LC, G, B, MAP, PL>(), 0, batch_launcher_of<TT, LC, G, B, MAP, PL>()},
 static const Variant k_batch_f32[] = {MMC_BATCH_VARIANTS_F32(MMC_BV)};
 static const Variant k_batch_f64[] = {MMC_BATCH_VARIANTS_F64(MMC_BV)};
 #undef MMC_BV
@@ -1507,7 +1534,7 @@ size_t batch_slot_bytes(int fp64, int variant, int L)
 {
     int n;
     const Variant *v = batch_variants(fp64, &n);
-    if (v[variant].lds) return 0;
+    if (v[variant].lds == PL_LDS) return 0;  // (a split variant sweeps colour 1 in its slot)
     return (size_t)(v[variant].block / v[variant].lanes) * 3 * (size_t)L * L * L * (fp64 ? 8 : 4);
 }
 

@@ -131,7 +131,7 @@ struct mmc_ctx {
         size_t off_items = 0, lds = 0;
         int n_slots = 0;                       // resident workgroups (the grid)
         double updates = 0;                    // Metropolis attempts of its items
-        size_t off_slots = 0, slot_bytes = 0;  // device-memory variants: this launch's spin slots
+        size_t off_slots = 0, slot_bytes = 0;  // device-memory and split variants: this launch's spin slots
     };
     std::vector<Launch> launches;
     size_t off_inst = 0, off_var = 0, off_head = 0, off_slots = 0;
@@ -1169,7 +1169,7 @@ static void batch_plan(mmc_ctx *c)
         if (names[g].find(vs[v].name) == std::string::npos) names[g] += (names[g].empty() ? "" : "+") + std::string(vs[v].name);
         const int ppi = mmc::batch_paths_per_item(c->fp64, v);
         lds[g] = std::max(lds[g], mmc::variant_lds_bytes(vs[v], in.L));
-        if (!vs[v].lds) slot[g] = std::max(slot[g], mmc::batch_slot_bytes(c->fp64, v, in.L));
+        slot[g] = std::max(slot[g], mmc::batch_slot_bytes(c->fp64, v, in.L));
         for (int p = 0; p < in.n_paths; p += ppi) {
             const int np = std::min(ppi, in.n_paths - p);
             work[g].push_back({(double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * np, {(int)i, p}});
@@ -1431,7 +1431,7 @@ static int batch_enqueue(mmc_ctx *c, hipStream_t s)
         b.items = reinterpret_cast<const mmc::BatchItem *>(c->ws + l.off_items);
         b.n_items = (int)l.items.size();
         b.head = reinterpret_cast<unsigned int *>(c->ws + c->off_head + 64 * k);
-        b.slots = c->ws + c->off_slots + l.off_slots;  // LDS variants: slot_bytes 0, never touched
+        b.slots = c->ws + c->off_slots + l.off_slots;  // all-LDS variants: slot_bytes 0, never touched
         b.slot_bytes = l.slot_bytes;
         b.n_slots = l.n_slots;
         e = mmc::launch_batch(b, c->fp64, l.variant, l.n_slots, l.lds, sk);

@@ -1,9 +1,11 @@
-"""Checkpoint and resume on the engines beyond the default ones: a run of a few sweeps, saved
+"""Checkpoint and resume on the engines beyond the default ones (2-D Ising, LDS and
+device-memory windows, the split placement): a run of a few sweeps, saved
 to a file, loaded into a new context and finished equals an uninterrupted run with the same
 kernel variant (the checkpoint records the variant's name). Spins and accept counts are
 exact everywhere; per-path sums are exact where the reduction order does not depend on where
-a run is split (the 2-D Ising model's integer sums), else equal to rounding (the window
-kernels sum a pass's partials in an order set by the pass length)."""
+a run is split (the 2-D Ising model's integer sums; the split placement's per-sweep sums),
+else equal to rounding (the window kernels sum a pass's partials in an order set by the pass
+length)."""
 import numpy as np
 import pytest
 
@@ -23,6 +25,8 @@ CASES = [
     ("ising", 20, 2.3, 6, 4, 7, "fp32", 1, None, 0, 5, 0.0),
     ("window-fp32", 24, 1.2, 3, 5, 6, "fp32", 0, "f32-win-L24-d2-b512", 5, 7, 1e-5),
     ("gwindow-fp64", 16, 1.3, 3, 4, 5, "fp64", 0, "f64-gwin-L16-d2-b256", 0, 3, 1e-14),
+    ("split-fp32", 24, 1.2, 2, 5, 6, "fp32", 0, "f32-split-L24-g1024-b1024", 5, 7, 0.0),
+    ("split-fp64", 10, 1.3, 3, 4, 5, "fp64", 0, "f64-split-any-g512-b512", 0, 3, 0.0),
 ]
 
 
