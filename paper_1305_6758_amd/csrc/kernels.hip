@@ -125,6 +125,11 @@ __device__ __forceinline__ double wave_sum(double v)
 
 enum Map { COLZ = 0, FLAT = 1 };
 
+// Where a path's spins live while it sweeps: all in device memory, all in LDS, or colour 0
+// in LDS and colour 1 in device memory (sides whose lattice is too large for LDS but half of
+// it is not: 22 <= L <= 30 in FP32).
+enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2 };
+
 // Everything a path group needs during its sweeps; path, key and counter word are
 // wave-uniform (each wave belongs to one path group).
 template <typename T>
@@ -184,36 +189,51 @@ struct Coef {
     float q;    // FP32 path: beta J log2(e)
 };
 
+// Element i of a spin array. For arrays in device memory (DEV) the index becomes an unsigned
+// 32-bit byte offset from the (wave-uniform) base, which the backend turns into a scalar base
+// plus a 32-bit vector offset instead of a 64-bit address per lane and component; LDS arrays
+// keep plain indexing, whose constant parts fold into the instructions' offset fields.
+template <bool DEV, typename T>
+__device__ __forceinline__ T &spin_at(T *base, int i)
+{
+    using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    if constexpr (DEV) return *reinterpret_cast<T *>(reinterpret_cast<Byte *>(base) + (uint32_t)i * (uint32_t)sizeof(T));
+    else return base[i];
+}
+
 // One Metropolis attempt at site s of colour c (own = this colour's spins, oth = the other
 // colour's), sweep k. Adds the resulting spin (and for the odd colour S . h) to the
-// measurement partials and the accepted count of the wave to nacc.
-template <typename T, bool ANG = false>
+// measurement partials and the accepted count of the wave to nacc. OWN_DEV / OTH_DEV: the
+// colour's spins are in device memory (addressing only; the arithmetic is the same).
+template <typename T, bool ANG = false, bool OWN_DEV = false, bool OTH_DEV = false>
 __device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const T *oth, int HALF, bool odd,
                                             const Site &s, uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy,
                                             T &pmz, unsigned long long &nacc)
 {
     const Words w = philox4x32_10((uint32_t)s.id, k, g.path, TAG_MET | g.ctr3, g.key0, g.key1);
-    const T sx = own[s.h], sy = own[HALF + s.h], sz = own[2 * HALF + s.h];
+    T *const ox = own, *const oy = own + HALF, *const oz = own + 2 * HALF;
+    const T *const tx = oth, *const ty = oth + HALF, *const tz = oth + 2 * HALF;
+    const T sx = spin_at<OWN_DEV>(ox, s.h), sy = spin_at<OWN_DEV>(oy, s.h), sz = spin_at<OWN_DEV>(oz, s.h);
     T hx, hy, hz;
     if constexpr (std::is_same<T, double>::value) {
         // h = ((((S_-x + S_+x) + S_-y) + S_+y) + S_-z) + S_+z, the reference order.
-        hx = oth[s.nb[0]];
-        hy = oth[HALF + s.nb[0]];
-        hz = oth[2 * HALF + s.nb[0]];
+        hx = spin_at<OTH_DEV>(tx, s.nb[0]);
+        hy = spin_at<OTH_DEV>(ty, s.nb[0]);
+        hz = spin_at<OTH_DEV>(tz, s.nb[0]);
 #pragma unroll
         for (int n = 1; n < 6; ++n) {
-            hx = hx + oth[s.nb[n]];
-            hy = hy + oth[HALF + s.nb[n]];
-            hz = hz + oth[2 * HALF + s.nb[n]];
+            hx = hx + spin_at<OTH_DEV>(tx, s.nb[n]);
+            hy = hy + spin_at<OTH_DEV>(ty, s.nb[n]);
+            hz = hz + spin_at<OTH_DEV>(tz, s.nb[n]);
         }
     } else {
         // FP32: pairwise tree (any order is a valid FP32 rounding of the same sum).
         T ax[6], ay[6], az[6];
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
-            ax[n] = oth[s.nb[n]];
-            ay[n] = oth[HALF + s.nb[n]];
-            az[n] = oth[2 * HALF + s.nb[n]];
+            ax[n] = spin_at<OTH_DEV>(tx, s.nb[n]);
+            ay[n] = spin_at<OTH_DEV>(ty, s.nb[n]);
+            az[n] = spin_at<OTH_DEV>(tz, s.nb[n]);
         }
         hx = ((ax[0] + ax[1]) + (ax[2] + ax[3])) + (ax[4] + ax[5]);
         hy = ((ay[0] + ay[1]) + (ay[2] + ay[3])) + (ay[4] + ay[5]);
@@ -234,9 +254,9 @@ __device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const 
         acc = Arith<float>::uni(w.w2) < __builtin_amdgcn_exp2f(cf.q * dot);
     }
     if (acc) {
-        own[s.h] = nx;
-        own[HALF + s.h] = ny;
-        own[2 * HALF + s.h] = nz;
+        spin_at<OWN_DEV>(ox, s.h) = nx;
+        spin_at<OWN_DEV>(oy, s.h) = ny;
+        spin_at<OWN_DEV>(oz, s.h) = nz;
     }
     const T fx = acc ? nx : sx, fy = acc ? ny : sy, fz = acc ? nz : sz;
     pmx += fx;
@@ -355,7 +375,7 @@ __device__ __forceinline__ LaneGeom make_lane_geom(int lane)
 //   z = z0 + DZ t with DZ = G / plane, else the lane owns columns lane + G t and every z
 //   (the wrap-around planes z = 0 and L-1 peeled off).
 //   FLAT (any L): lane owns half-indices lane + G s.
-template <typename T, int LC, int G, int MAP, bool SPLIT>
+template <typename T, int LC, int G, int MAP, int PL>
 __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, const LaneGeom &q, int c, uint32_t k,
                                            const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
                                            unsigned long long &nacc)
@@ -364,6 +384,7 @@ __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, const LaneGeom 
     const int HALF = L * L * L / 2;
     // (c is a constant after inlining, so each colour's address space is known statically;
     // colour 1 follows colour 0 unless the colours are split between LDS and device memory)
+    constexpr bool SPLIT = PL == PL_SPLIT, MEM = PL == PL_MEM;
     T *const sp1 = SPLIT ? g.sp1 : g.sp + 3 * HALF;
     T *own = c ? sp1 : g.sp;
     const T *oth = c ? g.sp : sp1;
@@ -378,7 +399,11 @@ __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, const LaneGeom 
     // parts of the LDS addresses into the instructions' offset fields)
     if constexpr ((G & (G - 1)) == 0) lane &= G - 1;
     else __builtin_assume(lane >= 0 && lane < G);
-    auto up = [&](const Site &s) { update_site<T>(g, own, oth, HALF, odd, s, k, cf, pe, pmx, pmy, pmz, nacc); };
+    auto up = [&](const Site &s) {
+        // colour 1 is in device memory for PL_SPLIT, both colours for PL_MEM
+        if (odd) update_site<T, false, MEM || SPLIT, MEM>(g, own, oth, HALF, odd, s, k, cf, pe, pmx, pmy, pmz, nacc);
+        else update_site<T, false, MEM, MEM || SPLIT>(g, own, oth, HALF, odd, s, k, cf, pe, pmx, pmy, pmz, nacc);
+    };
     if constexpr (MAP == COLZ && LC != 0) {
         constexpr int PLANE = LC * LC / 2;
         if constexpr (G >= PLANE) {
@@ -506,7 +531,7 @@ __device__ __attribute__((noinline)) void renorm_path(float *sp0, float *sp1, in
 // Sweeps [k0, k1) of one path group. All groups of the workgroup call this together (same
 // instance and sweep range), so __syncthreads() separates the half-sweeps of all of them.
 // Idle groups (path >= n_paths) and idle lanes still take every barrier.
-template <typename T, int LC, int G, int MAP, bool SPLIT>
+template <typename T, int LC, int G, int MAP, int PL>
 __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev &in, int k0, int k1, bool fresh)
 {
     const int L = LC ? LC : g.L;
@@ -522,7 +547,7 @@ __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev 
     constexpr int W = G / 64;  // waves per path group
     unsigned long long nacc = 0;  // this wave's accepted moves
 
-    T *const sp1 = SPLIT ? g.sp1 : nullptr;  // colour-1 spins when they do not follow colour 0
+    T *const sp1 = PL == PL_SPLIT ? g.sp1 : nullptr;  // colour-1 spins when they do not follow colour 0
     if (g.active && fresh) init_path<T, G>(g.sp, sp1, L, g.lane, g.path, g.key0, g.key1, g.ctr3, in.init);
     __syncthreads();
     LaneGeom geom{};
@@ -540,9 +565,9 @@ __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev 
             }
         }
         T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);
-        if (g.active) half_sweep<T, LC, G, MAP, SPLIT>(g, geom, 0, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+        if (g.active) half_sweep<T, LC, G, MAP, PL>(g, geom, 0, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
         __syncthreads();
-        if (g.active) half_sweep<T, LC, G, MAP, SPLIT>(g, geom, 1, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
+        if (g.active) half_sweep<T, LC, G, MAP, PL>(g, geom, 1, (uint32_t)k, cf, pe, pmx, pmy, pmz, nacc);
         const bool meas = k >= n_therm || k < trace_sweeps || k == k1 - 1;
         if (meas) {
             // sums over each 16-lane row; one lane per row leaves its row's four partials
@@ -623,11 +648,6 @@ __device__ __attribute__((noinline)) void copy_spins(T *__restrict__ dst, const 
     for (int t = lane; t < n; t += G) dst[t] = src[t];
 }
 
-// Where a path's spins live while it sweeps: all in device memory, all in LDS, or colour 0
-// in LDS and colour 1 in device memory (sides whose lattice is too large for LDS but half of
-// it is not: 22 <= L <= 30 in FP32).
-enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2 };
-
 // LDS bytes of one workgroup: spins (all of them, or colour 0), accumulators, reduction
 // slots (four partials per 16-lane row).
 template <typename T>
@@ -677,7 +697,7 @@ __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int
     load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
     if (IN_LDS && !fresh && g.active) copy_spins<G>(g.sp, gsp, (int)NL, g.lane);
     // (path_sweeps begins with a barrier)
-    path_sweeps<T, LC, G, MAP, PL == PL_SPLIT>(g, in, k0, k1, fresh);
+    path_sweeps<T, LC, G, MAP, PL>(g, in, k0, k1, fresh);
     if (IN_LDS && resident && g.active) copy_spins<G>(gsp, g.sp, (int)NL, g.lane);
     store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
 }
