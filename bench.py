@@ -78,17 +78,20 @@ SLOTS_PER_UPDATE_ISING = sum(n * VALU_PEAK / OP_RATES[op] for op, n in UPDATE_OP
 PLAIN_FP64_MAX_BYTES = 64 << 30
 
 
-def counters_file(workload):
+def counters_file(workload, kernel="k_batch_f32"):
+    """The committed counter summary of a workload's dominant kernel (family k_batch_f32,
+    k_resident_f32 or k_window_f32)."""
     short = workload[:-5] if workload.endswith("-fp32") else workload
-    return os.path.join(ROOT, "profiles", f"k_batch_f32_{short}_counters.md")
+    return os.path.join(ROOT, "profiles", f"{kernel}_{short}_counters.md")
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch from the committed counter summary of the workload, or None when
-    there is none or the kernels have changed since those counters were taken."""
+def measured_traffic(workload, kernel="k_batch_f32"):
+    """HBM bytes per launch from the committed counter summary of the workload's dominant
+    kernel, or None when there is none or the kernels have changed since those counters were
+    taken."""
     import hashlib
     try:
-        text = open(counters_file(workload)).read()
+        text = open(counters_file(workload, kernel)).read()
     except OSError:
         return None
     sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1305_6758_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()[:16]
@@ -468,6 +471,8 @@ def main():
     launched = re.findall(r"\[(\S+) block=\d+ workgroups=", plan)
     kernel_name = ("k_batch<float> " + " + ".join(launched)) if not single else (
         "k_window<float>" if "win-" in plan else "k_resident<float>")
+    kernel_family = kernel_name.split()[0].replace("<float>", "_f32")
+    traffic = measured_traffic(a.workload, kernel_family)
 
     golden_path = os.path.join(ROOT, "tests", "golden", f"oracle_{a.workload}.json")
     parity = None
@@ -497,7 +502,7 @@ def main():
         "data": "synthetic",
         "config": config,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(a.workload),
+                     "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": traffic,
                      "kernel": kernel_name, "kernel_ms": kms,
                      "lane_slots_per_update": SLOTS_PER_UPDATE_F32,
                      "ceiling_updates_per_s": VALU_PEAK / SLOTS_PER_UPDATE_F32,
@@ -508,7 +513,7 @@ def main():
         # the bound reported is the one the kernels come closer to; the other rides along
         gbs = hbm_bytes / (kms * 1e-3) / 1e9
         hbm = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-               "traffic": measured_traffic(a.workload), "kernel": kernel_name, "kernel_ms": kms,
+               "traffic": traffic, "kernel": kernel_name, "kernel_ms": kms,
                "bytes_per_update": {"device-memory": 36, "split": 18}, "hbm_updates_per_step": hbm_upd,
                "split_updates_per_step": split_upd}
         if hbm["frac"] > out["roofline"]["frac"]:
