@@ -88,7 +88,8 @@ typedef enum { MMC_MODEL_HEISENBERG3D = 0, MMC_MODEL_ISING2D = 1 } mmc_model;
 /* Where a path's spins live during a sweep. LDS: the whole lattice of one path in the
  * workgroup's LDS, or, where only half of it fits (compiled for L = 24 and 30 in FP32, any L
  * through the generic variants), its even-colour half in LDS and the odd colour in device
- * memory (variants named *-split-*). HBM: spins in device memory, one workgroup per path, sweeps inside
+ * memory (variants named *-split-*), or, where only a third fits (compiled for L = 32 in FP32),
+ * the even colour's x and y components in LDS and the rest in device memory (*-splitxy-*). HBM: spins in device memory, one workgroup per path, sweeps inside
  * one launch. WINDOW: spins in device memory, each workgroup (one path) running several
  * sweeps per pass, the half-sweeps pipelined over z-planes: either through a sliding window
  * of planes in LDS (compiled for L = 24, 30, 32 in FP32 and 12, 16 in FP64) or with every

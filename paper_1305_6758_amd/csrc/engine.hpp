@@ -65,7 +65,8 @@ struct Variant {
     const char *name;
     int fp64;        // 0: FP32, 1: FP64
     int L;           // compile-time side, 0 = any even L
-    int lds;         // 1: spins in LDS, 0: in device memory, 2: colour 0 in LDS, colour 1 in device memory
+    int lds;         // 1: spins in LDS, 0: in device memory, 2: colour 0 in LDS, colour 1 in device memory,
+                     // 3: colour 0's x and y components in LDS, the rest in device memory
     int block;       // threads per workgroup
     int lanes;       // threads per path (block % lanes == 0)
     size_t lds_bytes;                 // dynamic LDS per workgroup

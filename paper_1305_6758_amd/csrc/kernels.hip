@@ -125,10 +125,11 @@ __device__ __forceinline__ double wave_sum(double v)
 
 enum Map { COLZ = 0, FLAT = 1 };
 
-// Where a path's spins live while it sweeps: all in device memory, all in LDS, or colour 0
-// in LDS and colour 1 in device memory (sides whose lattice is too large for LDS but half of
-// it is not: 22 <= L <= 30 in FP32).
-enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2 };
+// Where a path's spins live while it sweeps: all in device memory, all in LDS, colour 0 in
+// LDS and colour 1 in device memory (sides whose lattice is too large for LDS but half of it
+// is not: 22 <= L <= 30 in FP32), or only colour 0's x and y components in LDS (a third of
+// the lattice: L = 32 and 34 in FP32).
+enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2, PL_SPLIT_XY = 3 };
 
 // Everything a path group needs during its sweeps; path, key and counter word are
 // wave-uniform (each wave belongs to one path group).
@@ -141,6 +142,7 @@ struct GroupCtx {
     T *sp;                            // colour-0 spins of this path while sweeping (LDS or device memory)
     T *sp1;                           // colour-1 spins (sp + 3 L^3 / 2, or device memory when only
                                       // colour 0 is in LDS)
+    T *sp0z;                          // colour-0 z components in device memory (PL_SPLIT_XY)
     double *shacc;                    // 16 doubles in LDS: the path's PathAcc while sweeping
     T *red;                           // LDS [16-lane rows of the group][4] measurement partials
 };
@@ -201,39 +203,49 @@ __device__ __forceinline__ T &spin_at(T *base, int i)
     else return base[i];
 }
 
-// One Metropolis attempt at site s of colour c (own = this colour's spins, oth = the other
-// colour's), sweep k. Adds the resulting spin (and for the odd colour S . h) to the
-// measurement partials and the accepted count of the wave to nacc. OWN_DEV / OTH_DEV: the
-// colour's spins are in device memory (addressing only; the arithmetic is the same).
-template <typename T, bool ANG = false, bool OWN_DEV = false, bool OTH_DEV = false>
-__device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const T *oth, int HALF, bool odd,
-                                            const Site &s, uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy,
-                                            T &pmz, unsigned long long &nacc)
+// Spins of the two colours as per-component arrays: own = the colour being updated, oth =
+// the other one (its components are the neighbours). DEV: a bit per component (x, y, z) set
+// when that component lives in device memory (addressing only; the arithmetic is the same).
+template <typename T>
+struct ColourView {
+    T *own[3];
+    const T *oth[3];
+};
+
+// One Metropolis attempt at site s of colour c, sweep k. Adds the resulting spin (and for the
+// odd colour S . h) to the measurement partials and the accepted count of the wave to nacc.
+// OWN_DEV / OTH_DEV: bit masks of the own / other colour's components in device memory.
+template <typename T, bool ANG = false, int OWN_DEV = 0, int OTH_DEV = 0>
+__device__ __forceinline__ void update_site_v(const GroupCtx<T> &g, const ColourView<T> &cv, bool odd, const Site &s,
+                                              uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
+                                              unsigned long long &nacc)
 {
     const Words w = philox4x32_10((uint32_t)s.id, k, g.path, TAG_MET | g.ctr3, g.key0, g.key1);
-    T *const ox = own, *const oy = own + HALF, *const oz = own + 2 * HALF;
-    const T *const tx = oth, *const ty = oth + HALF, *const tz = oth + 2 * HALF;
-    const T sx = spin_at<OWN_DEV>(ox, s.h), sy = spin_at<OWN_DEV>(oy, s.h), sz = spin_at<OWN_DEV>(oz, s.h);
+    T *const ox = cv.own[0], *const oy = cv.own[1], *const oz = cv.own[2];
+    const T *const tx = cv.oth[0], *const ty = cv.oth[1], *const tz = cv.oth[2];
+    constexpr bool OX = OWN_DEV & 1, OY = OWN_DEV & 2, OZ = OWN_DEV & 4;
+    constexpr bool TX = OTH_DEV & 1, TY = OTH_DEV & 2, TZ = OTH_DEV & 4;
+    const T sx = spin_at<OX>(ox, s.h), sy = spin_at<OY>(oy, s.h), sz = spin_at<OZ>(oz, s.h);
     T hx, hy, hz;
     if constexpr (std::is_same<T, double>::value) {
         // h = ((((S_-x + S_+x) + S_-y) + S_+y) + S_-z) + S_+z, the reference order.
-        hx = spin_at<OTH_DEV>(tx, s.nb[0]);
-        hy = spin_at<OTH_DEV>(ty, s.nb[0]);
-        hz = spin_at<OTH_DEV>(tz, s.nb[0]);
+        hx = spin_at<TX>(tx, s.nb[0]);
+        hy = spin_at<TY>(ty, s.nb[0]);
+        hz = spin_at<TZ>(tz, s.nb[0]);
 #pragma unroll
         for (int n = 1; n < 6; ++n) {
-            hx = hx + spin_at<OTH_DEV>(tx, s.nb[n]);
-            hy = hy + spin_at<OTH_DEV>(ty, s.nb[n]);
-            hz = hz + spin_at<OTH_DEV>(tz, s.nb[n]);
+            hx = hx + spin_at<TX>(tx, s.nb[n]);
+            hy = hy + spin_at<TY>(ty, s.nb[n]);
+            hz = hz + spin_at<TZ>(tz, s.nb[n]);
         }
     } else {
         // FP32: pairwise tree (any order is a valid FP32 rounding of the same sum).
         T ax[6], ay[6], az[6];
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
-            ax[n] = spin_at<OTH_DEV>(tx, s.nb[n]);
-            ay[n] = spin_at<OTH_DEV>(ty, s.nb[n]);
-            az[n] = spin_at<OTH_DEV>(tz, s.nb[n]);
+            ax[n] = spin_at<TX>(tx, s.nb[n]);
+            ay[n] = spin_at<TY>(ty, s.nb[n]);
+            az[n] = spin_at<TZ>(tz, s.nb[n]);
         }
         hx = ((ax[0] + ax[1]) + (ax[2] + ax[3])) + (ax[4] + ax[5]);
         hy = ((ay[0] + ay[1]) + (ay[2] + ay[3])) + (ay[4] + ay[5]);
@@ -254,9 +266,9 @@ __device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const 
         acc = Arith<float>::uni(w.w2) < __builtin_amdgcn_exp2f(cf.q * dot);
     }
     if (acc) {
-        spin_at<OWN_DEV>(ox, s.h) = nx;
-        spin_at<OWN_DEV>(oy, s.h) = ny;
-        spin_at<OWN_DEV>(oz, s.h) = nz;
+        spin_at<OX>(ox, s.h) = nx;
+        spin_at<OY>(oy, s.h) = ny;
+        spin_at<OZ>(oz, s.h) = nz;
     }
     const T fx = acc ? nx : sx, fy = acc ? ny : sy, fz = acc ? nz : sz;
     pmx += fx;
@@ -267,6 +279,17 @@ __device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const 
         else pe = fmaf(fz, hz, fmaf(fy, hy, fmaf(fx, hx, pe)));
     }
     nacc += (unsigned long long)__popcll(__ballot(acc));
+}
+
+// The same with each colour's components HALF apart (one array per colour, all in LDS or all
+// in device memory).
+template <typename T, bool ANG = false, bool OWN_DEV = false, bool OTH_DEV = false>
+__device__ __forceinline__ void update_site(const GroupCtx<T> &g, T *own, const T *oth, int HALF, bool odd,
+                                            const Site &s, uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy,
+                                            T &pmz, unsigned long long &nacc)
+{
+    const ColourView<T> cv{{own, own + HALF, own + 2 * HALF}, {oth, oth + HALF, oth + 2 * HALF}};
+    update_site_v<T, ANG, OWN_DEV ? 7 : 0, OTH_DEV ? 7 : 0>(g, cv, odd, s, k, cf, pe, pmx, pmy, pmz, nacc);
 }
 
 // Hides v from the optimizer's value tracking, keeping only that it is non-negative.
@@ -384,10 +407,14 @@ __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, const LaneGeom 
     const int HALF = L * L * L / 2;
     // (c is a constant after inlining, so each colour's address space is known statically;
     // colour 1 follows colour 0 unless the colours are split between LDS and device memory)
-    constexpr bool SPLIT = PL == PL_SPLIT, MEM = PL == PL_MEM;
+    constexpr bool SPLIT = PL == PL_SPLIT || PL == PL_SPLIT_XY, MEM = PL == PL_MEM, XY = PL == PL_SPLIT_XY;
+    // components in device memory (bit 0: x, 1: y, 2: z) of colour 0 and colour 1
+    constexpr int DEV0 = MEM ? 7 : (XY ? 4 : 0), DEV1 = (MEM || SPLIT) ? 7 : 0;
     T *const sp1 = SPLIT ? g.sp1 : g.sp + 3 * HALF;
-    T *own = c ? sp1 : g.sp;
-    const T *oth = c ? g.sp : sp1;
+    T *const c0[3] = {g.sp, g.sp + HALF, XY ? g.sp0z : g.sp + 2 * HALF};
+    T *const c1[3] = {sp1, sp1 + HALF, sp1 + 2 * HALF};
+    const ColourView<T> cv = c ? ColourView<T>{{c1[0], c1[1], c1[2]}, {c0[0], c0[1], c0[2]}}
+                               : ColourView<T>{{c0[0], c0[1], c0[2]}, {c1[0], c1[1], c1[2]}};
     const bool odd = c != 0;
     // The lane's site geometry and the sweep-independent part of its counters are cheap to
     // recompute here; an opaque lane index keeps the compiler from hoisting them for all of
@@ -400,9 +427,8 @@ __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, const LaneGeom 
     if constexpr ((G & (G - 1)) == 0) lane &= G - 1;
     else __builtin_assume(lane >= 0 && lane < G);
     auto up = [&](const Site &s) {
-        // colour 1 is in device memory for PL_SPLIT, both colours for PL_MEM
-        if (odd) update_site<T, false, MEM || SPLIT, MEM>(g, own, oth, HALF, odd, s, k, cf, pe, pmx, pmy, pmz, nacc);
-        else update_site<T, false, MEM, MEM || SPLIT>(g, own, oth, HALF, odd, s, k, cf, pe, pmx, pmy, pmz, nacc);
+        if (odd) update_site_v<T, false, DEV1, DEV0>(g, cv, odd, s, k, cf, pe, pmx, pmy, pmz, nacc);
+        else update_site_v<T, false, DEV0, DEV1>(g, cv, odd, s, k, cf, pe, pmx, pmy, pmz, nacc);
     };
     if constexpr (MAP == COLZ && LC != 0) {
         constexpr int PLANE = LC * LC / 2;
@@ -481,11 +507,11 @@ __device__ __forceinline__ void half_sweep(const GroupCtx<T> &g, const LaneGeom 
 
 // Initial state of Sec. 2.2 (Philox counter (id, 0, path, TAG_INIT)): the group's lanes take
 // the path's sites in a flat stride. sp0 / sp1: colour-0 / colour-1 spins (sp1 null: colour 1
-// follows colour 0). Out of line (runs once): inlined, it crashes the ROCm 7.2 optimizer
-// (SimplifyCFG).
+// follows colour 0); sp0z: colour 0's z components when they are apart from its x and y (else
+// null). Out of line (runs once): inlined, it crashes the ROCm 7.2 optimizer (SimplifyCFG).
 template <typename T, int G>
-__device__ __attribute__((noinline)) void init_path(T *sp0, T *sp1, int L, int lane, uint32_t path, uint32_t key0,
-                                                    uint32_t key1, uint32_t ctr3, int init)
+__device__ __attribute__((noinline)) void init_path(T *sp0, T *sp1, T *sp0z, int L, int lane, uint32_t path,
+                                                    uint32_t key0, uint32_t key1, uint32_t ctr3, int init)
 {
     const int HALF = L * L * L / 2;
     // mixed start: even paths from the random (sphere) start, odd paths ordered
@@ -504,27 +530,29 @@ __device__ __attribute__((noinline)) void init_path(T *sp0, T *sp1, int L, int l
             else Arith<T>::sphere(w.w0, w.w1, x, y, z);
         }
         T *own = c ? (sp1 ? sp1 : sp0 + 3 * HALF) : sp0;
+        T *ownz = (!c && sp0z) ? sp0z : own + 2 * HALF;
         own[h] = x;
         own[HALF + h] = y;
-        own[2 * HALF + h] = z;
+        ownz[h] = z;
     }
 }
 
-// FP32 only: S <- S / |S| for every site of the path (each site touched by one lane; sp0 and
-// sp1 as for init_path). Out of line (runs every renorm_every sweeps): inlined, it crashes the
-// ROCm 7.2 optimizer (SimplifyCFG).
+// FP32 only: S <- S / |S| for every site of the path (each site touched by one lane; sp0, sp1
+// and sp0z as for init_path). Out of line (runs every renorm_every sweeps): inlined, it
+// crashes the ROCm 7.2 optimizer (SimplifyCFG).
 template <int G>
-__device__ __attribute__((noinline)) void renorm_path(float *sp0, float *sp1, int L, int lane)
+__device__ __attribute__((noinline)) void renorm_path(float *sp0, float *sp1, float *sp0z, int L, int lane)
 {
     const int HALF = L * L * L / 2;
     for (int t = lane; t < 2 * HALF; t += G) {
         const int c = t >= HALF, h = t - c * HALF;
         float *own = c ? (sp1 ? sp1 : sp0 + 3 * HALF) : sp0;
-        const float x = own[h], y = own[HALF + h], z = own[2 * HALF + h];
+        float *ownz = (!c && sp0z) ? sp0z : own + 2 * HALF;
+        const float x = own[h], y = own[HALF + h], z = ownz[h];
         const float r = __builtin_amdgcn_rsqf(fmaf(z, z, fmaf(y, y, x * x)));
         own[h] = x * r;
         own[HALF + h] = y * r;
-        own[2 * HALF + h] = z * r;
+        ownz[h] = z * r;
     }
 }
 
@@ -547,8 +575,10 @@ __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev 
     constexpr int W = G / 64;  // waves per path group
     unsigned long long nacc = 0;  // this wave's accepted moves
 
-    T *const sp1 = PL == PL_SPLIT ? g.sp1 : nullptr;  // colour-1 spins when they do not follow colour 0
-    if (g.active && fresh) init_path<T, G>(g.sp, sp1, L, g.lane, g.path, g.key0, g.key1, g.ctr3, in.init);
+    // colour-1 spins and colour-0 z components when they do not follow colour 0's x and y
+    T *const sp1 = (PL == PL_SPLIT || PL == PL_SPLIT_XY) ? g.sp1 : nullptr;
+    T *const sp0z = PL == PL_SPLIT_XY ? g.sp0z : nullptr;
+    if (g.active && fresh) init_path<T, G>(g.sp, sp1, sp0z, L, g.lane, g.path, g.key0, g.key1, g.ctr3, in.init);
     __syncthreads();
     LaneGeom geom{};
     if constexpr (MAP == COLZ && ColzShape<LC, G>::FEW) {
@@ -560,7 +590,7 @@ __device__ __forceinline__ void path_sweeps(const GroupCtx<T> &g, const InstDev 
     for (int k = k0; k < k1; ++k) {
         if constexpr (std::is_same<T, float>::value) {
             if (renorm_every > 0 && k > 0 && k % renorm_every == 0) {
-                if (g.active) renorm_path<G>(g.sp, sp1, L, g.lane);
+                if (g.active) renorm_path<G>(g.sp, sp1, sp0z, L, g.lane);
                 __syncthreads();
             }
         }
@@ -654,7 +684,8 @@ template <typename T>
 __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, int pl)
 {
     const size_t ns = 3 * (size_t)L * L * L * sizeof(T);
-    return (size_t)(B / G) * (pl == PL_LDS ? ns : pl == PL_SPLIT ? ns / 2 : 0) + (size_t)(B / G) * 128 +
+    return (size_t)(B / G) * (pl == PL_LDS ? ns : pl == PL_SPLIT ? ns / 2 : pl == PL_SPLIT_XY ? ns / 3 : 0) +
+           (size_t)(B / G) * 128 +
            (size_t)(B / 16) * 4 * sizeof(T);
 }
 
@@ -663,7 +694,8 @@ __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, int p
 // the instance's resident array (resident = true: LDS spins are loaded from and stored back
 // to it) or a batch slot. The caller passes the base explicitly: a select between the two
 // crashes the ROCm 7.2 optimizer (SimplifyCFG). PL: a Place; with PL_SPLIT colour 1 is swept
-// in place in device memory and only colour 0 is copied to and from LDS.
+// in place in device memory and only colour 0 is copied to and from LDS (PL_SPLIT_XY: only
+// colour 0's x and y).
 template <typename T, int LC, int G, int B, int MAP, int PL>
 __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int k1, bool fresh, char *smem, T *gbase,
                                        bool resident)
@@ -684,8 +716,8 @@ __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int
     g.active = (int)g.path < in.n_paths;
     char *p = smem;
     T *lds_spins = reinterpret_cast<T *>(p);
-    // spin words of a path held in LDS
-    const size_t NL = PL == PL_LDS ? NS : PL == PL_SPLIT ? NS / 2 : 0;
+    // spin words of a path held in LDS (colour 0's x and y come first in the path's array)
+    const size_t NL = PL == PL_LDS ? NS : PL == PL_SPLIT ? NS / 2 : PL == PL_SPLIT_XY ? NS / 3 : 0;
     p += P * NL * sizeof(T);
     g.shacc = reinterpret_cast<double *>(p) + 16 * group;
     p += P * 128;
@@ -693,6 +725,7 @@ __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int
     T *gsp = gbase + (size_t)group * NS;
     g.sp = IN_LDS ? lds_spins + (size_t)group * NL : gsp;
     g.sp1 = PL == PL_LDS ? g.sp + NS / 2 : gsp + NS / 2;
+    g.sp0z = gsp + NS / 3;
 
     load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
     if (IN_LDS && !fresh && g.active) copy_spins<G>(g.sp, gsp, (int)NL, g.lane);
@@ -905,7 +938,7 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
     const int tid = g.lane, wave = tid >> 6, wl = tid & 63;
     unsigned long long nacc = 0;
 
-    if (g.active && fresh) init_path<T, B>(g.sp, nullptr, L, tid, g.path, g.key0, g.key1, g.ctr3, in.init);
+    if (g.active && fresh) init_path<T, B>(g.sp, nullptr, nullptr, L, tid, g.path, g.key0, g.key1, g.ctr3, in.init);
     __syncthreads();
     for (int ks = k0; ks < k1;) {
         int Dp = k1 - ks < D ? k1 - ks : D;
@@ -928,7 +961,7 @@ __device__ __forceinline__ void path_sweeps_win(const GroupCtx<T> &g, const Inst
         if constexpr (GM) {
             // planes stay in device memory: normalise the whole lattice before the pass
             if constexpr (std::is_same<T, float>::value) {
-                if (rn && g.active) renorm_path<B>(g.sp, nullptr, L, tid);
+                if (rn && g.active) renorm_path<B>(g.sp, nullptr, nullptr, L, tid);
             }
         } else if (g.active) {
 #pragma unroll 1
@@ -1180,6 +1213,8 @@ constexpr int BATCH_B = 512;
     X(float, 24, 1024, 1024, FLAT, PL_SPLIT, "f32-split-L24-g1024")   \
     X(float, 30, 1024, 1024, COLZ, PL_SPLIT, "f32-split-L30-g1024")   \
     X(float, 0, 1024, 1024, FLAT, PL_SPLIT, "f32-split-any-g1024")    \
+    X(float, 32, 1024, 1024, COLZ, PL_SPLIT_XY, "f32-splitxy-L32-g1024") \
+    X(float, 0, 1024, 1024, FLAT, PL_SPLIT_XY, "f32-splitxy-any-g1024") \
     X(float, 24, 512, 512, FLAT, PL_MEM, "f32-hbm-L24-g512")          \
     X(float, 32, 512, 512, COLZ, PL_MEM, "f32-hbm-L32-g512")          \
     X(float, 48, 512, 512, FLAT, PL_MEM, "f32-hbm-L48-g512")          \
@@ -1456,6 +1491,9 @@ static const Variant k_variants[] = {
     MMC_RES(float, 24, 1024, 1024, FLAT, PL_SPLIT, "f32-split-L24-g1024-b1024")
     MMC_RES(float, 30, 1024, 1024, COLZ, PL_SPLIT, "f32-split-L30-g1024-b1024")
     MMC_RES(float, 0, 512, 512, FLAT, PL_SPLIT, "f32-split-any-g512-b512")
+    // colour 0's x and y in LDS, the rest in device memory
+    MMC_RES(float, 32, 1024, 1024, COLZ, PL_SPLIT_XY, "f32-splitxy-L32-g1024-b1024")
+    MMC_RES(float, 0, 512, 512, FLAT, PL_SPLIT_XY, "f32-splitxy-any-g512-b512")
     // FP32, spins in device memory
     MMC_RES(float, 24, 512, 512, FLAT, PL_MEM, "f32-hbm-L24-g512-b512")
     MMC_RES(float, 32, 512, 512, COLZ, PL_MEM, "f32-hbm-L32-g512-b512")
@@ -1482,6 +1520,7 @@ static const Variant k_variants[] = {
     MMC_RES(double, 16, 512, 512, COLZ, PL_LDS, "f64-lds-L16-g512-b512")
     MMC_RES(double, 0, 256, 256, FLAT, PL_LDS, "f64-lds-any-g256-b256")
     MMC_RES(double, 0, 512, 512, FLAT, PL_SPLIT, "f64-split-any-g512-b512")
+    MMC_RES(double, 0, 512, 512, FLAT, PL_SPLIT_XY, "f64-splitxy-any-g512-b512")
     // FP64, spins in device memory
     MMC_RES(double, 16, 512, 512, COLZ, PL_MEM, "f64-hbm-L16-g512-b512")
     MMC_RES(double, 32, 512, 512, COLZ, PL_MEM, "f64-hbm-L32-g512-b512")

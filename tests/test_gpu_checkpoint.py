@@ -27,6 +27,7 @@ CASES = [
     ("gwindow-fp64", 16, 1.3, 3, 4, 5, "fp64", 0, "f64-gwin-L16-d2-b256", 0, 3, 1e-14),
     ("split-fp32", 24, 1.2, 2, 5, 6, "fp32", 0, "f32-split-L24-g1024-b1024", 5, 7, 0.0),
     ("split-fp64", 10, 1.3, 3, 4, 5, "fp64", 0, "f64-split-any-g512-b512", 0, 3, 0.0),
+    ("splitxy-fp32", 32, 1.4, 2, 3, 4, "fp32", 0, "f32-splitxy-L32-g1024-b1024", 3, 4, 0.0),
 ]
 
 

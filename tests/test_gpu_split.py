@@ -1,5 +1,6 @@
-"""The split placement: colour 0 of each path in LDS, colour 1 swept in place in device memory
-(variants *-split-*). FP64 reproduces the oracle like every other FP64 kernel; FP32 gives
+"""The split placements: colour 0 of each path in LDS and colour 1 swept in place in device
+memory (variants *-split-*), or only colour 0's x and y components in LDS (*-splitxy-*).
+FP64 reproduces the oracle like every other FP64 kernel; FP32 gives
 spins and accept counts bit-identical to the device-memory kernels (a site's update does not
 depend on where its spins live), including renormalisation and runs split at any sweep; the
 batch forms run beside LDS and device-memory kernels in one batch."""
@@ -17,16 +18,19 @@ def say(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("L", [2, 6, 10, 20])
-def test_fp64_split_matches_oracle(L):
-    """Generic FP64 split variant against the oracle: results, per-sweep trace and final spins
-    within 1e-12 (L = 20: colour 0 takes 96 KB of LDS, the whole lattice would not fit)."""
+@pytest.mark.parametrize("L,variant", [(2, "f64-split-any-g512-b512"), (6, "f64-split-any-g512-b512"),
+                                       (10, "f64-split-any-g512-b512"), (20, "f64-split-any-g512-b512"),
+                                       (4, "f64-splitxy-any-g512-b512"), (10, "f64-splitxy-any-g512-b512"),
+                                       (24, "f64-splitxy-any-g512-b512")])
+def test_fp64_split_matches_oracle(L, variant):
+    """Generic FP64 split variants against the oracle: results, per-sweep trace and final spins
+    within 1e-12 (L = 20: colour 0 takes 96 KB of LDS; L = 24: colour 0's x and y take 110 KB;
+    the whole lattice would fit in neither)."""
     n, nt, nm, T = 3, 3, 4, 1.3
-    say(f"case fp64 split L={L}")
+    say(f"case fp64 split L={L} {variant}")
     ora = oracle_run(L, T, n, nt, nm, trace=nt + nm, want_spins=True)
-    eng, tr, sp, plan, _ = engine_run(L, T, n, nt, nm, trace=nt + nm, spins_of=range(n),
-                                      variant="f64-split-any-g512-b512")
-    assert plan == "f64-split-any-g512-b512"
+    eng, tr, sp, plan, _ = engine_run(L, T, n, nt, nm, trace=nt + nm, spins_of=range(n), variant=variant)
+    assert plan == variant
     assert_results_close(eng, ora, TOL64)
     assert max_abs_diff(tr, ora["trace"]) <= TOL64
     for p in range(n):
@@ -34,7 +38,8 @@ def test_fp64_split_matches_oracle(L):
 
 
 @pytest.mark.parametrize("L,variant", [(24, "f32-split-L24-g1024-b1024"), (30, "f32-split-L30-g1024-b1024"),
-                                       (14, "f32-split-any-g512-b512")])
+                                       (14, "f32-split-any-g512-b512"), (32, "f32-splitxy-L32-g1024-b1024"),
+                                       (14, "f32-splitxy-any-g512-b512")])
 def test_fp32_split_bitwise_equals_device_memory_kernel(L, variant):
     """FP32 split variants against the generic device-memory kernel: identical final spins and
     accept counts, with renormalisation every 4 sweeps; energies equal to FP32 rounding."""
@@ -53,12 +58,15 @@ def test_fp32_split_bitwise_equals_device_memory_kernel(L, variant):
 
 
 def test_fp32_split_batch_equals_device_memory_batch():
-    """A batch of L = 24 and L = 30 instances (ragged path counts) on each split batch variant
+    """A batch of L = 24, 30 and 32 instances (ragged path counts) on each split batch variant
     and on the device-memory batch kernel: identical accept counts, final energies equal to
     FP32 rounding."""
     from paper_1305_6758_amd import mmc
-    insts = [(24, 1.3, 1.0, 3, 4, 3), (30, 1.4, 1.0, 2, 3, 4), (30, 1.45, 1.0, 3, 2, 2)]
-    runs = [("f32-hbm-any-g512",), ("f32-split-any-g1024",), ("f32-split-L24-g1024", "f32-split-L30-g1024")]
+    insts = [(24, 1.3, 1.0, 3, 4, 3), (30, 1.4, 1.0, 2, 3, 4), (30, 1.45, 1.0, 3, 2, 2), (32, 1.44, 1.0, 2, 3, 3)]
+    # (pinned in order: a later pin takes every instance it fits, so the colour split, which
+    # does not fit L = 32, comes after the generic x/y split)
+    runs = [("f32-hbm-any-g512",), ("f32-splitxy-any-g1024", "f32-split-any-g1024"),
+            ("f32-split-L24-g1024", "f32-split-L30-g1024", "f32-splitxy-L32-g1024")]
     got = []
     for pins in runs:
         say(f"case batch split {pins}")
