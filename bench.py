@@ -460,13 +460,16 @@ def main():
     kms = sum(kernel_ms) / len(kernel_ms)
     achieved = SLOTS_PER_UPDATE_F32 * upd_step / (kms * 1e-3)
     # Algorithmic device-memory bytes per update: 36 for the device-memory variants (read own
-    # 12 B, write 12 B, read the other colour 12 B per half-sweep), 18 for the split variants
+    # 12 B, write 12 B, read the other colour 12 B per half-sweep), 18 for the colour split
     # (colour 1 in device memory: read once per colour-0 update, read and written per colour-1
-    # update), none for LDS-resident lattices.
+    # update), 24 for the x/y split (as the colour split, plus colour 0's z: read and written
+    # per colour-0 update, read once per colour-1 update), none for LDS-resident lattices.
     variants = plan.split(";", 1)[1].split() if ";" in plan else [plan]
-    hbm_upd = sum(p * L ** 3 * (nt + nm) for (L, T, p, nt, nm), v in zip(instances, variants) if "-hbm-" in v)
-    split_upd = sum(p * L ** 3 * (nt + nm) for (L, T, p, nt, nm), v in zip(instances, variants) if "-split-" in v)
-    hbm_bytes = 36.0 * hbm_upd + 18.0 * split_upd
+    bytes_per_update = {"-hbm-": 36.0, "-split-": 18.0, "-splitxy-": 24.0}
+    upd_of = {k: sum(p * L ** 3 * (nt + nm) for (L, T, p, nt, nm), v in zip(instances, variants) if k in v)
+              for k in bytes_per_update}
+    hbm_upd, split_upd = upd_of["-hbm-"], upd_of["-split-"] + upd_of["-splitxy-"]
+    hbm_bytes = sum(bytes_per_update[k] * upd_of[k] for k in bytes_per_update)
     # the batch runs one persistent kernel per variant in use: name them by their variants
     launched = re.findall(r"\[(\S+) block=\d+ workgroups=", plan)
     kernel_name = ("k_batch<float> " + " + ".join(launched)) if not single else (
@@ -514,7 +517,7 @@ def main():
         gbs = hbm_bytes / (kms * 1e-3) / 1e9
         hbm = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
                "traffic": traffic, "kernel": kernel_name, "kernel_ms": kms,
-               "bytes_per_update": {"device-memory": 36, "split": 18}, "hbm_updates_per_step": hbm_upd,
+               "bytes_per_update": {"device-memory": 36, "split": 18, "splitxy": 24}, "hbm_updates_per_step": hbm_upd,
                "split_updates_per_step": split_upd}
         if hbm["frac"] > out["roofline"]["frac"]:
             out["roofline_valu"] = out["roofline"]

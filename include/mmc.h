@@ -190,7 +190,7 @@ int mmc_tune(mmc_ctx *ctx);
 
 /* Pins the kernel variant of a context by the name mmc_plan reports, in place of the
  * tuner's choice; on a batch, the named batch variant for every instance it serves (call it
- * before mmc_bind). Spins and accept counts are the same under every variant;
+ * before mmc_bind; a later call takes over the instances both variants serve). Spins and accept counts are the same under every variant;
  * FP32 per-path sums follow the variant's reduction order, so a pinned variant reproduces
  * them bit for bit whatever the tuner would pick on another machine. Only valid before the
  * first run. MMC_EINVAL: NULL argument, unknown name, or a variant that does not fit this
@@ -280,7 +280,10 @@ mmc_ctx *mmc_load(const char *file);
 /* Wall time of the last run's GPU work in milliseconds (hipEvents on the context's stream). */
 double mmc_last_timing_ms(const mmc_ctx *ctx);
 
-/* Human-readable description of the chosen kernel variant(s), NUL-terminated. */
+/* Human-readable description of the chosen kernel variant(s), NUL-terminated: the variant's
+ * name for a single instance ("plain-f64" for the plain engine); for a batch
+ * "batch launches=N [<variants> block=B workgroups=W items=I] ...; L<side>:<variant> ..."
+ * (one bracket per persistent launch, then the variant of each instance in order). */
 int mmc_plan(const mmc_ctx *ctx, char *buf, size_t n);
 
 /* Frees the context and the device memory it allocated. NULL is ignored. */

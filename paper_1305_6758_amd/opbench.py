@@ -1,9 +1,11 @@
 """Measures gfx950 VALU instruction throughput (libmmc_opbench.so) and prints the issue cost
 of each instruction class in full-rate lane slots (v_add_f32 = 1), the unit of the engine's
 VALU roofline. With --copy-bytes B it instead runs one plain device-to-device copy of B bytes
-(torch), the calibration kernel for the HBM byte counters.
+(torch), the calibration kernel for the HBM byte counters; with --copy-reps R as well it then
+times R more copies (HIP events on torch's stream) and prints the bytes read and written per
+second, the streaming rate a memory-bound kernel can reach in practice.
 
-Usage: python -m paper_1305_6758_amd.opbench [--iters N] [--copy-bytes B]
+Usage: python -m paper_1305_6758_amd.opbench [--ms MS] [--copy-bytes B [--copy-reps R]]
 """
 import argparse
 import ctypes as C
@@ -17,6 +19,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--ms", type=float, default=50.0, help="target run time per instruction class")
     ap.add_argument("--copy-bytes", type=int, default=0)
+    ap.add_argument("--copy-reps", type=int, default=0)
     a = ap.parse_args()
     import torch
     if a.copy_bytes:
@@ -25,7 +28,18 @@ def main():
         torch.cuda.synchronize()
         y.copy_(x)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": a.copy_bytes}))
+        out = {"copy_bytes": a.copy_bytes}
+        if a.copy_reps > 0:
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(a.copy_reps):
+                y.copy_(x)
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / a.copy_reps
+            out.update({"copy_reps": a.copy_reps, "ms_per_copy": ms,
+                        "read_plus_write_TBps": 2 * a.copy_bytes / (ms * 1e-3) / 1e12})
+        print(json.dumps(out))
         return
     lib = C.CDLL(os.path.join(HERE, "libmmc_opbench.so"))
     lib.mmc_opbench_name.restype = C.c_char_p
