@@ -101,6 +101,31 @@ def measured_traffic(workload, kernel="k_batch_f32"):
     return float(fields["traffic_bytes_per_launch"])
 
 
+# Algorithmic device-memory bytes per update by placement (the variant name's marker): 36 for
+# the device-memory variants (read own 12 B, write 12 B, read the other colour 12 B per
+# half-sweep), 18 for the colour split (colour 1 in device memory: read once per colour-0
+# update, read and written per colour-1 update), 24 for the x/y split (as the colour split,
+# plus colour 0's z: read and written per colour-0 update, read once per colour-1 update);
+# LDS-resident lattices (and windows, whose traffic depends on the pass length) move none here.
+BYTES_PER_UPDATE = {"-hbm-": 36.0, "-split-": 18.0, "-splitxy-": 24.0}
+
+
+def device_memory_bytes(instances, plan):
+    """(algorithmic device-memory bytes of one step, updates on device-memory variants, updates
+    on split variants) for the instances and the plan string of their run (a single variant
+    name, or a batch plan whose part after ';' names each instance's variant)."""
+    variants = plan.split(";", 1)[1].split() if ";" in plan else [plan] * len(instances)
+    if len(variants) != len(instances):
+        raise ValueError(f"plan names {len(variants)} variants for {len(instances)} instances")
+    upd_of = dict.fromkeys(BYTES_PER_UPDATE, 0)
+    for (L, T, p, nt, nm), v in zip(instances, variants):
+        for k in BYTES_PER_UPDATE:
+            if k in v:
+                upd_of[k] += p * L ** 3 * (nt + nm)
+    total = sum(BYTES_PER_UPDATE[k] * upd_of[k] for k in BYTES_PER_UPDATE)
+    return total, upd_of["-hbm-"], upd_of["-split-"] + upd_of["-splitxy-"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -459,17 +484,7 @@ def main():
     value = upd_step * steps / wall
     kms = sum(kernel_ms) / len(kernel_ms)
     achieved = SLOTS_PER_UPDATE_F32 * upd_step / (kms * 1e-3)
-    # Algorithmic device-memory bytes per update: 36 for the device-memory variants (read own
-    # 12 B, write 12 B, read the other colour 12 B per half-sweep), 18 for the colour split
-    # (colour 1 in device memory: read once per colour-0 update, read and written per colour-1
-    # update), 24 for the x/y split (as the colour split, plus colour 0's z: read and written
-    # per colour-0 update, read once per colour-1 update), none for LDS-resident lattices.
-    variants = plan.split(";", 1)[1].split() if ";" in plan else [plan]
-    bytes_per_update = {"-hbm-": 36.0, "-split-": 18.0, "-splitxy-": 24.0}
-    upd_of = {k: sum(p * L ** 3 * (nt + nm) for (L, T, p, nt, nm), v in zip(instances, variants) if k in v)
-              for k in bytes_per_update}
-    hbm_upd, split_upd = upd_of["-hbm-"], upd_of["-split-"] + upd_of["-splitxy-"]
-    hbm_bytes = sum(bytes_per_update[k] * upd_of[k] for k in bytes_per_update)
+    hbm_bytes, hbm_upd, split_upd = device_memory_bytes(instances, plan)
     # the batch runs one persistent kernel per variant in use: name them by their variants
     launched = re.findall(r"\[(\S+) block=\d+ workgroups=", plan)
     kernel_name = ("k_batch<float> " + " + ".join(launched)) if not single else (

@@ -118,6 +118,24 @@ def test_bench_refuses_several_gpus():
     assert r.returncode == 2 and "one GPU" in r.stderr
 
 
+def test_bench_device_memory_bytes_by_placement():
+    """bench.py prices each instance by its variant's placement: 36 B per update in device
+    memory, 18 B for the colour split, 24 B for the x/y split, none in LDS or a window."""
+    sys.path.insert(0, ROOT)
+    import bench
+    insts = [(48, 1.0, 10, 1, 1), (32, 1.2, 4, 2, 2), (24, 1.4, 3, 1, 0), (16, 1.6, 5, 3, 3), (32, 1.8, 2, 1, 1)]
+    plan = ("batch launches=4 [...]; L48:f32-hbm-L48-g512 L32:f32-splitxy-L32-g1024 L24:f32-split-L24-g1024 "
+            "L16:f32-lds-L16-g512 L32:f32-hbm-any-g512")
+    total, hbm_upd, split_upd = bench.device_memory_bytes(insts, plan)
+    u = [p * L ** 3 * (nt + nm) for (L, T, p, nt, nm) in insts]
+    assert hbm_upd == u[0] + u[4] and split_upd == u[1] + u[2]
+    assert total == 36 * (u[0] + u[4]) + 24 * u[1] + 18 * u[2]
+    assert bench.device_memory_bytes([(32, 1.4, 8, 5, 5)], "f32-win-L32-d2-b1024") == (0, 0, 0)
+    assert bench.device_memory_bytes([(32, 1.4, 8, 5, 5)], "f32-split-L30-g1024-b1024")[0] == 18 * 8 * 32 ** 3 * 10
+    with pytest.raises(ValueError):
+        bench.device_memory_bytes(insts, "batch launches=1 [x]; L48:f32-hbm-L48-g512")
+
+
 def test_host_binder_crossing_and_r_match_oracle_statistics():
     """mmc_binder_cumulant, mmc_cumulant_crossing and mmc_distribution_coefficient (C++ host
     code) against the oracle's statistics on oracle snapshot output (n_meas = 1)."""
