@@ -151,8 +151,8 @@ typedef struct {
     int n_paths, n_therm, n_meas;
 } mmc_instance;
 
-/* Creates a single-instance context: L even and >= 2 (the checkerboard needs a bipartite
- * periodic lattice), T > 0 (T = +inf allowed: beta = 0), J finite, n_paths >= 1,
+/* Creates a single-instance context: L even, >= 2 (the checkerboard needs a bipartite
+ * periodic lattice) and L^3 <= 2^30 (L <= 1024), T > 0 (T = +inf allowed: beta = 0), J finite, n_paths >= 1,
  * n_therm >= 0, n_meas >= 0, n_therm + n_meas < 2^31. Nothing runs on the GPU until
  * mmc_run. Returns NULL on error (see mmc_last_error). Defaults as documented in
  * mmc_config. */

@@ -194,7 +194,9 @@ struct Coef {
 // Element i of a spin array. For arrays in device memory (DEV) the index becomes an unsigned
 // 32-bit byte offset from the (wave-uniform) base, which the backend turns into a scalar base
 // plus a 32-bit vector offset instead of a 64-bit address per lane and component; LDS arrays
-// keep plain indexing, whose constant parts fold into the instructions' offset fields.
+// keep plain indexing, whose constant parts fold into the instructions' offset fields. The
+// base is one colour-component array and i < L^3 / 2 <= 2^29 (instances are limited to
+// L^3 <= 2^30), so even an FP64 byte offset stays below 2^32.
 template <bool DEV, typename T>
 __device__ __forceinline__ T &spin_at(T *base, int i)
 {
