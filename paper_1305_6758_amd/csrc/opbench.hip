@@ -161,9 +161,68 @@ const Op k_ops[] = {
     {"update_mix", k_update_mix},
 };
 
+// Streaming copy of n 16-byte elements: each thread moves U elements per step (all loads
+// issued before the stores, 256 elements apart, so that a wave keeps U loads in flight),
+// grid-stride over the array. Every index is checked against n.
+template <int U>
+__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
+{
+    const size_t step = (size_t)gridDim.x * 256 * U;
+    for (size_t base = (size_t)blockIdx.x * 256 * U + threadIdx.x; base < n; base += step) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + (size_t)u * 256 < n) v[u] = src[base + (size_t)u * 256];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + (size_t)u * 256 < n) dst[base + (size_t)u * 256] = v[u];
+    }
+}
+
 }  // namespace
 
 extern "C" {
+
+// Time of one streaming copy of `bytes` (a multiple of 16) from src to dst (device pointers,
+// disjoint), averaged over reps launches after one warm-up, on the null stream;
+// blocks_per_cu x CUs workgroups of 256 threads, unroll 1, 2 or 4 elements per thread and
+// step. Returns 0, -1 on bad arguments, -3 on a HIP error.
+int mmc_opbench_copy(const void *src, void *dst, size_t bytes, int reps, int blocks_per_cu, int unroll, double *ms)
+{
+    if (!src || !dst || !ms || bytes == 0 || bytes % 16 || reps < 1 || blocks_per_cu < 1 || blocks_per_cu > 64)
+        return -1;
+    if (unroll != 1 && unroll != 2 && unroll != 4) return -1;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return -3;
+    const size_t n = bytes / 16;
+    const int blocks = cus * blocks_per_cu;
+    auto launch = [&]() {
+        const uint4 *s = static_cast<const uint4 *>(src);
+        uint4 *d = static_cast<uint4 *>(dst);
+        if (unroll == 1) hipLaunchKernelGGL(k_copy16<1>, dim3(blocks), dim3(256), 0, 0, s, d, n);
+        else if (unroll == 2) hipLaunchKernelGGL(k_copy16<2>, dim3(blocks), dim3(256), 0, 0, s, d, n);
+        else hipLaunchKernelGGL(k_copy16<4>, dim3(blocks), dim3(256), 0, 0, s, d, n);
+    };
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -3;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return -3;
+    }
+    launch();  // warm-up
+    (void)hipEventRecord(a, 0);
+    for (int r = 0; r < reps; ++r) launch();
+    (void)hipEventRecord(b, 0);
+    hipError_t e = hipEventSynchronize(b);
+    float t = 0;
+    (void)hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess || hipGetLastError() != hipSuccess) return -3;
+    *ms = t / reps;
+    return 0;
+}
 
 int mmc_opbench_count(void) { return (int)(sizeof(k_ops) / sizeof(k_ops[0])); }
 

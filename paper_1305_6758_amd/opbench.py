@@ -2,8 +2,9 @@
 of each instruction class in full-rate lane slots (v_add_f32 = 1), the unit of the engine's
 VALU roofline. With --copy-bytes B it instead runs one plain device-to-device copy of B bytes
 (torch), the calibration kernel for the HBM byte counters; with --copy-reps R as well it then
-times R more copies (HIP events on torch's stream) and prints the bytes read and written per
-second, the streaming rate a memory-bound kernel can reach in practice.
+times R more copies (HIP events on torch's stream), and R launches each of a hand-written
+16-byte streaming copy over a few launch shapes, and prints the bytes read and written per
+second: the streaming rate a memory-bound kernel can reach in practice.
 
 Usage: python -m paper_1305_6758_amd.opbench [--ms MS] [--copy-bytes B [--copy-reps R]]
 """
@@ -39,6 +40,21 @@ def main():
             ms = t0.elapsed_time(t1) / a.copy_reps
             out.update({"copy_reps": a.copy_reps, "ms_per_copy": ms,
                         "read_plus_write_TBps": 2 * a.copy_bytes / (ms * 1e-3) / 1e12})
+            # the hand-written streaming copy over a few launch shapes: the best of them
+            lib = C.CDLL(os.path.join(HERE, "libmmc_opbench.so"))
+            lib.mmc_opbench_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_int,
+                                             C.POINTER(C.c_double)]
+            shapes = {}
+            for bpc in (4, 8, 16):
+                for unroll in (1, 2, 4):
+                    t = C.c_double()
+                    rc = lib.mmc_opbench_copy(x.data_ptr(), y.data_ptr(), a.copy_bytes // 16 * 16, a.copy_reps, bpc,
+                                              unroll, C.byref(t))
+                    if rc != 0:
+                        raise RuntimeError(f"mmc_opbench_copy failed ({rc})")
+                    shapes[f"{bpc}x{unroll}"] = 2 * (a.copy_bytes // 16 * 16) / (t.value * 1e-3) / 1e12
+            best = max(shapes, key=shapes.get)
+            out["hand_copy_TBps"] = {"by_blocks_per_cu_x_unroll": shapes, "best": best, "best_TBps": shapes[best]}
         print(json.dumps(out))
         return
     lib = C.CDLL(os.path.join(HERE, "libmmc_opbench.so"))
