@@ -109,3 +109,29 @@ def test_fp64_mixed_batch_with_split_matches_oracle():
             assert_results_close(eng, ora, TOL64)
     finally:
         mmc.mmc_destroy(ctx)
+
+
+@pytest.mark.parametrize("variant", ["f64-split-any-g512-b512", "f64-splitxy-any-g512-b512"])
+def test_fp64_split_edge_cases_match_oracle(variant):
+    """The split placements at the edges: negative J, infinite temperature (every move
+    accepted), no measured sweeps (NaN means) and a nonzero instance id with a 64-bit seed,
+    each against the oracle to 1e-12."""
+    import math
+    say(f"case split edges {variant} J<0")
+    ora = oracle_run(6, 0.9, 3, 4, 4, J=-1.0)
+    eng, *_ = engine_run(6, 0.9, 3, 4, 4, J=-1.0, variant=variant)
+    assert_results_close(eng, ora, TOL64)
+    say(f"case split edges {variant} T=inf")
+    ora = oracle_run(8, math.inf, 3, 2, 3)
+    eng, *_ = engine_run(8, math.inf, 3, 2, 3, variant=variant)
+    assert_results_close(eng, ora, TOL64)
+    assert np.all(eng["n_accept"] == 512 * 5)
+    say(f"case split edges {variant} n_meas=0")
+    ora = oracle_run(8, 1.1, 3, 5, 0)
+    eng, *_ = engine_run(8, 1.1, 3, 5, 0, variant=variant)
+    assert np.all(np.isnan(eng["e_mean"]))
+    assert_results_close(eng, ora, TOL64)
+    say(f"case split edges {variant} instance/seed")
+    ora = oracle_run(8, 1.4, 3, 2, 2, seed=0xDEADBEEF12345, instance_id=77)
+    eng, *_ = engine_run(8, 1.4, 3, 2, 2, seed=0xDEADBEEF12345, instance_id=77, variant=variant)
+    assert_results_close(eng, ora, TOL64)
