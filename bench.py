@@ -357,7 +357,7 @@ def cpu_model():
 
 
 def binder_summary(instances, results):
-    """Cumulants of the four (L, T) instances, their ratio and the crossing (Sec. 5)."""
+    """Cumulants of the four (L, T) instances, their ratio and the crossing (Sec. 4)."""
     from paper_1305_6758_amd import mmc
     cum = [mmc.mmc_binder_cumulant(r) for r in results]
     T1, T2 = instances[0][1], instances[2][1]
@@ -369,7 +369,7 @@ def binder_summary(instances, results):
 
 
 def run_experiment(name, spec, steps):
-    """An experiment of Secs. 3-5 or of the 2-D Ising appendix through
+    """An experiment of Secs. 3-4 or of the 2-D Ising appendix through
     paper_1305_6758_amd.experiments; returns the JSON line."""
     from paper_1305_6758_amd import experiments as X
     from paper_1305_6758_amd.workloads import experiment_instances, site_count

@@ -61,7 +61,7 @@ typedef enum { MMC_FP32 = 0, MMC_FP64 = 1 } mmc_precision;
 
 /* Initial state (Sec. 2.2): SPHERE draws each spin uniformly on the sphere; ANGLES draws
  * both spherical angles uniformly (the paper's random start taken literally); ORDERED starts
- * with every spin along +z; MIXED is the two-start set-up of Sec. 4 (half of the paths from
+ * with every spin along +z; MIXED is the two-start set-up of Sec. 3 (half of the paths from
  * a random start, half ordered): paths with an even index start as SPHERE, odd ones ORDERED. */
 typedef enum { MMC_INIT_SPHERE = 0, MMC_INIT_ANGLES = 1, MMC_INIT_ORDERED = 2, MMC_INIT_MIXED = 3 } mmc_init;
 
@@ -245,7 +245,7 @@ int mmc_stats_from_results(const mmc_path_result *res, int n, int L, double T, m
  * Host only. MMC_EINVAL for null pointers or n < 2. */
 int mmc_binder_cumulant(const mmc_path_result *res, int n, double *U, double *se);
 
-/* Critical-temperature estimate from two lattice sizes L > L' at two temperatures (Sec. 5:
+/* Critical-temperature estimate from two lattice sizes L > L' at two temperatures (Sec. 4:
  * U_L(Tc)/U_L'(Tc) = 1), the ratio R(T) = U_L/U_L' taken linear between T1 and T2.
  * u = {U_L(T1), U_L'(T1), U_L(T2), U_L'(T2)}, se = their standard errors (independent runs).
  * Fills r_t1/se_r_t1, r_t2/se_r_t2 (the ratios and their errors), tc and its first-order error
@@ -266,7 +266,7 @@ int mmc_distribution_coefficient(const double *x, int n, double *r);
  * p = path_begin, path_begin + path_stride, ... < n_paths (stride 2 separates the two halves
  * of a MIXED start). out[k][5] = (<m>, its standard error, the coefficient of variation of
  * that mean per eq. (eq:cv), <e>, its standard error), m = |M| per site: the order parameter
- * and its cv against the number of sweeps, Sec. 4. Host only. MMC_EINVAL for null pointers,
+ * and its cv against the number of sweeps, Sec. 3. Host only. MMC_EINVAL for null pointers,
  * fewer than 2 selected paths, n_sweeps < 1 or path_stride < 1. */
 int mmc_trace_stats(const double *trace, int n_paths, int n_sweeps, int path_begin, int path_stride, double *out);
 

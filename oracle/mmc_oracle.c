@@ -303,7 +303,7 @@ static int metropolis_site(const mmco_params *p, double beta, double *spins, int
 }
 
 /* Initial state of Sec. 2.2 (per site, Philox((i, 0, path, TAG_INIT))). MIXED: the set-up of
- * Sec. 4 with half of the paths from a random start and half from the ordered one -- paths
+ * Sec. 3 with half of the paths from a random start and half from the ordered one -- paths
  * with an even index start uniformly on the sphere, odd ones ordered. */
 void mmco_init_state(const mmco_params *p, uint32_t path, mmco_state *st)
 {

@@ -12,11 +12,11 @@ Paper (arXiv:1305.6758):
     cross-path means of the per-path averaged moments;
   - Binder cumulant, eq. (kum): U_L = 1 - <M^4> / (3 <M^2>^2), with a first-order
     (delta-method) standard error from the cross-path covariance of (M^2, M^4);
-  - critical temperature from the cumulant ratio, Sec. 5 (Fig. TCfig): U_L(Tc)/U_L'(Tc) = 1,
+  - critical temperature from the cumulant ratio, Sec. 4 (Fig. TCfig): U_L(Tc)/U_L'(Tc) = 1,
     the ratio taken linear in T between the two simulated temperatures;
   - distribution coefficient, eq. (dist-coefficient), Sec. 3: least-squares line through
     the normal Q-Q plot, r = 1 - ||R||^2 / ((N-1) sigma^2);
-  - coefficient of variation of the mean, eq. (eq:cv), Sec. 4.1: sigma_X / (sqrt(N) mean).
+  - coefficient of variation of the mean, eq. (eq:cv), Sec. 3: sigma_X / (sqrt(N) mean).
 Q-Q plotting positions (the paper does not name them): Filliben's order-statistic medians.
 Normality p-value (the paper's Q-Q coefficient has no p-value): D'Agostino-Pearson K^2,
 from D'Agostino (1970) for skewness, Anscombe & Glynn (1983) for kurtosis, and the
@@ -131,7 +131,7 @@ def binder_cumulant(m2, m4):
 
 
 def cumulant_crossing(T1, T2, u, se):
-    """Sec. 5: the temperature where U_L / U_L' = 1, with the ratio R(T) taken linear between
+    """Sec. 4: the temperature where U_L / U_L' = 1, with the ratio R(T) taken linear between
     T1 and T2. u = (U_L(T1), U_L'(T1), U_L(T2), U_L'(T2)) and se their standard errors, all four
     estimates independent. Returns (Tc, se_Tc, R1, se_R1, R2, se_R2).
 
@@ -149,7 +149,7 @@ def cumulant_crossing(T1, T2, u, se):
 
 
 def trace_statistics(trace, path_begin=0, path_stride=1):
-    """Sec. 4 (Figs. TC_on_T, L10T1_T150_M_cv, ee): the order parameter <m> = <|M|> per site over
+    """Sec. 3 (Figs. TC_on_T, L10T1_T150_M_cv, ee): the order parameter <m> = <|M|> per site over
     paths and the coefficient of variation of that mean, eq. (eq:cv), after each sweep k; plus
     <e>. The state after sweep k of a path run longer is the final state of the same path run
     for k + 1 sweeps (same counters), so one traced run gives every sweep count at once.

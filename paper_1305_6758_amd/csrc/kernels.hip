@@ -1232,10 +1232,11 @@ constexpr int BATCH_B = 512;
     X(double, 0, 512, 512, FLAT, PL_MEM, "f64-hbm-any-g512")
 
 // The persistent batch kernel of one variant: workgroups take (instance, path group) items
-// of the variant from its queue until the queue is empty. One kernel per variant (a batch
-// launches those of the variants it uses one after another) lets each be compiled for its
-// own occupancy, as the single-instance kernels are: the device-memory variants need more
-// registers than the LDS ones.
+// of the variant from its queue until the queue is empty. One kernel per variant lets each
+// be compiled for its own occupancy, as the single-instance kernels are: the device-memory
+// variants need more registers than the LDS ones. (The host runs a batch's kernels side by
+// side on streams forked from the context's stream, or starts the LDS ones after the
+// device-memory kernel when they carry little of the work.)
 template <typename T, int LC, int G, int B, int MAP, int PL>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(target_waves<T>(LC, B, G, PL))))
 void k_batch(BatchDev bd)

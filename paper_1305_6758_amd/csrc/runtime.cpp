@@ -716,6 +716,10 @@ int mmc_tune(mmc_ctx *c)
     const int sweeps = 6 * (int)ceil(std::min(64.0, std::max(2.0, 2e8 / per_sweep)) / 6.0);
     int best = cand[0];
     double best_ms = 1e30;
+    // the candidates write the workspace: with caller memory bound, they wait for the work
+    // already queued on the caller's stream, and the caller's later work waits for them
+    int rc_order = begin_work(c);
+    if (rc_order) return rc_order;
     for (int i : cand) {
         time_single_candidate(c, i, 1);  // warm-up (code load)
         const double ms = time_single_candidate(c, i, sweeps);
@@ -724,6 +728,8 @@ int mmc_tune(mmc_ctx *c)
             best = i;
         }
     }
+    rc_order = end_work(c);
+    if (rc_order) return rc_order;
     if (best_ms >= 1e30) return fail(MMC_EHIP, "every tuning candidate failed to launch");
     in.variant = best;
     c->tuned = true;
@@ -1048,6 +1054,13 @@ mmc_ctx *mmc_load(const char *file)
         return nullptr;
     }
     vname[63] = 0;
+    // sweeps_done indexes the trace and divides the measured sums: it must be a sweep count
+    // of this run
+    if (done < 0 || (long long)done > (long long)n_therm + n_meas) {
+        fclose(f);
+        fail(MMC_EIO, "%s: sweep count %d outside 0..%lld", file, done, (long long)n_therm + n_meas);
+        return nullptr;
+    }
     mmc_ctx *c = mmc_create_ex(L, T, J, n_paths, n_therm, n_meas, seed, &cfg);
     if (!c) {
         fclose(f);

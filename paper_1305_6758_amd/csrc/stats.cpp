@@ -1,6 +1,6 @@
 // stats.cpp -- host FP64 cross-path statistics of the simulation output
 // (arXiv:1305.6758: eq. (MCAV), eq. (M_and_H), the moments <|M|^k>, eq. (cv), eq. (kum),
-// eq. (dist-coefficient), eq. (eq:cv), and the cumulant-ratio crossing of Sec. 5).
+// eq. (dist-coefficient), eq. (eq:cv), and the cumulant-ratio crossing of Sec. 4).
 #include <math.h>
 
 #include <algorithm>

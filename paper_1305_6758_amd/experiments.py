@@ -6,10 +6,10 @@ happens here.
 
   - binder_crossing: the O(3) critical temperature from the ratio of fourth-order cumulants
     U_30/U_20 at two temperatures, 10^6 single-output paths per (L, T) and 200 sweeps
-    (Sec. 5, eq. (kum));
+    (Sec. 4, eq. (kum));
   - thermalisation: the order parameter <|M|> and the coefficient of variation of its mean
     against the number of sweeps from one traced run, for any start (random, both-angles,
-    ordered, or the mixed half-and-half set-up with each half reported separately) (Sec. 4);
+    ordered, or the mixed half-and-half set-up with each half reported separately) (Sec. 3);
   - distribution_table: the distribution coefficient r of the single-output paths' H, M^x,
     M^y, M^z and |M^z| per temperature (Sec. 3, Table 1), for either proposal;
   - ising_magnetisation / ising_binder: the appendix's 2-D Ising runs -- the order parameter

@@ -24,7 +24,7 @@ WORKLOADS = {
     "L32-T1.443-p1024": dict(precision="both", instances=[(32, 1.443, 1024, 5000, 5000)]),
     # L = 64 at T = 1.443, 256 paths, device-memory spins, FP32.
     "L64-T1.443-p256-fp32": dict(precision="fp32", instances=[(64, 1.443, 256, 10000, 10000)]),
-    # Critical temperature from the Binder-cumulant ratio U_30/U_20 (Sec. 5): L = 30 and 20 at
+    # Critical temperature from the Binder-cumulant ratio U_30/U_20 (Sec. 4): L = 30 and 20 at
     # T = 1.44 and 1.45, 10^6 single-output paths each (random start, 200 sweeps, the final
     # state measured: 199 thermalisation sweeps + 1 measured sweep), FP32.
     "binder-L30-L20-p1e6-fp32": dict(precision="fp32", instances=[(L, T, 10 ** 6, 199, 1)
@@ -57,12 +57,12 @@ def uneven_batch():
 WORKLOADS["uneven-batch-96-fp32"] = dict(precision="fp32", instances=uneven_batch())
 
 
-# Experiments of Secs. 3 and 4 run through paper_1305_6758_amd.experiments (single-instance
+# Experiments of Sec. 3 run through paper_1305_6758_amd.experiments (single-instance
 # contexts: traced sweeps, or the plain FP64 engine for the both-angles proposal).
 TABLE1_TS = (0.6, 0.8, 1.0, 1.2, 1.4, 1.6)
 ISING_TS = (1.0, 1.5, 2.0, 2.1, 2.2, 2.269, 2.3, 2.4, 2.5, 3.0)
 EXPERIMENTS = {
-    # Sec. 4: L = 10, T = 1, 10^4 paths, half from a random start and half ordered, every one of
+    # Sec. 3: L = 10, T = 1, 10^4 paths, half from a random start and half ordered, every one of
     # 5000 sweeps traced; <m> and its cv per sweep for each half.
     "thermalisation-L10-T1-mixed-p1e4-fp32": dict(kind="thermalisation", L=10, T=1.0, n_paths=10 ** 4,
                                                   sweeps=5000, init="mixed", fp64=False),

@@ -1,4 +1,4 @@
-"""Parity of the Binder-cumulant experiment (Sec. 5, eq. (kum)) with the FP64 oracle.
+"""Parity of the Binder-cumulant experiment (Sec. 4, eq. (kum)) with the FP64 oracle.
 
 Workload binder-L30-L20-p1e6-fp32: L = 30 and 20 at T = 1.44 and 1.45, single-output paths
 (random start, 199 + 1 sweeps), instance ids 0..3 in (T, L) order. The oracle's results for the

@@ -336,7 +336,7 @@ def test_invalid_arguments_rejected():
 
 
 def test_mixed_start_every_engine():
-    """The mixed start of Sec. 4 (even paths random, odd paths ordered) on the LDS, device-memory
+    """The mixed start of Sec. 3 (even paths random, odd paths ordered) on the LDS, device-memory
     and plain FP64 engines and in a batch: trajectories and traces match the oracle."""
     from paper_1305_6758_amd import mmc
     ora = oracle_run(6, 1.1, 8, 3, 4, init="mixed", trace=7)

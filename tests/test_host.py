@@ -73,6 +73,28 @@ def test_load_rejects_missing_or_foreign_files(tmp_path):
         mmc.mmc_load(str(junk))
 
 
+@pytest.mark.parametrize("done", [-1, -(1 << 30), 7, 1 << 30])
+def test_load_rejects_sweep_count_out_of_range(tmp_path, done):
+    """A checkpoint whose sweep count lies outside 0 .. n_therm + n_meas (here 2 + 4) is
+    refused before any device work: the count indexes the trace and divides the measured sums.
+    The header is written field by field in the order mmc_save writes it."""
+    import ctypes as C
+    import struct
+    from paper_1305_6758_amd import mmc
+    L, n_paths, n_therm, n_meas = 8, 2, 2, 4
+    cfg = mmc.config(trace_sweeps=3)
+    head = (b"MMCCKPT2" + struct.pack("<iddiiiQ", L, 1.5, 1.0, n_paths, n_therm, n_meas, 1234)
+            + bytes(C.string_at(C.addressof(cfg), C.sizeof(cfg))) + struct.pack("<i", done)
+            + b"f32-lds-L8-g64-b256".ljust(64, b"\0"))
+    body = bytes(n_paths * 3 * L ** 3 * 4 + n_paths * 128 + n_paths * 3 * 4 * 8)
+    f = tmp_path / "ckpt.bin"
+    f.write_bytes(head + struct.pack("<Q", len(body)) + body)
+    with pytest.raises(mmc.MMCError) as e:
+        mmc.mmc_load(str(f))
+    assert e.value.code == mmc.MMC_EIO
+    assert "sweep count" in mmc.mmc_last_error()
+
+
 def test_host_statistics_match_oracle_statistics():
     """mmc_stats_from_results (C++ host code: AS241 quantiles, Filliben Q-Q fit, K^2) against
     the oracle's statistics (numpy, scipy ndtri) on real oracle output."""

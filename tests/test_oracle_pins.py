@@ -230,8 +230,71 @@ def test_open_chain_closed_forms(K):
     m2, se = S.mean_se(r["m2_mean"])
     exact_m2 = (N + 2.0 * sum((N - k) * u ** k for k in range(1, N))) / N ** 2
     assert within_4sigma(m2, se, exact_m2)
-    cvh, se = jackknife(lambda e2, e1: N / T ** 2 * (e2 - e1 * e1), r["e2_mean"], r["e_mean"])
+    # the heat capacity as oracle.stats.path_statistics computes it (eq. (cv)), not a retyped
+    # formula: a dropped N or T instead of T^2 (K != 1) fails here
+    cvh, se = path_statistic_jackknife(r, N, T, "cv_heat", dim=1)
     assert within_4sigma(cvh, se, (N - 1) / N * (1.0 - K * K / math.sinh(K) ** 2))
+
+
+def path_statistic_jackknife(res, L, T, key, dim=3, blocks=32):
+    """S.path_statistics(res)[key] over all paths and its delete-one-block jackknife standard
+    error (paths are independent; `blocks` contiguous groups of paths)."""
+    n = res["e_mean"].size
+    cols = ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean")
+    full = S.path_statistics({k: res[k] for k in cols}, L, T, dim=dim)[key]
+    edges = np.linspace(0, n, blocks + 1).astype(int)
+    loo = []
+    for b in range(blocks):
+        keep = np.r_[0:edges[b], edges[b + 1]:n]
+        loo.append(S.path_statistics({k: res[k][keep] for k in cols}, L, T, dim=dim)[key])
+    loo = np.asarray(loo)
+    return full, math.sqrt((blocks - 1) / blocks * ((loo - loo.mean()) ** 2).sum())
+
+
+def _two_spin_m_moments(K):
+    """<m> and <m^2> of two coupled spins, m = |S1 + S2| / 2 = sqrt(2 + 2c) / 2 with c = S1.S2
+    distributed with density proportional to exp(K c) on [-1, 1] (the joint law of two unit
+    vectors with weight exp(K S1.S2): S2's angle to S1 is uniform in cos, tilted by exp(K c))."""
+    import scipy.integrate as si
+    z = si.quad(lambda c: math.exp(K * c), -1.0, 1.0)[0]
+    m1 = si.quad(lambda c: 0.5 * math.sqrt(2.0 + 2.0 * c) * math.exp(K * c), -1.0, 1.0)[0] / z
+    m2 = si.quad(lambda c: 0.25 * (2.0 + 2.0 * c) * math.exp(K * c), -1.0, 1.0)[0] / z
+    return m1, m2
+
+
+@pytest.mark.parametrize("K", [0.5, 2.0])
+def test_susceptibility_two_spin_exact(K):
+    """chi of eq. (cv), chi = (N/T)(<m^2> - <m>^2) with m = |M| per site, as
+    oracle.stats.path_statistics computes it from oracle runs of two coupled spins (open chain,
+    N = 2), against the exact moments from one-dimensional quadrature. T = 1/K = 2 and 0.5,
+    so T^2 in place of T, or a dropped N, changes chi by a factor of 2 and fails; so does the
+    mean of m^2 taken in place of the mean of m (or the reverse)."""
+    T = 1.0 / K
+    r = O.run_paths(2, T, J=1.0, n_therm=40, n_meas=400, path_end=3000, dim=1, periodic=False)
+    m1, m2 = _two_spin_m_moments(K)
+    chi_exact = 2.0 / T * (m2 - m1 * m1)
+    chi, se = path_statistic_jackknife(r, 2, T, "chi", dim=1)
+    assert within_4sigma(chi, se, chi_exact), (chi, se, chi_exact)
+    # the factor-of-two alternatives lie far outside the bound
+    assert 4.0 * se < 0.25 * chi_exact
+
+
+@pytest.mark.parametrize("L,path,inst,seed,init", [(4, 0, 0, 1234, "sphere"), (6, 5, 3, 0x123456789ABCDEF, "sphere"),
+                                                   (4, 2, 1, 99, "angles")])
+def test_initial_state_stream(L, path, inst, seed, init):
+    """The random start of Sec. 2.2: every site's spin is the unit vector of words 0 and 1 of
+    Philox4x32-10 at counter (site id, 0, path, 0 | instance << 8) with key (seed_lo, seed_hi),
+    the words recomputed here with the independent numpy Philox. A start drawn from tag 1 (the
+    sweep-0 proposals), with the path and site words swapped, or without the instance or the
+    seed's high word fails."""
+    p = O.make_params(L, 1.5, seed=seed, instance=inst, init=init)
+    st = O.PathState(p, path)
+    N = L ** 3
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], dtype=np.uint32)
+    ctr = np.array([[i, 0, path, inst << 8] for i in range(N)], dtype=np.uint32)
+    w = P.philox4x32_10(ctr, key)
+    want = np.array([O.unit_vector(int(a), int(b), init) for a, b, _, _ in w])
+    assert np.array_equal(st.spins, want)
 
 
 def test_low_temperature_limit_3d():
@@ -413,7 +476,7 @@ def test_binder_cumulant_of_oracle_runs_at_infinite_temperature():
 
 
 def test_cumulant_crossing_exact_and_error():
-    """Sec. 5 crossing: a ratio linear in T through 1 at Tc gives Tc to rounding; the
+    """Sec. 4 crossing: a ratio linear in T through 1 at Tc gives Tc to rounding; the
     propagated error matches the spread of Tc under independent noise on the four cumulants."""
     Tc0, k = 1.442, -3.7
     T1, T2 = 1.44, 1.45
@@ -471,7 +534,7 @@ def test_angle_proposal_two_spin_law(K):
 
 
 def test_mixed_start_is_sphere_and_ordered_by_path_parity():
-    """The mixed start of Sec. 4 (half of the paths random, half ordered): even paths are the
+    """The mixed start of Sec. 3 (half of the paths random, half ordered): even paths are the
     random-start (sphere) paths and odd paths the ordered-start paths, bit for bit."""
     kw = dict(n_therm=3, n_meas=4, path_end=6, seed=9, instance=2)
     mix = O.run_paths(4, 1.2, init="mixed", want_spins=True, **kw)
@@ -486,7 +549,7 @@ def test_mixed_start_is_sphere_and_ordered_by_path_parity():
 
 
 def test_trace_statistics_against_scipy():
-    """Per-sweep statistics of a trace (Sec. 4: <m> and the coefficient of variation of the
+    """Per-sweep statistics of a trace (Sec. 3: <m> and the coefficient of variation of the
     mean, eq. (eq:cv)) against scipy's sem and variation of |M_k| computed directly."""
     r = O.run_paths(4, 1.2, n_therm=12, n_meas=0, path_end=30, init="mixed", trace_sweeps=12, seed=3)
     t = r["trace"]
