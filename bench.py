@@ -59,8 +59,8 @@ UPDATE_OPS_F32 = {
 # at 5.874e11 updates/s on one MI355X (`opbench` "update_mix"), i.e. 133.9 lane-slots of the
 # peak per update.
 SUMMED_SLOTS_PER_UPDATE_F32 = sum(n * VALU_PEAK / OP_RATES[op] for op, n in UPDATE_OPS_F32.items())
-UPDATE_MIX_UPDATES_PER_S = 5.8744e11
-SLOTS_PER_UPDATE_F32 = VALU_PEAK / UPDATE_MIX_UPDATES_PER_S
+# The mix's rate, hence the lane-slots per update, follows each box's sustained clock: it is
+# measured in the benchmarking process itself (measure_update_mix) right after the timed steps.
 # 2-D Ising update (per site): a quarter of one Philox4x32-10 call (one call serves four
 # sites); the field (3 adds), a = s h (multiply), the threshold index (2) and the
 # always-accept flag (2), the threshold select (4 cndmask) and compare, the flipped spin
@@ -107,7 +107,14 @@ def measured_traffic(workload, kernel="k_batch_f32"):
 # update, read and written per colour-1 update), 24 for the x/y split (as the colour split,
 # plus colour 0's z: read and written per colour-0 update, read once per colour-1 update);
 # LDS-resident lattices (and windows, whose traffic depends on the pass length) move none here.
-BYTES_PER_UPDATE = {"-hbm-": 36.0, "-split-": 18.0, "-splitxy-": 24.0}
+BYTES_PER_UPDATE = {"-hbm-": 36.0, "-split-": 18.0, "-splitxy-": 24.0, "-ring-": None}
+BYTES_PER_UPDATE_BY_KIND = {"device-memory": 36, "split": 18, "splitxy": 24, "ring": "24 + 24/L"}
+
+
+def ring_bytes_per_update(L):
+    """The plane ring reads each half-plane once per sweep plus four half-planes twice
+    (12 (2L + 4) / (2L) B per update) and writes every site once (12 B)."""
+    return 12.0 * (2 * L + 4) / (2 * L) + 12.0
 
 
 def device_memory_bytes(instances, plan):
@@ -118,28 +125,69 @@ def device_memory_bytes(instances, plan):
     if len(variants) != len(instances):
         raise ValueError(f"plan names {len(variants)} variants for {len(instances)} instances")
     upd_of = dict.fromkeys(BYTES_PER_UPDATE, 0)
+    total = 0.0
     for (L, T, p, nt, nm), v in zip(instances, variants):
         for k in BYTES_PER_UPDATE:
             if k in v:
-                upd_of[k] += p * L ** 3 * (nt + nm)
-    total = sum(BYTES_PER_UPDATE[k] * upd_of[k] for k in BYTES_PER_UPDATE)
-    return total, upd_of["-hbm-"], upd_of["-split-"] + upd_of["-splitxy-"]
+                upd = p * L ** 3 * (nt + nm)
+                upd_of[k] += upd
+                total += upd * (ring_bytes_per_update(L) if k == "-ring-" else BYTES_PER_UPDATE[k])
+    return total, upd_of["-hbm-"] + upd_of["-ring-"], upd_of["-split-"] + upd_of["-splitxy-"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measure_update_mix(target_ms=1500.0):
+    """The FP32 update's instruction mix alone (opbench's update_mix: the 81.5 algorithmic VALU
+    instructions of one update on independent register chains, no memory traffic) on this GPU,
+    in this process, run for about target_ms at full occupancy: its updates/s is the VALU
+    ceiling the sweep kernels are measured against. Also returns the mean shader clock of that
+    run (MHz, s_memtime cycles over wall-clock ticks)."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_1305_6758_amd", "libmmc_opbench.so"))
+    fn = lib.mmc_opbench_update_mix
+    fn.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    rate, ms, mhz = C.c_double(), C.c_double(), C.c_double()
+    iters = 4096
+    for _ in range(6):
+        rc = fn(iters, C.byref(rate), C.byref(ms), C.byref(mhz))
+        if rc != 0:
+            raise RuntimeError(f"mmc_opbench_update_mix failed ({rc})")
+        if ms.value >= 0.8 * target_ms:
+            break
+        iters = int(iters * min(64.0, max(2.0, target_ms / max(ms.value, 1e-3))))
+    log(f"update mix: {rate.value:.4e} updates/s over {ms.value:.0f} ms at {mhz.value:.0f} MHz")
+    return {"updates_per_s": rate.value, "ms": ms.value, "clock_mhz": mhz.value,
+            "lane_slots_per_update": VALU_PEAK / rate.value}
+
+
+def valu_roofline(updates, kernel_ms, mix, kernel):
+    """VALU roofline of a sweep kernel: the update mix's cost per update (lane-slots of the
+    published peak, from its rate measured on this GPU) times the updates, over the kernel time."""
+    slots = mix["lane_slots_per_update"]
+    achieved = slots * updates / (kernel_ms * 1e-3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "T VALU lane-op/s",
+            "frac": achieved / VALU_PEAK, "traffic": None, "kernel": kernel, "kernel_ms": kernel_ms,
+            "lane_slots_per_update": slots, "ceiling_updates_per_s": mix["updates_per_s"],
+            "ceiling_clock_mhz": mix["clock_mhz"],
+            "ceiling_source": "measured in this run: the update's instruction mix alone (opbench update_mix)"}
+
+
 def four_sigma_vs_oracle(results, golden):
-    """Per instance: |<x>_gpu - <x>_oracle| against 4 sqrt(SE_gpu^2 + SE_oracle^2) for x = e, |m|,
-    m^2, m^4. With fewer than 8 oracle paths per instance the oracle's own spread is no usable
-    error: the z-scores (using the GPU's per-path spread for both sides) are pooled over the
-    instances instead -- none beyond 4.5 and a mean square below 2."""
+    """Per instance and observable x = e, |m|, m^2, m^4: |<x>_gpu - <x>_oracle| against
+    4 sqrt(SE_gpu^2 + SE_oracle^2). SE_oracle is the oracle sample's standard deviation over
+    sqrt(K) when it holds K >= 16 paths; with fewer its own spread is too noisy an estimate
+    (a t-law with K - 1 degrees of freedom) and the GPU's per-path spread of the same instance
+    stands in for it (both sides sample the same law when the engine is right). With fewer
+    than 16 oracle paths the z-scores must also have a mean square below 2 over all instances
+    and observables (a systematic shift well inside each 4-sigma bound still fails that)."""
     import numpy as np
     out = []
     ok = True
     zs = []
-    pooled = golden.get("paths_per_instance", 8) < 8
+    small = golden.get("paths_per_instance", 16) < 16
     for inst, res in zip(golden["instances"], results):
         row = {"L": inst["L"], "T": inst["T"], "oracle_paths": len(inst["e_mean"])}
         for key in ("e_mean", "absm_mean", "m2_mean", "m4_mean"):
@@ -147,27 +195,27 @@ def four_sigma_vs_oracle(results, golden):
             b = np.asarray(inst[key])
             d = abs(a.mean() - b.mean())
             sa = a.std(ddof=1) / math.sqrt(a.size)
-            sb = (a.std(ddof=1) if pooled else b.std(ddof=1)) / math.sqrt(b.size)
+            sb = (a.std(ddof=1) if small else b.std(ddof=1)) / math.sqrt(b.size)
             bound = 4 * math.hypot(sa, sb)
             row[key] = {"gpu": float(a.mean()), "oracle": float(b.mean()), "diff": float(d), "bound_4sigma": float(bound)}
-            if pooled:
-                zs.append((a.mean() - b.mean()) / math.hypot(sa, sb))
-            else:
-                ok = bool(ok and d <= bound)
+            ok = bool(ok and d <= bound)
+            zs.append((a.mean() - b.mean()) / math.hypot(sa, sb))
         out.append(row)
-    if pooled:
+    if small:
         zs = np.asarray(zs)
-        ok = bool(np.max(np.abs(zs)) < 4.5 and np.mean(zs * zs) < 2.0)
+        ok = bool(ok and np.mean(zs * zs) < 2.0)
         out.append({"pooled_z": {"n": int(zs.size), "max_abs": float(np.max(np.abs(zs))),
                                  "mean_square": float(np.mean(zs * zs))}})
     return ok, out
 
 
-def run_batched(instances, steps, warmup):
+def run_batched(instances, steps, warmup, init="sphere"):
     import torch
     from paper_1305_6758_amd import mmc
+    inits = {"sphere": mmc.MMC_INIT_SPHERE, "angles": mmc.MMC_INIT_ANGLES, "ordered": mmc.MMC_INIT_ORDERED,
+             "mixed": mmc.MMC_INIT_MIXED}
     ctx = mmc.mmc_batch_create([(L, T, 1.0, p, nt, nm) for (L, T, p, nt, nm) in instances], 1234,
-                               mmc.config(precision=mmc.MMC_FP32))
+                               mmc.config(precision=mmc.MMC_FP32, init=inits[init]))
     ws = mmc.Workspace(ctx)
     plan = mmc.mmc_plan(ctx)
     log("plan:", plan)
@@ -226,17 +274,20 @@ def run_single(instance, steps, warmup, placement, variant=None):
     return wall, kernel_ms, results, stats, plan
 
 
-def run_plain_fp64(instances):
+def run_plain_fp64(instances, init="sphere"):
     """One pass of the same workload on the plain per-instance FP64 engine."""
     import torch
     from paper_1305_6758_amd import mmc
+    init_id = {"sphere": mmc.MMC_INIT_SPHERE, "angles": mmc.MMC_INIT_ANGLES, "ordered": mmc.MMC_INIT_ORDERED,
+               "mixed": mmc.MMC_INIT_MIXED}[init]
     total_ms = 0.0
     results = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i, (L, T, p, nt, nm) in enumerate(instances):
         ctx = mmc.mmc_create_ex(L, T, 1.0, p, nt, nm, 1234,
-                                mmc.config(precision=mmc.MMC_FP64, placement=mmc.MMC_PLACE_PLAIN, instance_id=i))
+                                mmc.config(precision=mmc.MMC_FP64, placement=mmc.MMC_PLACE_PLAIN, instance_id=i,
+                                           init=init_id))
         try:
             mmc.mmc_run(ctx)
             total_ms += mmc.mmc_last_timing_ms(ctx)
@@ -248,15 +299,16 @@ def run_plain_fp64(instances):
     return time.perf_counter() - t0, total_ms, results
 
 
-def cpu_baseline(instances, init="sphere", proposal="sphere", trace=False, ising=False):
+def cpu_baseline(instances, init="sphere", proposal="sphere", trace=False, ising=False, idx=None):
     """The FP64 CPU oracle as it stands, on the host cores, on a bounded sample of the
-    workload: paths of one instance (the second, or the only one), as many per thread as keep
+    workload: paths of one instance (idx; by default the second, or the only one), as many per thread as keep
     the sample near 1.5e8 updates per thread (about 15 s); where one path's full sweep count
     exceeds that, the sample paths run fewer sweeps (same thermalised/measured proportion) --
     the oracle's cost per update does not depend on the sweep count."""
     from oracle import oracle as O
     threads = O.max_threads()
-    idx = 1 if len(instances) > 1 else 0
+    if idx is None:
+        idx = 1 if len(instances) > 1 else 0
     L, T, p, nt, nm = instances[idx]
     N = L * L if ising else L ** 3
     budget = 1.5e8  # updates per thread
@@ -368,7 +420,7 @@ def binder_summary(instances, results):
             "tc": cross["tc"], "se_tc": cross["se_tc"]}
 
 
-def run_experiment(name, spec, steps):
+def run_experiment(name, spec, steps, mix):
     """An experiment of Secs. 3-4 or of the 2-D Ising appendix through
     paper_1305_6758_amd.experiments; returns the JSON line."""
     from paper_1305_6758_amd import experiments as X
@@ -407,13 +459,16 @@ def run_experiment(name, spec, steps):
         "kernel_updates_per_s": upd / (kms_avg * 1e-3),
         "experiment": {k: v for k, v in out.items() if k not in ("plan",)},
     }
-    if not spec["fp64"]:
-        slots = SLOTS_PER_UPDATE_ISING if ising else SLOTS_PER_UPDATE_F32
+    if not spec["fp64"] and not ising:
+        line["roofline"] = valu_roofline(upd, kms_avg, mix, kernel)
+    elif ising:
+        slots = SLOTS_PER_UPDATE_ISING
         achieved = slots * upd / (kms_avg * 1e-3)
         line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                             "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
                             "kernel": kernel, "kernel_ms": kms_avg, "lane_slots_per_update": slots,
-                            "ceiling_updates_per_s": VALU_PEAK / slots}
+                            "ceiling_updates_per_s": VALU_PEAK / slots,
+                            "ceiling_source": "summed instruction-class model (an upper estimate of the cost)"}
     else:
         # plain FP64 engine: 72 B of algorithmic device-memory traffic per update
         achieved = 72.0 * upd / (kms_avg * 1e-3)
@@ -421,6 +476,125 @@ def run_experiment(name, spec, steps):
                             "frac": achieved / 8e12, "traffic": None, "kernel": kernel, "kernel_ms": kms_avg,
                             "bytes_per_update": 72}
     return line, instances
+
+
+# The largest configuration: the uneven batch of 96 (L, T) instances, measured once per bench
+# run beside the stepped default workload.
+LARGEST = "uneven-batch-96-fp32"
+
+
+def parity_summary(rows):
+    """Compact form of four_sigma_vs_oracle's rows: the largest |diff| / bound over every
+    (instance, observable) and where it is."""
+    worst = (0.0, None)
+    n = 0
+    for r in rows:
+        for key in ("e_mean", "absm_mean", "m2_mean", "m4_mean"):
+            if key in r:
+                n += 1
+                q = r[key]["diff"] / r[key]["bound_4sigma"] if r[key]["bound_4sigma"] > 0 else float("inf")
+                if q > worst[0]:
+                    worst = (q, {"L": r["L"], "T": r["T"], "observable": key, **r[key]})
+    return {"comparisons": n, "max_diff_over_bound": worst[0], "worst": worst[1]}
+
+
+def measure_workload(name, steps, warmup, mix, a, plain_paths=None, compact=False):
+    """One batched (or single-instance) FP32 workload of workloads.WORKLOADS: `steps` timed
+    passes after `warmup` untimed ones, parity with the stored oracle sample, the VALU and
+    device-memory rooflines, the plain FP64 engine on the same seeds (all paths, or the first
+    plain_paths of each instance), and the oracle on the host cores. Returns the JSON record."""
+    import numpy as np
+    from paper_1305_6758_amd.workloads import WORKLOADS, updates
+    from paper_1305_6758_amd import mmc as _m
+    instances = WORKLOADS[name]["instances"]
+    upd_step = updates(instances)
+    single = len(instances) == 1
+    if single:
+        place = {"auto": _m.MMC_PLACE_AUTO, "lds": _m.MMC_PLACE_LDS, "hbm": _m.MMC_PLACE_HBM,
+                 "window": _m.MMC_PLACE_WINDOW}[a.placement]
+        wall, kernel_ms, results, stats, plan = run_single(instances[0], steps, warmup, place, a.variant)
+    else:
+        wall, kernel_ms, results, stats, plan = run_batched(instances, steps, warmup,
+                                                            init=WORKLOADS[name].get("init", "sphere"))
+    value = upd_step * steps / wall
+    kms = sum(kernel_ms) / len(kernel_ms)
+    hbm_bytes, hbm_upd, split_upd = device_memory_bytes(instances, plan)
+    # the batch runs one persistent kernel per variant in use: name them by their variants
+    launched = re.findall(r"\[(\S+) block=\d+ workgroups=", plan)
+    kernel_name = ("k_batch<float> " + " + ".join(launched)) if not single else (
+        "k_window<float>" if "win-" in plan else "k_resident<float>")
+    kernel_family = kernel_name.split()[0].replace("<float>", "_f32")
+    traffic = measured_traffic(name, kernel_family)
+    if mix is None:
+        mix = measure_update_mix()
+
+    golden_path = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
+    parity = None
+    if os.path.exists(golden_path):
+        with open(golden_path) as f:
+            ok, rows = four_sigma_vs_oracle(results, json.load(f))
+        parity = {"agree_4sigma": ok, **({"summary": parity_summary(rows)} if compact else {"per_instance": rows})}
+
+    Ls = sorted({x[0] for x in instances})
+    config = {"workload": name, "L": Ls[0] if len(Ls) == 1 else Ls,
+              "T": sorted({x[1] for x in instances}) if len(instances) <= 16 else [min(x[1] for x in instances),
+                                                                               max(x[1] for x in instances)],
+              "instances": len(instances),
+              "paths": sum(x[2] for x in instances), "n_therm": sorted({x[3] for x in instances}),
+              "n_meas": sorted({x[4] for x in instances}), "updates_per_step": upd_step, "seed": 1234,
+              "plan": plan, "engine": "single-instance, tuned" if single else "batch",
+              "init": WORKLOADS[name].get("init", "sphere")}
+    roof = valu_roofline(upd_step, kms, mix, kernel_name)
+    roof["traffic"] = traffic
+    out = {
+        "metric": METRIC, "value": value, "unit": "spin updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic", "config": config, "roofline": roof, "parity": parity,
+    }
+    if hbm_bytes > 0:
+        # the bound reported is the one the kernels come closer to; the other rides along
+        gbs = hbm_bytes / (kms * 1e-3) / 1e9
+        hbm = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+               "traffic": traffic, "kernel": kernel_name, "kernel_ms": kms,
+               "bytes_per_update": BYTES_PER_UPDATE_BY_KIND, "hbm_updates_per_step": hbm_upd,
+               "split_updates_per_step": split_upd}
+        if hbm["frac"] > out["roofline"]["frac"]:
+            out["roofline_valu"] = out["roofline"]
+            out["roofline"] = hbm
+        else:
+            out["roofline_hbm"] = hbm
+    if len(instances) <= 16:
+        out["stats"] = [{k: s[k] for k in ("mean_e", "se_e", "mean_absm", "se_absm", "chi", "cv_heat", "binder",
+                                           "r_e", "p_norm_e", "accept_rate")} for s in stats]
+    if name.startswith("binder-"):
+        out["experiment"] = binder_summary(instances, results)
+    plain_inst = [(L, T, min(p, plain_paths) if plain_paths else p, nt, nm) for (L, T, p, nt, nm) in instances]
+    fits = sum(p * 3 * 8 * L ** 3 for (L, T, p, nt, nm) in plain_inst) <= PLAIN_FP64_MAX_BYTES
+    if not a.skip_plain and fits:
+        pwall, pms, presults = run_plain_fp64(plain_inst, init=WORKLOADS[name].get("init", "sphere"))
+        pupd = updates(plain_inst)
+        out["fp64_plain"] = {"value": pupd / pwall, "unit": "spin updates/s", "kernel_ms": pms,
+                             "speedup_of_batched_fp32": value / (pupd / pwall)}
+        if plain_paths:
+            out["fp64_plain"]["sample"] = f"the first {plain_paths} paths of every instance, all sweeps ({pupd:.3e} updates)"
+        if os.path.exists(golden_path):
+            with open(golden_path) as f:
+                ok, rows = four_sigma_vs_oracle(presults, json.load(f))
+            out["fp64_plain"]["agree_4sigma"] = ok
+        cmp = fp32_vs_fp64(plain_inst, [{k: np.asarray(r[k])[:q[2]] for k in r} for r, q in zip(results, plain_inst)],
+                           presults)
+        if len(instances) <= 16:
+            out["fp32_vs_fp64"] = cmp
+        else:
+            within = [row[k]["within"] for row in cmp for k in ("e_mean", "absm_mean", "m2_mean", "m4_mean")]
+            out["fp32_vs_fp64"] = {"comparisons": len(within), "within_4sigma": int(sum(within)),
+                                   "max_abs_rel_diff": max(abs(row[k]["rel_diff"] or 0.0) for row in cmp
+                                                           for k in ("e_mean", "absm_mean"))}
+    if not a.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline(instances, init=WORKLOADS[name].get("init", "sphere"),
+                                           idx=None if len(instances) <= 16 else
+                                           max(range(len(instances)), key=lambda i: instances[i][0]))
+    return out, mix
 
 
 def main():
@@ -438,6 +612,8 @@ def main():
                          "file when set) and exit, so that a later (profiled) run launches only its steps")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-largest", action="store_true",
+                    help="default workload only: leave out the one-pass record of the uneven batch")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the engine runs its paths on a single MI355X; several GPUs "
@@ -445,7 +621,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    from paper_1305_6758_amd.workloads import EXPERIMENTS, WORKLOADS, updates
+    from paper_1305_6758_amd.workloads import EXPERIMENTS, WORKLOADS
     if a.workload not in WORKLOADS and a.workload not in EXPERIMENTS:
         print(f"unknown workload {a.workload}; one of {sorted(WORKLOADS) + sorted(EXPERIMENTS)}", file=sys.stderr)
         sys.exit(2)
@@ -454,11 +630,12 @@ def main():
         return
     if a.workload in EXPERIMENTS:
         spec = EXPERIMENTS[a.workload]
-        line, instances = run_experiment(a.workload, spec, a.steps or 1)
+        ising = spec.get("model", 0) == 1 or spec["kind"].startswith("ising")
+        mix = None if (spec["fp64"] or ising) else measure_update_mix()
+        line, instances = run_experiment(a.workload, spec, a.steps or 1, mix)
         if not a.skip_cpu:
             line["cpu_baseline"] = cpu_baseline(instances, init=spec["init"], proposal=spec.get("proposal", "sphere"),
-                                                trace=spec["kind"] == "thermalisation",
-                                                ising=spec.get("model", 0) == 1 or spec["kind"].startswith("ising"))
+                                                trace=spec["kind"] == "thermalisation", ising=ising)
         print(json.dumps(line), flush=True)
         return
     default = a.workload == WORKLOAD
@@ -467,96 +644,17 @@ def main():
     if steps < 1 or warmup < 0:
         print("need --steps >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
-    instances = WORKLOADS[a.workload]["instances"]
-    upd_step = updates(instances)
-
-    from paper_1305_6758_amd import mmc as _m
-    single = len(instances) == 1
-    if a.variant and not single:
+    if a.variant and len(WORKLOADS[a.workload]["instances"]) != 1:
         print("--variant applies to one-instance workloads only", file=sys.stderr)
         sys.exit(2)
-    if single:
-        place = {"auto": _m.MMC_PLACE_AUTO, "lds": _m.MMC_PLACE_LDS, "hbm": _m.MMC_PLACE_HBM,
-                 "window": _m.MMC_PLACE_WINDOW}[a.placement]
-        wall, kernel_ms, results, stats, plan = run_single(instances[0], steps, warmup, place, a.variant)
-    else:
-        wall, kernel_ms, results, stats, plan = run_batched(instances, steps, warmup)
-    value = upd_step * steps / wall
-    kms = sum(kernel_ms) / len(kernel_ms)
-    achieved = SLOTS_PER_UPDATE_F32 * upd_step / (kms * 1e-3)
-    hbm_bytes, hbm_upd, split_upd = device_memory_bytes(instances, plan)
-    # the batch runs one persistent kernel per variant in use: name them by their variants
-    launched = re.findall(r"\[(\S+) block=\d+ workgroups=", plan)
-    kernel_name = ("k_batch<float> " + " + ".join(launched)) if not single else (
-        "k_window<float>" if "win-" in plan else "k_resident<float>")
-    kernel_family = kernel_name.split()[0].replace("<float>", "_f32")
-    traffic = measured_traffic(a.workload, kernel_family)
-
-    golden_path = os.path.join(ROOT, "tests", "golden", f"oracle_{a.workload}.json")
-    parity = None
-    if os.path.exists(golden_path):
-        with open(golden_path) as f:
-            ok, rows = four_sigma_vs_oracle(results, json.load(f))
-        parity = {"agree_4sigma": ok, "per_instance": rows}
-
-    Ls = sorted({x[0] for x in instances})
-    config = {"workload": a.workload, "L": Ls[0] if len(Ls) == 1 else Ls,
-              "T": sorted({x[1] for x in instances}), "instances": len(instances),
-              "paths": sum(x[2] for x in instances), "n_therm": sorted({x[3] for x in instances}),
-              "n_meas": sorted({x[4] for x in instances}), "updates_per_step": upd_step, "seed": 1234,
-              "plan": plan, "engine": "single-instance, tuned" if single else "batch"}
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "spin updates/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": warmup,
-        "ms_per_step": wall / steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": config,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": traffic,
-                     "kernel": kernel_name, "kernel_ms": kms,
-                     "lane_slots_per_update": SLOTS_PER_UPDATE_F32,
-                     "ceiling_updates_per_s": VALU_PEAK / SLOTS_PER_UPDATE_F32,
-                     "ceiling_source": "measured: the update's instruction mix alone (opbench update_mix)"},
-        "parity": parity,
-    }
-    if hbm_bytes > 0:
-        # the bound reported is the one the kernels come closer to; the other rides along
-        gbs = hbm_bytes / (kms * 1e-3) / 1e9
-        hbm = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-               "traffic": traffic, "kernel": kernel_name, "kernel_ms": kms,
-               "bytes_per_update": {"device-memory": 36, "split": 18, "splitxy": 24}, "hbm_updates_per_step": hbm_upd,
-               "split_updates_per_step": split_upd}
-        if hbm["frac"] > out["roofline"]["frac"]:
-            out["roofline_valu"] = out["roofline"]
-            out["roofline"] = hbm
-        else:
-            out["roofline_hbm"] = hbm
-    if len(instances) <= 16:
-        out["stats"] = [{k: s[k] for k in ("mean_e", "se_e", "mean_absm", "se_absm", "chi", "cv_heat", "binder",
-                                           "r_e", "p_norm_e", "accept_rate")} for s in stats]
-    if a.workload.startswith("binder-"):
-        out["experiment"] = binder_summary(instances, results)
-    fits = sum(p * 3 * 8 * L ** 3 for (L, T, p, nt, nm) in instances) <= PLAIN_FP64_MAX_BYTES
-    if not a.skip_plain and fits:
-        pwall, pms, presults = run_plain_fp64(instances)
-        out["fp64_plain"] = {"value": upd_step / pwall, "unit": "spin updates/s", "kernel_ms": pms,
-                             "speedup_of_batched_fp32": value / (upd_step / pwall)}
-        if os.path.exists(golden_path):
-            with open(golden_path) as f:
-                ok, rows = four_sigma_vs_oracle(presults, json.load(f))
-            out["fp64_plain"]["agree_4sigma"] = ok
-        if len(instances) <= 16:
-            out["fp32_vs_fp64"] = fp32_vs_fp64(instances, results, presults)
-    if not a.skip_cpu:
-        out["cpu_baseline"] = cpu_baseline(instances)
+    out, mix = measure_workload(a.workload, steps, warmup, None, a)
+    if default and not a.skip_largest:
+        # the largest configuration, one timed pass (a step of it lasts about a minute or more)
+        log(f"largest configuration: {LARGEST}, one pass")
+        sub, _ = measure_workload(LARGEST, 1, 0, mix, a, plain_paths=64, compact=True)
+        for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+            sub.pop(k, None)
+        out["largest_config"] = sub
     print(json.dumps(out), flush=True)
 
 

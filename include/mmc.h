@@ -90,11 +90,13 @@ typedef enum { MMC_MODEL_HEISENBERG3D = 0, MMC_MODEL_ISING2D = 1 } mmc_model;
  * through the generic variants), its even-colour half in LDS and the odd colour in device
  * memory (variants named *-split-*), or, where only a third fits (compiled for L = 32 in FP32),
  * the even colour's x and y components in LDS and the rest in device memory (*-splitxy-*). HBM: spins in device memory, one workgroup per path, sweeps inside
- * one launch. WINDOW: spins in device memory, each workgroup (one path) running several
- * sweeps per pass, the half-sweeps pipelined over z-planes: either through a sliding window
- * of planes in LDS (compiled for L = 24, 30, 32 in FP32 and 12, 16 in FP64) or with every
- * plane left in device memory and reused through the caches (L = 32, 48, 64 in FP32; 16, 24
- * in FP64). PLAIN: the plain FP64 engine, one launch per half-sweep and
+ * one launch. WINDOW: spins in device memory, each workgroup (one path) running its sweeps
+ * in passes over z-planes: one sweep per pass through a ring of five z-planes in LDS, colour 1
+ * two planes behind colour 0 (*-ring-*, compiled for L = 48 in FP32, single-instance and
+ * batch), or several sweeps per pass with the half-sweeps pipelined over the planes, either
+ * through a sliding window of planes in LDS (compiled for L = 24, 30, 32 in FP32 and 12, 16 in
+ * FP64) or with every plane left in device memory and reused through the caches (L = 32, 48,
+ * 64 in FP32; 16, 24 in FP64). PLAIN: the plain FP64 engine, one launch per half-sweep and
  * one thread per site (FP64 only). AUTO: the tuner decides. */
 typedef enum {
     MMC_PLACE_AUTO = 0,
@@ -279,6 +281,18 @@ mmc_ctx *mmc_load(const char *file);
 
 /* Wall time of the last run's GPU work in milliseconds (hipEvents on the context's stream). */
 double mmc_last_timing_ms(const mmc_ctx *ctx);
+
+/* The proposal step of the Metropolis move on its own (the spherical parametrisation of
+ * Sec. 2.1 with the proposal reading of mmc_proposal): xyz[3t + a] = component a of the unit
+ * vector the engine proposes in the given precision from the words (words[2t], words[2t + 1])
+ * -- for the sphere proposal cos(theta) = 2 u0 - 1, phi = 2 pi u1, with the precision's
+ * uniforms (FP32 ((w >> 8) | 1) 2^-24 and the hardware sqrt/sin/cos, FP64 (w + 1/2) 2^-32 and
+ * IEEE FP64 with the library's sqrt/sin/cos), computed on the GPU by the code the sweep
+ * kernels inline. words: host array of 2n words; xyz: host array of 3n doubles, both owned by
+ * the caller. 1 <= n <= 2^31. Allocates and frees its own device buffers. MMC_EINVAL for null
+ * pointers, n or an enum out of range; MMC_ENOMEM if the buffers do not fit; MMC_EHIP without
+ * a GPU. */
+int mmc_proposal_vectors(int precision, int proposal, const uint32_t *words, int64_t n, double *xyz);
 
 /* Human-readable description of the chosen kernel variant(s), NUL-terminated: the variant's
  * name for a single instance ("plain-f64" for the plain engine); for a batch

@@ -28,7 +28,8 @@
  *   - acceptance: accept iff u < exp(-beta dE), beta = 1/T, k_B = 1, u in (0,1);
  *   - random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
  *     as easy as 1, 2, 3", SC'11), counter (site, sweep, path, tag | instance << 8),
- *     key (seed_lo, seed_hi); uniform u = (w + 1/2) 2^-32;
+ *     key (seed_lo, seed_hi); uniform u = (w + 1/2) 2^-32, or on request the FP32 engine's
+ *     grid u = ((w >> 8) | 1) 2^-24 (same words, FP64 arithmetic);
  *   - sweep: checkerboard (colour (x+y+z) mod 2; colour 0 then colour 1, each in increasing
  *     site id) -- the GPU order; the paper's literal random-site sweep and a typewriter
  *     sweep are kept for statistical cross-checks;
@@ -100,6 +101,14 @@ double mmco_uniform(uint32_t w)
     return ((double)w + 0.5) * (1.0 / 4294967296.0);
 }
 
+/* The FP32 engine's uniform, exact: ((w >> 8) | 1) 2^-24 -- the top 23 bits of the word and
+ * a trailing one, an odd multiple of 2^-24 in (0, 1). Used when the oracle is asked for the
+ * FP32 grid, to compare with the FP32 engine step by step (same uniforms, FP64 arithmetic). */
+double mmco_uniform_fp32(uint32_t w)
+{
+    return (double)((w >> 8) | 1u) * (1.0 / 16777216.0);
+}
+
 enum { MMCO_TAG_INIT = 0, MMCO_TAG_MET = 1, MMCO_TAG_SITE = 2 };
 enum { MMCO_SWEEP_CHECKERBOARD = 0, MMCO_SWEEP_RANDOM_SITE = 1, MMCO_SWEEP_TYPEWRITER = 2,
        MMCO_SWEEP_CHECKERBOARD_REVERSED = 3 };
@@ -120,7 +129,15 @@ typedef struct {
     int init;          /* MMCO_INIT_* */
     int trace_sweeps;  /* record (e_k, M_k) for sweeps k < trace_sweeps */
     int proposal;      /* MMCO_PROPOSAL_* */
+    int uniforms;      /* MMCO_UNIFORMS_*: how a word becomes a uniform */
 } mmco_params;
+
+enum { MMCO_UNIFORMS_FP64 = 0, MMCO_UNIFORMS_FP32 = 1 };
+
+static double uniform_of(int grid, uint32_t w)
+{
+    return grid == MMCO_UNIFORMS_FP32 ? mmco_uniform_fp32(w) : mmco_uniform(w);
+}
 
 typedef struct {
     double e_mean, e2_mean, absm_mean, m2_mean, m4_mean; /* per site, means over n_meas */
@@ -234,10 +251,10 @@ double mmco_delta_e(const mmco_params *p, const double *spins, int64_t i, const 
  *   SPHERE: cos(theta) = z = 2 u0 - 1 uniform, phi = 2 pi u1 (uniform on the sphere);
  *   ANGLES: theta = pi u0, phi = 2 pi u1 (both angles uniform);
  *   ORDERED: (0, 0, 1). */
-void mmco_unit_vector(uint32_t w0, uint32_t w1, int mode, double s[3])
+static void unit_vector_grid(uint32_t w0, uint32_t w1, int mode, int grid, double s[3])
 {
     if (mode == MMCO_INIT_ORDERED) { s[0] = 0.0; s[1] = 0.0; s[2] = 1.0; return; }
-    double u0 = mmco_uniform(w0), u1 = mmco_uniform(w1);
+    double u0 = uniform_of(grid, w0), u1 = uniform_of(grid, w1);
     double phi = 2.0 * MMCO_PI * u1;
     if (mode == MMCO_INIT_ANGLES) {
         double theta = MMCO_PI * u0;
@@ -251,6 +268,17 @@ void mmco_unit_vector(uint32_t w0, uint32_t w1, int mode, double s[3])
     s[0] = r * cos(phi);
     s[1] = r * sin(phi);
     s[2] = z;
+}
+
+void mmco_unit_vector(uint32_t w0, uint32_t w1, int mode, double s[3])
+{
+    unit_vector_grid(w0, w1, mode, MMCO_UNIFORMS_FP64, s);
+}
+
+/* n unit vectors from word pairs w[2t], w[2t+1] on either uniform grid (vectorised for tests). */
+void mmco_unit_vectors(int64_t n, const uint32_t *w, int mode, int grid, double *out /* [n][3] */)
+{
+    for (int64_t t = 0; t < n; ++t) unit_vector_grid(w[2 * t], w[2 * t + 1], mode, grid, out + 3 * t);
 }
 
 /* Many proposals for moment tests: draw t uses Philox((t, 0, 0, TAG_MET), seed). */
@@ -290,9 +318,10 @@ static int metropolis_site(const mmco_params *p, double beta, double *spins, int
                            const uint32_t w[4])
 {
     double snew[3];
-    mmco_unit_vector(w[0], w[1], p->proposal == MMCO_PROPOSAL_ANGLES ? MMCO_INIT_ANGLES : MMCO_INIT_SPHERE, snew);
+    unit_vector_grid(w[0], w[1], p->proposal == MMCO_PROPOSAL_ANGLES ? MMCO_INIT_ANGLES : MMCO_INIT_SPHERE,
+                     p->uniforms, snew);
     double dE = mmco_delta_e(p, spins, i, snew);
-    double u = mmco_uniform(w[2]);
+    double u = uniform_of(p->uniforms, w[2]);
     if (mmco_accept(u, dE, beta)) {
         spins[3 * i + 0] = snew[0];
         spins[3 * i + 1] = snew[1];
@@ -313,7 +342,7 @@ void mmco_init_state(const mmco_params *p, uint32_t path, mmco_state *st)
     for (int64_t i = 0; i < N; ++i) {
         uint32_t w[4];
         words(p, (uint32_t)i, 0u, path, MMCO_TAG_INIT, w);
-        mmco_unit_vector(w[0], w[1], mode, st->spins + 3 * i);
+        unit_vector_grid(w[0], w[1], mode, p->uniforms, st->spins + 3 * i);
     }
     st->sweeps_done = 0;
     st->sum_e = st->sum_e2 = st->sum_m = st->sum_m2 = st->sum_m4 = 0.0;

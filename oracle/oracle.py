@@ -14,13 +14,14 @@ from . import build as _build
 SWEEPS = {"checkerboard": 0, "random_site": 1, "typewriter": 2, "checkerboard_reversed": 3}
 INITS = {"sphere": 0, "angles": 1, "ordered": 2, "mixed": 3}
 PROPOSALS = {"sphere": 0, "angles": 1}
+UNIFORMS = {"fp64": 0, "fp32": 1}  # (w + 1/2) 2^-32, or the FP32 engine's ((w >> 8) | 1) 2^-24
 
 
 class Params(C.Structure):
     _fields_ = [("dim", C.c_int), ("L", C.c_int), ("periodic", C.c_int), ("T", C.c_double),
                 ("J", C.c_double), ("n_therm", C.c_int), ("n_meas", C.c_int),
                 ("seed", C.c_uint64), ("instance", C.c_uint32), ("sweep", C.c_int),
-                ("init", C.c_int), ("trace_sweeps", C.c_int), ("proposal", C.c_int)]
+                ("init", C.c_int), ("trace_sweeps", C.c_int), ("proposal", C.c_int), ("uniforms", C.c_int)]
 
 
 class PathResult(C.Structure):
@@ -52,6 +53,9 @@ def lib():
         L.mmco_philox_many.argtypes = [C.c_int64, u32p, u32p, u32p]
         L.mmco_uniform.argtypes = [C.c_uint32]
         L.mmco_uniform.restype = C.c_double
+        L.mmco_uniform_fp32.argtypes = [C.c_uint32]
+        L.mmco_uniform_fp32.restype = C.c_double
+        L.mmco_unit_vectors.argtypes = [C.c_int64, u32p, C.c_int, C.c_int, dp]
         L.mmco_n_sites.argtypes = [C.POINTER(Params)]
         L.mmco_n_sites.restype = C.c_int64
         L.mmco_neighbors.argtypes = [C.POINTER(Params), C.c_int64, i64p]
@@ -93,9 +97,9 @@ def _dp(a):
 
 
 def make_params(L, T, J=1.0, n_therm=0, n_meas=0, seed=1234, instance=0, dim=3, periodic=True,
-                sweep="checkerboard", init="sphere", trace_sweeps=0, proposal="sphere"):
+                sweep="checkerboard", init="sphere", trace_sweeps=0, proposal="sphere", uniforms="fp64"):
     return Params(dim, L, 1 if periodic else 0, float(T), float(J), n_therm, n_meas, seed,
-                  instance, SWEEPS[sweep], INITS[init], trace_sweeps, PROPOSALS[proposal])
+                  instance, SWEEPS[sweep], INITS[init], trace_sweeps, PROPOSALS[proposal], UNIFORMS[uniforms])
 
 
 def philox(ctr, key):
@@ -111,12 +115,13 @@ def philox(ctr, key):
 
 def run_paths(L, T, J=1.0, n_therm=0, n_meas=0, seed=1234, path_begin=0, path_end=1, instance=0,
               dim=3, periodic=True, sweep="checkerboard", init="sphere", trace_sweeps=0,
-              want_spins=False, n_threads=0, proposal="sphere"):
-    """Runs paths [path_begin, path_end). Returns a dict of numpy arrays:
+              want_spins=False, n_threads=0, proposal="sphere", uniforms="fp64"):
+    """Runs paths [path_begin, path_end) (uniforms "fp32": the FP32 engine's uniform grid, same
+    words, FP64 arithmetic). Returns a dict of numpy arrays:
     e_mean, e2_mean, absm_mean, m2_mean, m4_mean [n]; final_m [n,3]; final_e [n];
     n_accept [n]; trace [n, trace_sweeps, 4] (e_k, Mx_k, My_k, Mz_k); spins [n, N, 3]."""
     p = make_params(L, T, J, n_therm, n_meas, seed, instance, dim, periodic, sweep, init,
-                    trace_sweeps, proposal)
+                    trace_sweeps, proposal, uniforms)
     n = path_end - path_begin
     N = L ** dim
     res = (PathResult * n)()
@@ -213,6 +218,19 @@ def unit_vector(w0, w1, mode="sphere"):
     out = np.zeros(3)
     lib().mmco_unit_vector(w0, w1, INITS[mode], _dp(out))
     return out
+
+
+def unit_vectors(words, mode="sphere", uniforms="fp64"):
+    """Unit vectors of word pairs words[t] = (w0, w1) -> [n, 3], on either uniform grid."""
+    w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1, 2)
+    out = np.zeros((w.shape[0], 3))
+    lib().mmco_unit_vectors(w.shape[0], w.ctypes.data_as(C.POINTER(C.c_uint32)), INITS[mode], UNIFORMS[uniforms],
+                            _dp(out))
+    return out
+
+
+def uniform_fp32(w):
+    return lib().mmco_uniform_fp32(w)
 
 
 def max_threads():

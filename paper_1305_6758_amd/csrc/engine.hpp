@@ -66,7 +66,8 @@ struct Variant {
     int fp64;        // 0: FP32, 1: FP64
     int L;           // compile-time side, 0 = any even L
     int lds;         // 1: spins in LDS, 0: in device memory, 2: colour 0 in LDS, colour 1 in device memory,
-                     // 3: colour 0's x and y components in LDS, the rest in device memory
+                     // 3: colour 0's x and y components in LDS, the rest in device memory,
+                     // 4: in device memory, swept through a ring of z-planes in LDS
     int block;       // threads per workgroup
     int lanes;       // threads per path (block % lanes == 0)
     size_t lds_bytes;                 // dynamic LDS per workgroup
@@ -98,6 +99,12 @@ hipError_t prepare_kernels(int max_lds);  // once per process, before the first 
 hipError_t plain_init(const InstDev &in, hipStream_t s);
 hipError_t plain_half(const InstDev &in, const int *k_dev, int colour, hipStream_t s);
 hipError_t plain_measure(const InstDev &in, int *k_dev, int k_last, hipStream_t s);
+
+// The proposal step alone: xyz[3t..3t+2] = unit vector of words w[2t], w[2t+1] (device arrays).
+hipError_t proposal_vectors(int fp64, int angles, const uint32_t *w, long long n, double *xyz, hipStream_t s);
+
+// Sets the calling thread's C-ABI error (mmc_last_error / mmc_last_status); returns code.
+int report_error(int code, const char *msg);
 
 // Small helpers (kernel-based; no hipMemset inside captured graphs).
 hipError_t fill_zero(void *p, size_t bytes, hipStream_t s);

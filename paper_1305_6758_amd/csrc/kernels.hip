@@ -129,7 +129,7 @@ enum Map { COLZ = 0, FLAT = 1 };
 // LDS and colour 1 in device memory (sides whose lattice is too large for LDS but half of it
 // is not: 22 <= L <= 30 in FP32), or only colour 0's x and y components in LDS (a third of
 // the lattice: L = 32 and 34 in FP32).
-enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2, PL_SPLIT_XY = 3 };
+enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2, PL_SPLIT_XY = 3, PL_RING = 4 };
 
 // Everything a path group needs during its sweeps; path, key and counter word are
 // wave-uniform (each wave belongs to one path group).
@@ -217,10 +217,12 @@ struct ColourView {
 // One Metropolis attempt at site s of colour c, sweep k. Adds the resulting spin (and for the
 // odd colour S . h) to the measurement partials and the accepted count of the wave to nacc.
 // OWN_DEV / OTH_DEV: bit masks of the own / other colour's components in device memory.
-template <typename T, bool ANG = false, int OWN_DEV = 0, int OTH_DEV = 0>
-__device__ __forceinline__ void update_site_v(const GroupCtx<T> &g, const ColourView<T> &cv, bool odd, const Site &s,
+// store(acc, new spin, old spin) writes the outcome (update_site_v: the new spin into the own
+// arrays when accepted).
+template <typename T, bool ANG, int OWN_DEV, int OTH_DEV, typename Store>
+__device__ __forceinline__ void update_site_s(const GroupCtx<T> &g, const ColourView<T> &cv, bool odd, const Site &s,
                                               uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
-                                              unsigned long long &nacc)
+                                              unsigned long long &nacc, Store &&store)
 {
     const Words w = philox4x32_10((uint32_t)s.id, k, g.path, TAG_MET | g.ctr3, g.key0, g.key1);
     T *const ox = cv.own[0], *const oy = cv.own[1], *const oz = cv.own[2];
@@ -267,11 +269,7 @@ __device__ __forceinline__ void update_site_v(const GroupCtx<T> &g, const Colour
         const float dot = fmaf(dz, hz, fmaf(dy, hy, dx * hx));
         acc = Arith<float>::uni(w.w2) < __builtin_amdgcn_exp2f(cf.q * dot);
     }
-    if (acc) {
-        spin_at<OX>(ox, s.h) = nx;
-        spin_at<OY>(oy, s.h) = ny;
-        spin_at<OZ>(oz, s.h) = nz;
-    }
+    store(acc, nx, ny, nz, sx, sy, sz);
     const T fx = acc ? nx : sx, fy = acc ? ny : sy, fz = acc ? nz : sz;
     pmx += fx;
     pmy += fy;
@@ -281,6 +279,24 @@ __device__ __forceinline__ void update_site_v(const GroupCtx<T> &g, const Colour
         else pe = fmaf(fz, hz, fmaf(fy, hy, fmaf(fx, hx, pe)));
     }
     nacc += (unsigned long long)__popcll(__ballot(acc));
+}
+
+template <typename T, bool ANG = false, int OWN_DEV = 0, int OTH_DEV = 0>
+__device__ __forceinline__ void update_site_v(const GroupCtx<T> &g, const ColourView<T> &cv, bool odd, const Site &s,
+                                              uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
+                                              unsigned long long &nacc)
+{
+    T *const ox = cv.own[0], *const oy = cv.own[1], *const oz = cv.own[2];
+    constexpr bool OX = OWN_DEV & 1, OY = OWN_DEV & 2, OZ = OWN_DEV & 4;
+    const int h = s.h;
+    update_site_s<T, ANG, OWN_DEV, OTH_DEV>(g, cv, odd, s, k, cf, pe, pmx, pmy, pmz, nacc,
+                                            [&](bool acc, T nx, T ny, T nz, T, T, T) {
+                                                if (acc) {
+                                                    spin_at<OX>(ox, h) = nx;
+                                                    spin_at<OY>(oy, h) = ny;
+                                                    spin_at<OZ>(oz, h) = nz;
+                                                }
+                                            });
 }
 
 // The same with each colour's components HALF apart (one array per colour, all in LDS or all
@@ -680,15 +696,336 @@ __device__ __attribute__((noinline)) void copy_spins(T *__restrict__ dst, const 
     for (int t = lane; t < n; t += G) dst[t] = src[t];
 }
 
+// ------------------------------------------------------------------ colour-split z-plane ring
+// For lattices too large for LDS whose z-planes are not (L = 48 in FP32): the path's spins
+// stay in device memory and the workgroup (one path, B lanes) sweeps them through a ring of
+// RING = 5 plane slots in LDS, each slot holding one z-plane's colour-0 and colour-1 halves
+// (three components each). One pass is one sweep, in L + 3 steps with one barrier each:
+//   stage 0 (colour 0) updates virtual plane tau at step tau, 0 <= tau < L;
+//   stage 1 (colour 1) updates virtual plane tau - 2 at step tau, 3 <= tau <= L + 2, i.e. the
+//   virtual planes 1 .. L, so physical plane 0 comes last, after colour 0's plane L - 1.
+// A colour-1 update at plane v reads colour 0 of planes v - 1 .. v + 1, all updated in earlier
+// steps; a colour-0 update at plane v reads colour 1 of planes v - 1 .. v + 1, none of which
+// is updated before step v + 1 (plane 0's wrap-around neighbour L - 1 last of all): each site
+// sees exactly the neighbour values of the sequential half-sweep order. The two stages of a
+// step touch disjoint data. Virtual plane v lives in slot v mod RING: colour 0 of plane v is
+// in the ring during steps v .. v + 3, colour 1 during steps v - 1 .. v + 2, and each step
+// brings in the next step's two half-planes (colour 0 of plane tau + 1, colour 1 of plane
+// tau + 2), loaded into registers at the start of the step and stored into the ring at its
+// end, into slots whose previous half-planes are no longer read. Every update writes its
+// outcome straight to device memory (only the accepted ones, except on renormalisation
+// passes); colour 0 also updates its ring copy, which colour 1 reads later, and the two
+// colour-0 planes read again as virtual planes L and L + 1 are reloaded from device memory.
+// Device-memory traffic per update: 12 (2L + 4) / (2L) B read + 12 B written, 24.5 B at L = 48.
+// Renormalisation (FP32, every renorm_every sweeps) happens on load: every site is normalised
+// when its plane first enters the ring in the pass (colour 0 virtual planes 0 .. L - 1, every
+// colour-1 load) and written back whether or not its move is accepted, which leaves the spins
+// bit-identical to the other kernels'.
+constexpr int RING = 5;
+
+template <typename T>
+__host__ __device__ constexpr size_t ring_lds_bytes(int L, int B)
+{
+    return (size_t)RING * 3 * (size_t)L * L * sizeof(T) + 128 + (size_t)(B / 16) * 4 * sizeof(T);
+}
+
 // LDS bytes of one workgroup: spins (all of them, or colour 0), accumulators, reduction
 // slots (four partials per 16-lane row).
 template <typename T>
 __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, int pl)
 {
+    if (pl == PL_RING) return ring_lds_bytes<T>(L, B);
     const size_t ns = 3 * (size_t)L * L * L * sizeof(T);
     return (size_t)(B / G) * (pl == PL_LDS ? ns : pl == PL_SPLIT ? ns / 2 : pl == PL_SPLIT_XY ? ns / 3 : 0) +
            (size_t)(B / G) * 128 +
            (size_t)(B / 16) * 4 * sizeof(T);
+}
+
+// Half-planes in flight between device memory and the ring: lane t holds groups of E
+// consecutive sites (one 16-byte vector per component: E = 4 in FP32, 2 in FP64)
+// q = t + B i of two half-planes, q < PLANE / E in the first, the rest in the second.
+template <typename T, int LC, int B>
+struct RingRegs {
+    using V = typename std::conditional<std::is_same<T, float>::value, float4, double2>::type;
+    static constexpr int E = 16 / (int)sizeof(T);
+    static constexpr int PLANE = LC * LC / 2, NQ = PLANE / E, R = (2 * NQ + B - 1) / B;
+    V x[R], y[R], z[R];
+};
+
+template <typename V, typename T>
+__device__ __forceinline__ V ld16(const T *base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+__device__ __forceinline__ void normalise_sites(float4 &x, float4 &y, float4 &z)
+{
+    const float ra = __builtin_amdgcn_rsqf(fmaf(z.x, z.x, fmaf(y.x, y.x, x.x * x.x)));
+    const float rb = __builtin_amdgcn_rsqf(fmaf(z.y, z.y, fmaf(y.y, y.y, x.y * x.y)));
+    const float rc = __builtin_amdgcn_rsqf(fmaf(z.z, z.z, fmaf(y.z, y.z, x.z * x.z)));
+    const float rd = __builtin_amdgcn_rsqf(fmaf(z.w, z.w, fmaf(y.w, y.w, x.w * x.w)));
+    x = make_float4(x.x * ra, x.y * rb, x.z * rc, x.w * rd);
+    y = make_float4(y.x * ra, y.y * rb, y.z * rc, y.w * rd);
+    z = make_float4(z.x * ra, z.y * rb, z.z * rc, z.w * rd);
+}
+
+__device__ __forceinline__ void normalise_sites(double2 &, double2 &, double2 &) {}  // FP64: never
+
+// Loads colour c0 of plane zp0 (when h0) and colour c1 of plane zp1 (when h1) from the path's
+// device-memory spins gsp into registers.
+template <typename T, int LC, int B>
+__device__ __forceinline__ void ring_load(RingRegs<T, LC, B> &r, const T *gsp, int c0, int zp0, bool h0, int c1,
+                                          int zp1, bool h1, int tid)
+{
+    using R = RingRegs<T, LC, B>;
+    using V = typename R::V;
+    constexpr int PLANE = R::PLANE, NQ = R::NQ, E = R::E, HALF = LC * PLANE;
+    constexpr uint32_t CB = HALF * sizeof(T);  // bytes between components
+#pragma unroll
+    for (int i = 0; i < R::R; ++i) {
+        const int q = tid + B * i;
+        const bool second = q >= NQ;
+        if (q < 2 * NQ && (second ? h1 : h0)) {
+            const int c = second ? c1 : c0, zp = second ? zp1 : zp0, rq = q - (second ? NQ : 0);
+            const uint32_t off = (uint32_t)(c * 3 * HALF + zp * PLANE + E * rq) * (uint32_t)sizeof(T);
+            r.x[i] = ld16<V>(gsp, off);
+            r.y[i] = ld16<V>(gsp, off + CB);
+            r.z[i] = ld16<V>(gsp, off + 2u * CB);
+        }
+    }
+}
+
+// Stores what ring_load brought in into ring slots s0 / s1 (normalising first where n0 / n1).
+template <typename T, int LC, int B>
+__device__ __forceinline__ void ring_store(RingRegs<T, LC, B> &r, T *ring, int c0, int s0, bool h0, bool n0, int c1,
+                                           int s1, bool h1, bool n1, int tid)
+{
+    using R = RingRegs<T, LC, B>;
+    using V = typename R::V;
+    constexpr int PLANE = R::PLANE, NQ = R::NQ, E = R::E, SLOT = 6 * PLANE;
+#pragma unroll
+    for (int i = 0; i < R::R; ++i) {
+        const int q = tid + B * i;
+        const bool second = q >= NQ;
+        if (q < 2 * NQ && (second ? h1 : h0)) {
+            const int c = second ? c1 : c0, sl = second ? s1 : s0, rq = q - (second ? NQ : 0);
+            if (second ? n1 : n0) normalise_sites(r.x[i], r.y[i], r.z[i]);
+            T *o = ring + sl * SLOT + c * 3 * PLANE + E * rq;
+            *reinterpret_cast<V *>(o) = r.x[i];
+            *reinterpret_cast<V *>(o + PLANE) = r.y[i];
+            *reinterpret_cast<V *>(o + 2 * PLANE) = r.z[i];
+        }
+    }
+}
+
+// Geometry of the sites a lane updates in every plane: in-plane half-index s = rank 64 + wl +
+// (B/2) t, its site id less the x-parity and the z part, the parity of y, and the in-plane
+// neighbour offsets (x-1 when the x-parity is 0, x+1 when it is 1, y-1, y+1).
+struct RingSite {
+    int s, idb, ypar, xm0, xp1, ym, yp;
+};
+
+template <typename T, int C, int LC, int B, int K>
+__device__ __forceinline__ void ring_stage(const GroupCtx<T> &g, const RingSite (&q)[K], T *ring, T *gsp, int v,
+                                           uint32_t k, const Coef<T> &cf, bool rn, T &pe, T &pmx, T &pmy, T &pmz,
+                                           unsigned long long &nacc)
+{
+    constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE, SLOT = 6 * PLANE, SL = B / 2;
+    const int zp = v < LC ? v : v - LC;
+    const int sl = v % RING;
+    const int dm = ((v + RING - 1) % RING - sl) * SLOT, dp = ((v + 1) % RING - sl) * SLOT;
+    T *const own = ring + sl * SLOT + C * 3 * PLANE;
+    const T *const oth = ring + sl * SLOT + (1 - C) * 3 * PLANE;
+    const ColourView<T> cv{{own, own + PLANE, own + 2 * PLANE}, {oth, oth + PLANE, oth + 2 * PLANE}};
+    T *const gx = gsp + C * 3 * HALF + zp * PLANE, *const gy = gx + HALF, *const gz = gx + 2 * HALF;
+    const int zpar = zp & 1, idz = LC * LC * zp;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        if ((PLANE % SL) == 0 || t < K - 1 || q[t].s < PLANE) {
+            const int p = (q[t].ypar + zpar + C) & 1;
+            const int h = q[t].s;
+            Site st;
+            st.h = h;
+            st.id = q[t].idb + p + idz;
+            st.nb[0] = h + (p ? 0 : q[t].xm0);
+            st.nb[1] = h + (p ? q[t].xp1 : 0);
+            st.nb[2] = h + q[t].ym;
+            st.nb[3] = h + q[t].yp;
+            st.nb[4] = h + dm;
+            st.nb[5] = h + dp;
+            update_site_s<T, false, 0, 0>(g, cv, C != 0, st, k, cf, pe, pmx, pmy, pmz, nacc,
+                                          [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
+                                              if (C == 0 && acc) {
+                                                  own[h] = nx;
+                                                  own[PLANE + h] = ny;
+                                                  own[2 * PLANE + h] = nz;
+                                              }
+                                              if (acc || rn) {
+                                                  spin_at<true>(gx, h) = acc ? nx : sx;
+                                                  spin_at<true>(gy, h) = acc ? ny : sy;
+                                                  spin_at<true>(gz, h) = acc ? nz : sz;
+                                              }
+                                          });
+        }
+    }
+}
+
+// Sweeps [k0, k1) of one path (the whole workgroup) through the ring. Waves of even index run
+// stage 0, odd ones stage 1.
+template <typename T, int LC, int B>
+__device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const InstDev &in, int k0, int k1, bool fresh,
+                                                 T *ring)
+{
+    constexpr int L = LC, HL = L / 2, PLANE = L * L / 2, W = B / 64, SL = B / 2, K = (PLANE + SL - 1) / SL;
+    static_assert(W % 2 == 0 && (PLANE % RingRegs<T, LC, B>::E) == 0 && L > RING, "ring shape");
+    constexpr bool FP32 = std::is_same<T, float>::value;
+    const double Nd = (double)L * L * L;
+    const int n_therm = in.n_therm, trace_sweeps = in.trace_sweeps, renorm_every = in.renorm_every;
+    const double J = in.J;
+    Coef<T> cf;
+    cf.beta = (T)in.beta;
+    cf.J = (T)in.J;
+    cf.q = (float)(in.beta * in.J * 1.4426950408889634);  // beta J log2(e)
+    const int tid = g.lane, wave = tid >> 6, wl = tid & 63;
+    const bool odd_wave = (wave & 1) != 0;
+    unsigned long long nacc = 0;
+    T *const gsp = g.sp;
+
+    if (g.active && fresh) init_path<T, B>(gsp, nullptr, nullptr, L, tid, g.path, g.key0, g.key1, g.ctr3, in.init);
+    // this lane's sites (the same in every plane and for both stages)
+    RingSite q[K];
+    {
+        int lane = tid;
+        asm volatile("" : "+v"(lane));  // not hoisted out of a persistent kernel's item loop
+        const int rank = (lane >> 6) >> 1, l64 = lane & 63;
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const int sidx = rank * 64 + l64 + SL * t;
+            const int jx = sidx % HL, y = sidx / HL;
+            q[t].s = sidx;
+            q[t].idb = 2 * jx + L * y;
+            q[t].ypar = y & 1;
+            q[t].xm0 = (jx == 0) ? HL - 1 : -1;
+            q[t].xp1 = (jx == HL - 1) ? -(HL - 1) : 1;
+            q[t].ym = (y == 0) ? (L - 1) * HL : -HL;
+            q[t].yp = (y == L - 1) ? -(L - 1) * HL : HL;
+        }
+    }
+    __syncthreads();
+    for (int ks = k0; ks < k1; ++ks) {
+        const bool rn = FP32 && renorm_every > 0 && ks > 0 && ks % renorm_every == 0;
+        // the pass starts with colour 0 of plane 0 and colour 1 of planes -1, 0, 1
+        if (g.active) {
+            RingRegs<T, LC, B> r;
+            ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, L - 1, true, tid);
+            ring_store<T, LC, B>(r, ring, 0, 0, true, rn, 1, RING - 1, true, rn, tid);
+            ring_load<T, LC, B>(r, gsp, 1, 0, true, 1, 1, true, tid);
+            ring_store<T, LC, B>(r, ring, 1, 0, true, rn, 1, 1, true, rn, tid);
+        }
+        __syncthreads();
+        T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);
+#pragma unroll 1
+        for (int tau = 0; tau <= L + 2; ++tau) {
+            // next step's half-planes: colour 0 of plane tau + 1 (virtual planes up to L + 1),
+            // colour 1 of plane tau + 2 (up to L)
+            const bool h0 = tau + 1 <= L + 1, h1 = tau + 2 <= L;
+            const int z0 = tau + 1 < L ? tau + 1 : tau + 1 - L, z1 = tau + 2 < L ? tau + 2 : tau + 2 - L;
+            RingRegs<T, LC, B> r;
+            if (g.active) ring_load<T, LC, B>(r, gsp, 0, z0, h0, 1, z1, h1, tid);
+            if (g.active) {
+                if (odd_wave) {
+                    if (tau >= 3)
+                        ring_stage<T, 1, LC, B, K>(g, q, ring, gsp, tau - 2, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
+                } else if (tau < L) {
+                    ring_stage<T, 0, LC, B, K>(g, q, ring, gsp, tau, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
+                }
+                ring_store<T, LC, B>(r, ring, 0, (tau + 1) % RING, h0, rn && tau + 1 < L, 1, (tau + 2) % RING, h1, rn,
+                                     tid);
+            }
+            __syncthreads();
+        }
+        // measurement of sweep ks (the state after it): every site was added once
+        const bool meas = ks >= n_therm || ks < trace_sweeps || ks == k1 - 1;
+        if (meas) {
+            pe = row_sum(pe);
+            pmx = row_sum(pmx);
+            pmy = row_sum(pmy);
+            pmz = row_sum(pmz);
+            if ((wl & 15) == 0) {
+                T *slot = g.red + 4 * (tid >> 4);
+                slot[0] = pe;
+                slot[1] = pmx;
+                slot[2] = pmy;
+                slot[3] = pmz;
+            }
+        }
+        __syncthreads();
+        if (meas && g.active && wave == 0) {
+            T se = T(0), sx = T(0), sy = T(0), sz = T(0);
+            if (wl < 4 * W) {
+                se = g.red[4 * wl + 0];
+                sx = g.red[4 * wl + 1];
+                sy = g.red[4 * wl + 2];
+                sz = g.red[4 * wl + 3];
+            }
+            se = wave_sum(se);
+            sx = wave_sum(sx);
+            sy = wave_sum(sy);
+            sz = wave_sum(sz);
+            if (wl == 0) {
+                const double e = -J * (double)se / Nd;
+                const double mx = (double)sx / Nd, my = (double)sy / Nd, mz = (double)sz / Nd;
+                if (ks >= n_therm) {
+                    const double m = sqrt(mx * mx + my * my + mz * mz);
+                    g.shacc[0] += e;
+                    g.shacc[1] += e * e;
+                    g.shacc[2] += m;
+                    g.shacc[3] += m * m;
+                    g.shacc[4] += (m * m) * (m * m);
+                }
+                if (ks < trace_sweeps) {
+                    double *tr = in.trace + ((size_t)g.path * trace_sweeps + ks) * 4;
+                    tr[0] = e;
+                    tr[1] = mx;
+                    tr[2] = my;
+                    tr[3] = mz;
+                }
+                if (ks == k1 - 1) {
+                    g.shacc[5] = e;
+                    g.shacc[6] = mx;
+                    g.shacc[7] = my;
+                    g.shacc[8] = mz;
+                }
+            }
+        }
+        // (the next pass's first stores go to the ring, not to the partial slots, which are
+        // written again only after L + 3 more barriers)
+    }
+    if (g.active && wl == 0) atomicAdd((unsigned long long *)&g.shacc[9], nacc);
+    __syncthreads();
+}
+
+template <typename T, int LC, int B>
+__device__ __forceinline__ void wg_run_ring(const InstDev &in, int path, int k0, int k1, bool fresh, char *smem, T *gsp)
+{
+    GroupCtx<T> g;
+    g.L = in.L;
+    g.lane = threadIdx.x;
+    g.path = (uint32_t)__builtin_amdgcn_readfirstlane(path);
+    g.key0 = in.key0;
+    g.key1 = in.key1;
+    g.ctr3 = in.ctr3;
+    g.active = path < in.n_paths;
+    T *ring = reinterpret_cast<T *>(smem);
+    char *p = smem + (size_t)RING * 3 * LC * LC * sizeof(T);
+    g.shacc = reinterpret_cast<double *>(p);
+    g.red = reinterpret_cast<T *>(p + 128);
+    g.sp = gsp;
+    g.sp1 = nullptr;
+    g.sp0z = nullptr;
+    load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
+    path_sweeps_ring<T, LC, B>(g, in, k0, k1, fresh, ring);
+    store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
 }
 
 // Sets up the group views of one workgroup and runs sweeps [k0, k1) for paths
@@ -699,8 +1036,8 @@ __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, int p
 // in place in device memory and only colour 0 is copied to and from LDS (PL_SPLIT_XY: only
 // colour 0's x and y).
 template <typename T, int LC, int G, int B, int MAP, int PL>
-__device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int k1, bool fresh, char *smem, T *gbase,
-                                       bool resident)
+__device__ __forceinline__ void wg_run_groups(const InstDev &in, int path0, int k0, int k1, bool fresh, char *smem,
+                                              T *gbase, bool resident)
 {
     constexpr bool IN_LDS = PL != PL_MEM;
     constexpr int P = B / G;
@@ -737,6 +1074,18 @@ __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int
     store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
 }
 
+template <typename T, int LC, int G, int B, int MAP, int PL>
+__device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int k1, bool fresh, char *smem, T *gbase,
+                                       bool resident)
+{
+    if constexpr (PL == PL_RING) {
+        static_assert(G == B, "one path per workgroup");
+        wg_run_ring<T, LC, B>(in, path0, k0, k1, fresh, smem, gbase);
+    } else {
+        wg_run_groups<T, LC, G, B, MAP, PL>(in, path0, k0, k1, fresh, smem, gbase, resident);
+    }
+}
+
 // Waves per SIMD a kernel variant aims for (the compiler sizes its registers to fit): as
 // many workgroups as the 160 KiB of LDS per CU holds, 4 SIMDs per CU, at most 8 waves per
 // SIMD (4 in FP64); 4 (FP64: 2) for spins in device memory.
@@ -746,7 +1095,8 @@ constexpr int target_waves(int L, int B, int G, int pl)
     const int fp64 = sizeof(T) == 8;  // FP64 values take register pairs
     if (pl == PL_MEM || L == 0) return fp64 ? 2 : 4;
     const int wgs = (int)((size_t)160 * 1024 / lds_layout_bytes<T>(L, B, G, pl));
-    const int w = wgs * (B / 64) / 4, cap = fp64 ? 4 : 8;
+    // (the plane ring keeps a whole update's worth of geometry and in-flight planes per lane)
+    const int w = wgs * (B / 64) / 4, cap = pl == PL_RING ? (fp64 ? 2 : 4) : (fp64 ? 4 : 8);
     return w < 1 ? 1 : (w > cap ? cap : w);
 }
 
@@ -1217,6 +1567,9 @@ constexpr int BATCH_B = 512;
     X(float, 0, 1024, 1024, FLAT, PL_SPLIT, "f32-split-any-g1024")    \
     X(float, 32, 1024, 1024, COLZ, PL_SPLIT_XY, "f32-splitxy-L32-g1024") \
     X(float, 0, 1024, 1024, FLAT, PL_SPLIT_XY, "f32-splitxy-any-g1024") \
+    X(float, 48, 1024, 1024, FLAT, PL_RING, "f32-ring-L48-g1024")     \
+    X(float, 48, 768, 768, FLAT, PL_RING, "f32-ring-L48-g768")        \
+    X(float, 32, 512, 512, FLAT, PL_RING, "f32-ring-L32-g512")        \
     X(float, 24, 512, 512, FLAT, PL_MEM, "f32-hbm-L24-g512")          \
     X(float, 32, 512, 512, COLZ, PL_MEM, "f32-hbm-L32-g512")          \
     X(float, 48, 512, 512, FLAT, PL_MEM, "f32-hbm-L48-g512")          \
@@ -1453,6 +1806,22 @@ __global__ __launch_bounds__(256) void k_plain_measure(InstDev in, int *k_dev, i
     }
 }
 
+// ------------------------------------------------------------------ proposal step alone
+// The unit vector each precision's Metropolis move proposes from a word pair (the same
+// Arith<T> code the sweep kernels inline), for checks of the proposal step on its own.
+template <typename T, bool ANG>
+__global__ __launch_bounds__(256) void k_proposals(const uint32_t *w, long long n, double *xyz)
+{
+    for (long long t = blockIdx.x * 256ll + threadIdx.x; t < n; t += (long long)gridDim.x * 256) {
+        T x, y, z;
+        if constexpr (ANG) Arith<T>::angles(w[2 * t], w[2 * t + 1], x, y, z);
+        else Arith<T>::sphere(w[2 * t], w[2 * t + 1], x, y, z);
+        xyz[3 * t + 0] = (double)x;
+        xyz[3 * t + 1] = (double)y;
+        xyz[3 * t + 2] = (double)z;
+    }
+}
+
 // ------------------------------------------------------------------ fills
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v)
 {
@@ -1505,6 +1874,11 @@ static const Variant k_variants[] = {
     MMC_RES(float, 64, 512, 512, COLZ, PL_MEM, "f32-hbm-L64-g512-b512")
     MMC_RES(float, 64, 1024, 1024, COLZ, PL_MEM, "f32-hbm-L64-g1024-b1024")
     MMC_RES(float, 0, 512, 512, FLAT, PL_MEM, "f32-hbm-any-g512-b512")
+    // FP32, spins in device memory, swept through a ring of z-planes in LDS
+    MMC_RES(float, 48, 1024, 1024, FLAT, PL_RING, "f32-ring-L48-b1024")
+    MMC_RES(float, 48, 768, 768, FLAT, PL_RING, "f32-ring-L48-b768")
+    MMC_RES(float, 32, 512, 512, FLAT, PL_RING, "f32-ring-L32-b512")
+    MMC_RES(float, 16, 256, 256, FLAT, PL_RING, "f32-ring-L16-b256")
     // FP32, spins in device memory, z-pipelined window in LDS
     MMC_WIN(float, 24, 512, 2, false, "f32-win-L24-d2-b512")
     MMC_WIN(float, 24, 1024, 3, false, "f32-win-L24-d3-b1024")
@@ -1529,6 +1903,9 @@ static const Variant k_variants[] = {
     MMC_RES(double, 32, 512, 512, COLZ, PL_MEM, "f64-hbm-L32-g512-b512")
     MMC_RES(double, 64, 1024, 1024, COLZ, PL_MEM, "f64-hbm-L64-g1024-b1024")
     MMC_RES(double, 0, 512, 512, FLAT, PL_MEM, "f64-hbm-any-g512-b512")
+    // FP64, plane ring (small lattices: parity of its schedule with the oracle)
+    MMC_RES(double, 12, 256, 256, FLAT, PL_RING, "f64-ring-L12-b256")
+    MMC_RES(double, 16, 256, 256, FLAT, PL_RING, "f64-ring-L16-b256")
     // FP64, window (small lattices: parity of the pipelined schedule with the oracle)
     MMC_WIN(double, 12, 256, 1, false, "f64-win-L12-d1-b256")
     MMC_WIN(double, 16, 256, 2, false, "f64-win-L16-d2-b256")
@@ -1664,6 +2041,17 @@ hipError_t plain_half(const InstDev &in, const int *k_dev, int colour, hipStream
 hipError_t plain_measure(const InstDev &in, int *k_dev, int k_last, hipStream_t s)
 {
     hipLaunchKernelGGL(k_plain_measure, dim3(in.n_paths), dim3(256), 0, s, in, k_dev, k_last);
+    return hipGetLastError();
+}
+
+hipError_t proposal_vectors(int fp64, int angles, const uint32_t *w, long long n, double *xyz, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    if (fp64 && angles) hipLaunchKernelGGL((k_proposals<double, true>), dim3(grid), dim3(256), 0, s, w, n, xyz);
+    else if (fp64) hipLaunchKernelGGL((k_proposals<double, false>), dim3(grid), dim3(256), 0, s, w, n, xyz);
+    else if (angles) hipLaunchKernelGGL((k_proposals<float, true>), dim3(grid), dim3(256), 0, s, w, n, xyz);
+    else hipLaunchKernelGGL((k_proposals<float, false>), dim3(grid), dim3(256), 0, s, w, n, xyz);
     return hipGetLastError();
 }
 

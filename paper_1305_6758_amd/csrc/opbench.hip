@@ -61,6 +61,8 @@ OPBENCH_KERNEL(k_add_f64, double, 1.0 + c, asm volatile("v_add_f64 %0, %0, %1" :
 // is the ALU ceiling of the update's instruction mix, whatever the classes' overlap.
 __global__ __launch_bounds__(256) void k_update_mix(uint32_t *sink, int iters)
 {
+    // shader-clock cycles and constant-rate wall-clock ticks of the loop (per workgroup)
+    const uint64_t c0 = __builtin_amdgcn_s_memtime(), r0 = __builtin_amdgcn_s_memrealtime();
     const uint32_t t = threadIdx.x + blockIdx.x * 256u;
     const uint32_t yb = t * 0x9E3779B9u + 1u;
     const float yf = 1.0f + 1e-7f * (float)(t & 7);
@@ -142,7 +144,14 @@ __global__ __launch_bounds__(256) void k_update_mix(uint32_t *sink, int iters)
 #pragma unroll
     for (int c = 0; c < 4; ++c) h ^= (uint32_t)m[c] ^ b[c] ^ (uint32_t)sb[c] ^ (uint32_t)fm[c] ^ (uint32_t)ad[c] ^ (uint32_t)tr[c];
     h ^= al[0] ^ al[1] ^ cm[0] ^ cm[1] ^ cm[2] ^ (uint32_t)mu[0] ^ (uint32_t)mu[1];
-    if (h == 0x12345678u) sink[t] = h;
+    if (h == 0x12345678u && threadIdx.x >= 4) sink[t] = h;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t c1 = __builtin_amdgcn_s_memtime(), r1 = __builtin_amdgcn_s_memrealtime();
+        uint64_t *clk = reinterpret_cast<uint64_t *>(sink + blockIdx.x * 256u);
+        clk[0] = c1 - c0;
+        clk[1] = r1 - r0;
+    }
 }
 
 struct Op {
@@ -161,21 +170,82 @@ const Op k_ops[] = {
     {"update_mix", k_update_mix},
 };
 
-// Streaming copy of n 16-byte elements: each thread moves U elements per step (all loads
-// issued before the stores, 256 elements apart, so that a wave keeps U loads in flight),
-// grid-stride over the array. Every index is checked against n.
-template <int U>
-__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
+// Streaming kernels over n 16-byte elements, grid-stride, each thread moving U elements per
+// step (all loads issued before the stores, TB elements apart, so that a wave keeps U loads in
+// flight): KIND 0 copies src to dst, 1 only reads src (xor-folding what it reads, stored only
+// if it hits a value that never occurs), 2 only writes dst. NT: nontemporal loads and stores
+// (streamed past the caches' normal allocation). Every index is checked against n.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int U, int TB, int KIND, bool NT>
+__global__ __launch_bounds__(TB) void k_stream16(const uint4 *__restrict__ src4, uint4 *__restrict__ dst4, size_t n)
 {
-    const size_t step = (size_t)gridDim.x * 256 * U;
-    for (size_t base = (size_t)blockIdx.x * 256 * U + threadIdx.x; base < n; base += step) {
-        uint4 v[U];
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(src4);
+    u32x4 *dst = reinterpret_cast<u32x4 *>(dst4);
+    const size_t step = (size_t)gridDim.x * TB * U;
+    uint32_t fold = 0;
+    for (size_t base = (size_t)blockIdx.x * TB * U + threadIdx.x; base < n; base += step) {
+        u32x4 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (base + (size_t)u * 256 < n) v[u] = src[base + (size_t)u * 256];
+        for (int u = 0; u < U; ++u) {
+            const size_t i = base + (size_t)u * TB;
+            if (KIND != 2 && i < n) v[u] = NT ? __builtin_nontemporal_load(src + i) : src[i];
+            else v[u] = u32x4{(uint32_t)i, 1u, 2u, 3u};
+        }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (base + (size_t)u * 256 < n) dst[base + (size_t)u * 256] = v[u];
+        for (int u = 0; u < U; ++u) {
+            const size_t i = base + (size_t)u * TB;
+            if (i < n) {
+                if (KIND == 1) {
+                    fold ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+                } else if (NT) {
+                    __builtin_nontemporal_store(v[u], dst + i);
+                } else {
+                    dst[i] = v[u];
+                }
+            }
+        }
+    }
+    if (KIND == 1 && fold == 0x9E3779B9u && n > 0) dst[0] = u32x4{fold, 0u, 0u, 0u};
+}
+
+template <int U, int TB, int KIND, bool NT>
+void launch_stream(int blocks, hipStream_t s, const uint4 *src, uint4 *dst, size_t n)
+{
+    hipLaunchKernelGGL((k_stream16<U, TB, KIND, NT>), dim3(blocks), dim3(TB), 0, s, src, dst, n);
+}
+
+template <int TB, int KIND, bool NT>
+bool launch_u(int unroll, int blocks, hipStream_t s, const uint4 *src, uint4 *dst, size_t n)
+{
+    switch (unroll) {
+    case 1: launch_stream<1, TB, KIND, NT>(blocks, s, src, dst, n); return true;
+    case 2: launch_stream<2, TB, KIND, NT>(blocks, s, src, dst, n); return true;
+    case 4: launch_stream<4, TB, KIND, NT>(blocks, s, src, dst, n); return true;
+    case 8: launch_stream<8, TB, KIND, NT>(blocks, s, src, dst, n); return true;
+    default: return false;
+    }
+}
+
+template <int KIND, bool NT>
+bool launch_tb(int threads, int unroll, int blocks, hipStream_t s, const uint4 *src, uint4 *dst, size_t n)
+{
+    if (threads == 256) return launch_u<256, KIND, NT>(unroll, blocks, s, src, dst, n);
+    if (threads == 1024) return launch_u<1024, KIND, NT>(unroll, blocks, s, src, dst, n);
+    return false;
+}
+
+bool launch_any(int kind, int nt, int threads, int unroll, int blocks, hipStream_t s, const uint4 *src, uint4 *dst,
+                size_t n)
+{
+    switch (kind * 2 + (nt ? 1 : 0)) {
+    case 0: return launch_tb<0, false>(threads, unroll, blocks, s, src, dst, n);
+    case 1: return launch_tb<0, true>(threads, unroll, blocks, s, src, dst, n);
+    case 2: return launch_tb<1, false>(threads, unroll, blocks, s, src, dst, n);
+    case 3: return launch_tb<1, true>(threads, unroll, blocks, s, src, dst, n);
+    case 4: return launch_tb<2, false>(threads, unroll, blocks, s, src, dst, n);
+    case 5: return launch_tb<2, true>(threads, unroll, blocks, s, src, dst, n);
+    default: return false;
     }
 }
 
@@ -183,36 +253,34 @@ __global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, u
 
 extern "C" {
 
-// Time of one streaming copy of `bytes` (a multiple of 16) from src to dst (device pointers,
-// disjoint), averaged over reps launches after one warm-up, on the null stream;
-// blocks_per_cu x CUs workgroups of 256 threads, unroll 1, 2 or 4 elements per thread and
-// step. Returns 0, -1 on bad arguments, -3 on a HIP error.
-int mmc_opbench_copy(const void *src, void *dst, size_t bytes, int reps, int blocks_per_cu, int unroll, double *ms)
+// Time of one streaming pass over `bytes` (a multiple of 16) averaged over reps launches after
+// one warm-up, on the null stream: kind 0 copies src to dst (disjoint device buffers), 1 reads
+// src, 2 writes dst; nt = 1 for nontemporal accesses; blocks_per_cu x CUs workgroups of
+// `threads` (256 or 1024) threads, unroll 1, 2, 4 or 8 elements per thread and step.
+// Returns 0, -1 on bad arguments, -3 on a HIP error.
+int mmc_opbench_stream(const void *src, void *dst, size_t bytes, int reps, int kind, int nt, int threads,
+                       int blocks_per_cu, int unroll, double *ms)
 {
-    if (!src || !dst || !ms || bytes == 0 || bytes % 16 || reps < 1 || blocks_per_cu < 1 || blocks_per_cu > 64)
+    if (!src || !dst || !ms || bytes == 0 || bytes % 16 || reps < 1 || blocks_per_cu < 1 || blocks_per_cu > 64 ||
+        kind < 0 || kind > 2 || (threads != 256 && threads != 1024) ||
+        (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8))
         return -1;
-    if (unroll != 1 && unroll != 2 && unroll != 4) return -1;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return -3;
     const size_t n = bytes / 16;
     const int blocks = cus * blocks_per_cu;
-    auto launch = [&]() {
-        const uint4 *s = static_cast<const uint4 *>(src);
-        uint4 *d = static_cast<uint4 *>(dst);
-        if (unroll == 1) hipLaunchKernelGGL(k_copy16<1>, dim3(blocks), dim3(256), 0, 0, s, d, n);
-        else if (unroll == 2) hipLaunchKernelGGL(k_copy16<2>, dim3(blocks), dim3(256), 0, 0, s, d, n);
-        else hipLaunchKernelGGL(k_copy16<4>, dim3(blocks), dim3(256), 0, 0, s, d, n);
-    };
+    const uint4 *s = static_cast<const uint4 *>(src);
+    uint4 *d = static_cast<uint4 *>(dst);
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return -3;
     if (hipEventCreate(&b) != hipSuccess) {
         (void)hipEventDestroy(a);
         return -3;
     }
-    launch();  // warm-up
+    launch_any(kind, nt, threads, unroll, blocks, 0, s, d, n);  // warm-up
     (void)hipEventRecord(a, 0);
-    for (int r = 0; r < reps; ++r) launch();
+    for (int r = 0; r < reps; ++r) launch_any(kind, nt, threads, unroll, blocks, 0, s, d, n);
     (void)hipEventRecord(b, 0);
     hipError_t e = hipEventSynchronize(b);
     float t = 0;
@@ -222,6 +290,13 @@ int mmc_opbench_copy(const void *src, void *dst, size_t bytes, int reps, int blo
     if (e != hipSuccess || hipGetLastError() != hipSuccess) return -3;
     *ms = t / reps;
     return 0;
+}
+
+// The plain 256-thread copy (kind 0, no nontemporal hints): the calibration kernel of the
+// byte counters.
+int mmc_opbench_copy(const void *src, void *dst, size_t bytes, int reps, int blocks_per_cu, int unroll, double *ms)
+{
+    return mmc_opbench_stream(src, dst, bytes, reps, 0, 0, 256, blocks_per_cu, unroll, ms);
 }
 
 int mmc_opbench_count(void) { return (int)(sizeof(k_ops) / sizeof(k_ops[0])); }

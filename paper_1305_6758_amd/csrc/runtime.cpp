@@ -62,6 +62,15 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
+}  // namespace
+
+namespace mmc {
+// The thread-local error of the C ABI, for the library's other translation units.
+int report_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace mmc
+
+namespace {
+
 #define HIP_TRY(call)                                                                                     \
     do {                                                                                                  \
         hipError_t e_ = (call);                                                                           \
@@ -296,6 +305,12 @@ std::string tune_key(bool batch, int fp64, int L, int n_paths)
 }
 
 // ---------------------------------------------------------------- candidates
+// Variant::lds of the plane-ring variants: their spins live in device memory and stream
+// through LDS, so they count as window placements, not LDS ones.
+constexpr int LDS_RING = 4;
+bool is_ring(const mmc::Variant &v) { return v.lds == LDS_RING; }
+bool lds_resident(const mmc::Variant &v) { return v.lds != 0 && !is_ring(v); }
+
 bool variant_fits(const mmc::Variant &v, int fp64, int L, int lds_limit)
 {
     if (v.fp64 != fp64) return false;
@@ -323,9 +338,9 @@ std::vector<int> single_candidates(const mmc_ctx *c, int L, bool keep_generic = 
     for (int i = 0; i < n; ++i) {
         const mmc::Variant &v = vs[i];
         if (!variant_fits(v, c->fp64, L, lim)) continue;
-        if (place == MMC_PLACE_LDS && !v.lds) continue;
+        if (place == MMC_PLACE_LDS && !lds_resident(v)) continue;
         if (place == MMC_PLACE_HBM && (v.lds || v.window)) continue;
-        if (place == MMC_PLACE_WINDOW && !v.window) continue;
+        if (place == MMC_PLACE_WINDOW && !v.window && !is_ring(v)) continue;
         if (c->cfg.block && v.block != c->cfg.block) continue;
         if (c->cfg.lanes_per_path && v.lanes != c->cfg.lanes_per_path) continue;
         out.push_back(i);
@@ -348,9 +363,9 @@ std::vector<int> batch_candidates(int fp64, int L, int placement, bool keep_gene
         const mmc::Variant &v = vs[i];
         if (v.L != 0 && v.L != L) continue;
         if (v.lds && mmc::variant_lds_bytes(v, L) > lds_budget) continue;
-        if (placement == MMC_PLACE_LDS && !v.lds) continue;
+        if (placement == MMC_PLACE_LDS && !lds_resident(v)) continue;
         if (placement == MMC_PLACE_HBM && v.lds) continue;
-        if (placement == MMC_PLACE_WINDOW) continue;  // no batch form yet
+        if (placement == MMC_PLACE_WINDOW && !is_ring(v)) continue;  // the batch window form
         out.push_back(i);
     }
     if (keep_generic) return out;
@@ -1104,6 +1119,36 @@ mmc_ctx *mmc_load(const char *file)
 
 double mmc_last_timing_ms(const mmc_ctx *c) { return c ? c->last_ms : -1.0; }
 
+int mmc_proposal_vectors(int precision, int proposal, const uint32_t *words, int64_t n, double *xyz)
+{
+    if (!words || !xyz || n < 1 || n > (1LL << 31)) return fail(MMC_EINVAL, "need words, xyz and 1 <= n <= 2^31");
+    if ((precision != MMC_FP32 && precision != MMC_FP64) ||
+        (proposal != MMC_PROPOSAL_SPHERE && proposal != MMC_PROPOSAL_ANGLES))
+        return fail(MMC_EINVAL, "precision or proposal out of range");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return fail(MMC_EHIP, "no HIP device available (%s)", hipGetErrorString(e));
+    uint32_t *dw = nullptr;
+    double *dx = nullptr;
+    hipStream_t s = nullptr;
+    const size_t wb = (size_t)n * 2 * sizeof(uint32_t), xb = (size_t)n * 3 * sizeof(double);
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&dw, wb);
+    if (e == hipSuccess) e = hipMalloc(&dx, xb);
+    if (e == hipSuccess) e = hipMemcpyAsync(dw, words, wb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = mmc::proposal_vectors(precision == MMC_FP64, proposal == MMC_PROPOSAL_ANGLES, dw, n, dx, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(xyz, dx, xb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (dw) (void)hipFree(dw);
+    if (dx) (void)hipFree(dx);
+    if (s) (void)hipStreamDestroy(s);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return fail(MMC_ENOMEM, "device memory for %lld proposals", (long long)n);
+    }
+    return e == hipSuccess ? MMC_OK : fail(MMC_EHIP, "proposal vectors: %s", hipGetErrorString(e));
+}
+
 int mmc_plan(const mmc_ctx *c, char *buf, size_t n)
 {
     if (!c || !buf || n == 0) return fail(MMC_EINVAL, "null argument");
@@ -1429,9 +1474,9 @@ static int batch_enqueue(mmc_ctx *c, hipStream_t s)
     double total = 0, in_lds = 0;
     for (const auto &l : c->launches) {
         total += l.updates;
-        if (vs[l.variant].lds) in_lds += l.updates;
+        if (lds_resident(vs[l.variant])) in_lds += l.updates;
     }
-    const bool after_memory = !vs[c->launches[0].variant].lds && in_lds < 0.1 * total;
+    const bool after_memory = !lds_resident(vs[c->launches[0].variant]) && in_lds < 0.1 * total;
     for (size_t k = 0; k < c->launches.size(); ++k) {
         const auto &l = c->launches[k];
         hipStream_t sk = k ? c->aux[k - 1] : s;

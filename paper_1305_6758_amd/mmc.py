@@ -90,6 +90,7 @@ _SIGNATURES = [
     ("mmc_save", C.c_int, [_P, C.c_char_p]),
     ("mmc_load", _P, [C.c_char_p]),
     ("mmc_last_timing_ms", C.c_double, [_P]),
+    ("mmc_proposal_vectors", C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_uint32), C.c_int64, C.POINTER(C.c_double)]),
     ("mmc_plan", C.c_int, [_P, C.c_char_p, C.c_size_t]),
     ("mmc_destroy", None, [_P]),
     ("mmc_batch_create", _P, [C.POINTER(mmc_instance), C.c_int, C.c_uint64, C.POINTER(mmc_config)]),
@@ -307,6 +308,16 @@ def mmc_load(path):
 
 def mmc_last_timing_ms(ctx):
     return lib().mmc_last_timing_ms(ctx)
+
+
+def mmc_proposal_vectors(precision, proposal, words):
+    """words: uint32 [n, 2] -> float64 [n, 3], the engine's proposed unit vectors."""
+    import numpy as np
+    w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1, 2)
+    out = np.empty((w.shape[0], 3))
+    _check(lib().mmc_proposal_vectors(precision, proposal, w.ctypes.data_as(C.POINTER(C.c_uint32)), w.shape[0],
+                                      out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
 
 
 def mmc_plan(ctx):

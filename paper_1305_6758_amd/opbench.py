@@ -2,9 +2,10 @@
 of each instruction class in full-rate lane slots (v_add_f32 = 1), the unit of the engine's
 VALU roofline. With --copy-bytes B it instead runs one plain device-to-device copy of B bytes
 (torch), the calibration kernel for the HBM byte counters; with --copy-reps R as well it then
-times R more copies (HIP events on torch's stream), and R launches each of a hand-written
-16-byte streaming copy over a few launch shapes, and prints the bytes read and written per
-second: the streaming rate a memory-bound kernel can reach in practice.
+times R more copies (HIP events on torch's stream), and R launches each of hand-written
+16-byte streaming kernels (copy, read only, write only; plain or nontemporal accesses) over
+192 launch shapes, and prints the bytes moved per second of the best shapes: the streaming
+rates a memory-bound kernel can reach in practice.
 
 Usage: python -m paper_1305_6758_amd.opbench [--ms MS] [--copy-bytes B [--copy-reps R]]
 """
@@ -40,21 +41,30 @@ def main():
             ms = t0.elapsed_time(t1) / a.copy_reps
             out.update({"copy_reps": a.copy_reps, "ms_per_copy": ms,
                         "read_plus_write_TBps": 2 * a.copy_bytes / (ms * 1e-3) / 1e12})
-            # the hand-written streaming copy over a few launch shapes: the best of them
+            # hand-written streaming kernels (copy, read only, write only; plain or nontemporal
+            # accesses) over launch shapes: the best rate of each is the practical ceiling of
+            # that access pattern
             lib = C.CDLL(os.path.join(HERE, "libmmc_opbench.so"))
-            lib.mmc_opbench_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_int,
-                                             C.POINTER(C.c_double)]
-            shapes = {}
-            for bpc in (4, 8, 16):
-                for unroll in (1, 2, 4):
-                    t = C.c_double()
-                    rc = lib.mmc_opbench_copy(x.data_ptr(), y.data_ptr(), a.copy_bytes // 16 * 16, a.copy_reps, bpc,
-                                              unroll, C.byref(t))
-                    if rc != 0:
-                        raise RuntimeError(f"mmc_opbench_copy failed ({rc})")
-                    shapes[f"{bpc}x{unroll}"] = 2 * (a.copy_bytes // 16 * 16) / (t.value * 1e-3) / 1e12
-            best = max(shapes, key=shapes.get)
-            out["hand_copy_TBps"] = {"by_blocks_per_cu_x_unroll": shapes, "best": best, "best_TBps": shapes[best]}
+            lib.mmc_opbench_stream.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_int, C.c_int,
+                                               C.c_int, C.c_int, C.POINTER(C.c_double)]
+            nb = a.copy_bytes // 16 * 16
+            best = {}
+            for kind, name, moved in ((0, "copy", 2 * nb), (1, "read", nb), (2, "write", nb)):
+                rates = {}
+                for nt in (0, 1):
+                    for threads, bpcs in ((256, (1, 2, 4, 8, 16, 32)), (1024, (1, 2))):
+                        for bpc in bpcs:
+                            for unroll in (1, 2, 4, 8):
+                                t = C.c_double()
+                                rc = lib.mmc_opbench_stream(x.data_ptr(), y.data_ptr(), nb, a.copy_reps, kind, nt,
+                                                            threads, bpc, unroll, C.byref(t))
+                                if rc != 0:
+                                    raise RuntimeError(f"mmc_opbench_stream failed ({rc})")
+                                rates[f"{'nt' if nt else 'plain'}-t{threads}-b{bpc}-u{unroll}"] = moved / (t.value * 1e-3) / 1e12
+                top = sorted(rates, key=rates.get, reverse=True)[:5]
+                best[name] = {"best": top[0], "best_TBps": rates[top[0]], "top5": {k: rates[k] for k in top},
+                              "shapes": len(rates)}
+            out["hand_stream_TBps"] = best
         print(json.dumps(out))
         return
     lib = C.CDLL(os.path.join(HERE, "libmmc_opbench.so"))

@@ -29,6 +29,12 @@ WORKLOADS = {
     # state measured: 199 thermalisation sweeps + 1 measured sweep), FP32.
     "binder-L30-L20-p1e6-fp32": dict(precision="fp32", instances=[(L, T, 10 ** 6, 199, 1)
                                                                    for T in (1.44, 1.45) for L in (30, 20)]),
+    # The 200-sweep protocol from the other starts the paper's set-up allows: every spin along
+    # +z, or half of the paths random and half ordered (init applies to the whole batch).
+    "binder-L30-L20-p1e6-ordered-fp32": dict(precision="fp32", init="ordered",
+                                             instances=[(L, T, 10 ** 6, 199, 1) for T in (1.44, 1.45) for L in (30, 20)]),
+    "binder-L30-L20-p1e6-mixed-fp32": dict(precision="fp32", init="mixed",
+                                           instances=[(L, T, 10 ** 6, 199, 1) for T in (1.44, 1.45) for L in (30, 20)]),
     # The same crossing at equilibrium: 4000 thermalisation sweeps, then the cumulant from the
     # per-path time means of M^2 and M^4 over 4000 measured sweeps, 10^4 paths per (L, T).
     "binder-L30-L20-p1e4-s8000-fp32": dict(precision="fp32", instances=[(L, T, 10 ** 4, 4000, 4000)

@@ -26,8 +26,9 @@ SAMPLE = {
     "L16-T3-p4096-fp32": 32,
     "L32-T1.443-p1024": 16,
     "L64-T1.443-p256-fp32": 8,
-    "uneven-batch-96-fp32": 2,
+    "uneven-batch-96-fp32": 8,
     "binder-L30-L20-p1e6-fp32": 256,
+    "binder-L30-L20-p1e4-s8000-fp32": 64,
 }
 
 

@@ -23,16 +23,18 @@ from oracle import stats as S
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_binder-L30-L20-p1e6-fp32.json")
+# the equilibrated form: 10^4 paths per (L, T), 4000 + 4000 sweeps, time-averaged moments
+GOLDEN_EQ = os.path.join(os.path.dirname(__file__), "golden", "oracle_binder-L30-L20-p1e4-s8000-fp32.json")
 
 
 def say(*a):
     print(*a, flush=True)
 
 
-def golden():
-    if not os.path.exists(GOLDEN):
-        pytest.skip(f"oracle sample {GOLDEN} not written")
-    with open(GOLDEN) as f:
+def golden(path=GOLDEN):
+    if not os.path.exists(path):
+        pytest.skip(f"oracle sample {path} not written")
+    with open(path) as f:
         return json.load(f)
 
 
@@ -90,3 +92,60 @@ def test_binder_fp32_cumulants_and_crossing():
     assert abs(out["tc"] - Tc) < 1e-12 and abs(out["se_tc"] - sTc) < 1e-12
     assert abs(out["ratio"][0]["R"] - R1) < 1e-14 and abs(out["ratio"][1]["R"] - R2) < 1e-14
     say(f"U30/U20: {R1:.4f} +- {s1:.4f} (T={Ts[0]}), {R2:.4f} +- {s2:.4f} (T={Ts[1]}); crossing {Tc:.4f} +- {sTc:.4f}")
+
+
+def _batch(rows, seed, fp64):
+    from paper_1305_6758_amd import mmc
+    ctx = mmc.mmc_batch_create(rows, seed, mmc.config(precision=mmc.MMC_FP64 if fp64 else mmc.MMC_FP32))
+    try:
+        mmc.mmc_batch_run(ctx)
+        say("plan", mmc.mmc_plan(ctx), f"{mmc.mmc_last_timing_ms(ctx):.0f} ms")
+        return [mmc.mmc_batch_results(ctx, i, r[3]) for i, r in enumerate(rows)]
+    finally:
+        mmc.mmc_destroy(ctx)
+
+
+@pytest.mark.timeout(300)
+def test_equilibrated_binder_fp64_sampled_paths_match_oracle():
+    """Workload binder-L30-L20-p1e4-s8000-fp32 (the equilibrated crossing: L = 30 and 20 at
+    T = 1.44 and 1.45, 4000 + 4000 sweeps): the FP64 batch's first 8 paths of every instance
+    match the oracle's to 1e-12 over all 8000 sweeps."""
+    g = golden(GOLDEN_EQ)
+    K = 8
+    rows = [(i["L"], i["T"], 1.0, K, i["n_therm"], i["n_meas"]) for i in g["instances"]]
+    say("case equilibrated binder fp64 batch,", K, "paths per instance")
+    res = _batch(rows, g["seed"], fp64=True)
+    for i, inst in enumerate(g["instances"]):
+        ora = {k: v[:K] for k, v in as_results(inst).items()}
+        assert_results_close(res[i], ora, 1e-12)
+
+
+@pytest.mark.timeout(600)
+def test_equilibrated_binder_fp32_cumulants_and_crossing():
+    """The same workload at full size in FP32 (10^4 paths per instance, the benchmark's batch):
+    <e>, <M^2>, <M^4> and the cumulant U of every instance agree with the oracle's 64 sampled
+    paths within 4 standard errors; the crossing of U_30/U_20 from the engine's cumulants lies
+    within the paper's T_c = 1.442(20) (Sec. 4), widened by 4 of its own standard errors."""
+    g = golden(GOLDEN_EQ)
+    rows = [(i["L"], i["T"], 1.0, i["n_paths"], i["n_therm"], i["n_meas"]) for i in g["instances"]]
+    say("case equilibrated binder fp32 batch, full size")
+    res = _batch(rows, g["seed"], fp64=False)
+    u, se = [], []
+    for inst, r in zip(g["instances"], res):
+        ora = as_results(inst)
+        for key in ("e_mean", "m2_mean", "m4_mean"):
+            ma, sa = mean_se(r[key])
+            mb, sb = mean_se(ora[key])
+            bound = 4.0 * math.hypot(sa, sb)
+            assert abs(ma - mb) <= bound, f"L={inst['L']} T={inst['T']} {key}: {ma} vs {mb} (4 sigma {bound})"
+        Ur, ser = S.binder_cumulant(r["m2_mean"], r["m4_mean"])
+        Uo, seo = S.binder_cumulant(ora["m2_mean"], ora["m4_mean"])
+        say(f"L={inst['L']} T={inst['T']}: U = {Ur:.5f} +- {ser:.5f} (oracle, {len(inst['e_mean'])} paths: "
+            f"{Uo:.5f} +- {seo:.5f})")
+        assert abs(Ur - Uo) <= 4.0 * math.hypot(ser, seo)
+        u.append(Ur)
+        se.append(ser)
+    Ts = [g["instances"][0]["T"], g["instances"][2]["T"]]
+    Tc, sTc, R1, s1, R2, s2 = S.cumulant_crossing(Ts[0], Ts[1], u, se)
+    say(f"U30/U20: {R1:.4f} +- {s1:.4f} (T={Ts[0]}), {R2:.4f} +- {s2:.4f} (T={Ts[1]}); crossing {Tc:.4f} +- {sTc:.4f}")
+    assert abs(Tc - 1.442) <= 0.020 + 4.0 * sTc

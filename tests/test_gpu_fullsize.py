@@ -124,8 +124,9 @@ def test_L32_fp32_and_fp64():
 def test_uneven_batch():
     """The uneven batch (96 instances, L = 8 ... 48, T = 1 ... 2, 64-2048 paths, 2000 + 2000
     sweeps) in one persistent launch: FP64 batch on the sampled paths matches the oracle to
-    1e-12; the FP32 batch agrees with the oracle per instance within 4 sigma (z-scores pooled:
-    none beyond 4.5 and their mean square near 1)."""
+    1e-12; the FP32 batch agrees with the oracle per instance and observable within 4 sigma,
+    SE_oracle taken from the GPU's per-path spread of the instance over sqrt(K) while the
+    oracle sample has fewer than 16 paths, and the z-scores' mean square stays below 2."""
     g = golden("uneven-batch-96-fp32")
     insts = [(i["L"], i["T"], i["n_paths"], i["n_therm"], i["n_meas"]) for i in g["instances"]]
     K = g["paths_per_instance"]
@@ -135,19 +136,17 @@ def test_uneven_batch():
         assert_results_close(r64[i], as_results(inst), TOL64)
     say("case uneven fp32 full")
     r32 = run_batch(insts, fp64=False)
-    # FP32 vs the FP64 engine's sampled paths is weak with K = 2; pool z-scores against the
-    # oracle over the 96 instances using the GPU's per-instance spread for both sides
     z = []
     for i, inst in enumerate(g["instances"]):
         ora = as_results(inst)
-        for key in ("e_mean", "absm_mean"):
+        for key in ("e_mean", "absm_mean", "m2_mean", "m4_mean"):
             m32, s32 = mean_se(r32[i][key])
-            sd = float(np.std(r32[i][key], ddof=1))
+            sd = float(np.std(r32[i][key] if K < 16 else ora[key], ddof=1))
             mo = float(np.mean(ora[key]))
             z.append((m32 - mo) / math.hypot(s32, sd / math.sqrt(K)))
+            assert abs(z[-1]) <= 4.0, f"instance {i} (L={inst['L']}, T={inst['T']:.4g}) {key}: z = {z[-1]:.2f}"
     z = np.array(z)
     say(f"uneven batch: max |z| = {np.max(np.abs(z)):.2f}, mean z^2 = {np.mean(z * z):.2f} over {z.size}")
-    assert np.max(np.abs(z)) < 4.5
     assert np.mean(z * z) < 2.0
 
 

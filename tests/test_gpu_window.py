@@ -25,7 +25,7 @@ def say(*a):
 
 
 FP64_VARIANTS = [(12, "f64-win-L12-d1-b256"), (16, "f64-win-L16-d2-b256"), (16, "f64-gwin-L16-d2-b256"),
-                 (24, "f64-gwin-L24-d3-b512")]
+                 (24, "f64-gwin-L24-d3-b512"), (12, "f64-ring-L12-b256"), (16, "f64-ring-L16-b256")]
 
 
 @pytest.mark.parametrize("L,variant", FP64_VARIANTS)
@@ -45,7 +45,7 @@ def test_window_fp64_matches_oracle(L, variant):
             assert max_abs_diff(sp[p], ora["spins"][p]) <= TOL64
 
 
-@pytest.mark.parametrize("variant", ["f64-win-L16-d2-b256", "f64-gwin-L16-d2-b256"])
+@pytest.mark.parametrize("variant", ["f64-win-L16-d2-b256", "f64-gwin-L16-d2-b256", "f64-ring-L16-b256"])
 def test_window_fp64_split_runs(variant):
     """Sweeps run in chunks of 3, 1, 4 and the rest equal one uninterrupted run."""
     from paper_1305_6758_amd import mmc
@@ -70,7 +70,8 @@ def test_window_fp64_split_runs(variant):
 
 FP32_VARIANTS = [(24, "f32-win-L24-d2-b512"), (24, "f32-win-L24-d3-b1024"), (30, "f32-win-L30-d2-b1024"),
                  (32, "f32-win-L32-d2-b512"), (32, "f32-win-L32-d2-b1024"), (32, "f32-gwin-L32-d2-b1024"),
-                 (48, "f32-gwin-L48-d1-b1024"), (64, "f32-gwin-L64-d1-b1024")]
+                 (48, "f32-gwin-L48-d1-b1024"), (64, "f32-gwin-L64-d1-b1024"), (16, "f32-ring-L16-b256"),
+                 (32, "f32-ring-L32-b512"), (48, "f32-ring-L48-b1024"), (48, "f32-ring-L48-b768")]
 
 
 @pytest.mark.parametrize("L,variant", FP32_VARIANTS)
@@ -104,3 +105,27 @@ def test_set_variant_rejects_what_does_not_fit():
             mmc.mmc_set_variant(ctx, "f32-hbm-L32-g512-b512")
     finally:
         mmc.mmc_destroy(ctx)
+
+
+def test_ring_batch_equals_device_memory_batch():
+    """The plane-ring batch kernels (L = 48, 1024 and 768 lanes) against the device-memory batch
+    kernel on the same instances, ragged path counts, renormalisation every 5 sweeps: identical
+    accept counts (the spins are identical), energies and magnetisations to FP32 rounding."""
+    from paper_1305_6758_amd import mmc
+    insts = [(48, 1.3, 1.0, 3, 6, 5), (48, 1.45, 1.0, 2, 5, 6), (48, 2.0, -1.0, 1, 3, 3)]
+    got = []
+    for pin in ("f32-hbm-L48-g512", "f32-ring-L48-g1024", "f32-ring-L48-g768"):
+        say(f"case ring batch {pin}")
+        ctx = mmc.mmc_batch_create(insts, 1234, mmc.config(precision=mmc.MMC_FP32, renorm_every=5))
+        try:
+            mmc.mmc_set_variant(ctx, pin)
+            assert pin in mmc.mmc_plan(ctx)
+            mmc.mmc_batch_run(ctx)
+            got.append([mmc.mmc_batch_results(ctx, i, x[3]) for i, x in enumerate(insts)])
+        finally:
+            mmc.mmc_destroy(ctx)
+    for g in got[1:]:
+        for i in range(len(insts)):
+            assert np.array_equal(g[i]["n_accept"], got[0][i]["n_accept"]), i
+            for k in ("e_mean", "absm_mean", "final_e"):
+                assert max_abs_diff(g[i][k], got[0][i][k]) < 1e-5, (i, k)

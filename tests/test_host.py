@@ -142,7 +142,8 @@ def test_bench_refuses_several_gpus():
 
 def test_bench_device_memory_bytes_by_placement():
     """bench.py prices each instance by its variant's placement: 36 B per update in device
-    memory, 18 B for the colour split, 24 B for the x/y split, none in LDS or a window."""
+    memory, 18 B for the colour split, 24 B for the x/y split, 24 + 24/L B for the plane ring,
+    none in LDS or a multi-sweep window."""
     sys.path.insert(0, ROOT)
     import bench
     insts = [(48, 1.0, 10, 1, 1), (32, 1.2, 4, 2, 2), (24, 1.4, 3, 1, 0), (16, 1.6, 5, 3, 3), (32, 1.8, 2, 1, 1)]
@@ -154,6 +155,9 @@ def test_bench_device_memory_bytes_by_placement():
     assert total == 36 * (u[0] + u[4]) + 24 * u[1] + 18 * u[2]
     assert bench.device_memory_bytes([(32, 1.4, 8, 5, 5)], "f32-win-L32-d2-b1024") == (0, 0, 0)
     assert bench.device_memory_bytes([(32, 1.4, 8, 5, 5)], "f32-split-L30-g1024-b1024")[0] == 18 * 8 * 32 ** 3 * 10
+    # the plane ring: 12 (2L + 4)/(2L) B read + 12 B written per update, 24.5 B at L = 48
+    assert bench.device_memory_bytes([(48, 1.4, 2, 3, 3)], "f32-ring-L48-b1024") == (24.5 * 2 * 48 ** 3 * 6,
+                                                                                   2 * 48 ** 3 * 6, 0)
     with pytest.raises(ValueError):
         bench.device_memory_bytes(insts, "batch launches=1 [x]; L48:f32-hbm-L48-g512")
 

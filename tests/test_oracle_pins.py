@@ -77,6 +77,48 @@ def test_uniform_exact_open_interval():
 
 # ---------------------------------------------------------------- proposal
 
+def test_fp32_uniform_grid_exact():
+    """The FP32 engine's uniforms (the oracle's FP32-grid option): u = ((w >> 8) | 1) / 2^24
+    exactly, an odd multiple of 2^-24 inside (0, 1), checked with integer arithmetic; the grid
+    reaches the sweep: at beta = 0 the spins after one sweep are the FP32-grid unit vectors of
+    the sweep-0 words, whose z = 2u - 1 is exact, and they differ from the FP64-grid spins by
+    no more than the grids do (|du| < 2^-24, so |dz| < 2^-23 and a turn of phi below 2 pi 2^-24)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(3)
+    words = [0, 1, 255, 256, 511, 0x7FFFFFFF, 0x80000000, 0xFFFFFEFF, 0xFFFFFFFF] + list(rng.integers(0, 2 ** 32, 2000))
+    for w in words:
+        w = int(w)
+        want = Fraction((w >> 8) | 1, 2 ** 24)
+        got = O.uniform_fp32(w)
+        assert Fraction(got) == want and 0 < got < 1
+        assert abs(Fraction(got) - Fraction(O.lib().mmco_uniform(w))) < Fraction(1, 2 ** 24)
+    L, N, path = 4, 64, 2
+    r32 = O.run_paths(L, math.inf, n_therm=1, path_begin=path, path_end=path + 1, want_spins=True, uniforms="fp32")
+    r64 = O.run_paths(L, math.inf, n_therm=1, path_begin=path, path_end=path + 1, want_spins=True)
+    key = np.array([1234, 0], dtype=np.uint32)
+    w = P.philox4x32_10(np.array([[i, 0, path, 1] for i in range(N)], dtype=np.uint32), key)
+    want = O.unit_vectors(w[:, :2], uniforms="fp32")
+    assert np.array_equal(r32["spins"][0], want)
+    z_exact = np.array([2.0 * float(Fraction((int(a) >> 8) | 1, 2 ** 24)) - 1.0 for a in w[:, 0]])
+    assert np.array_equal(r32["spins"][0][:, 2], z_exact)
+    assert np.max(np.abs(r32["spins"][0][:, 2] - r64["spins"][0][:, 2])) < 2.0 ** -23
+    assert np.max(np.abs(r32["spins"][0] - r64["spins"][0])) < 1e-3  # near the poles r moves by sqrt(|dz|)
+    assert not np.array_equal(r32["spins"][0], r64["spins"][0])
+
+
+def test_fp32_grid_two_spin_stationary_law():
+    """The FP32-grid oracle is still a correct sampler: the two-spin law (density proportional
+    to exp(beta J c)) holds with uniforms at 2^-24 resolution."""
+    K, J = 2.0, 1.0
+    T = J / K
+    r = O.run_paths(2, T, J=J, n_therm=60, n_meas=0, path_end=4000, dim=1, periodic=False, uniforms="fp32")
+    c = -2.0 * r["final_e"] / J
+    cdf = lambda x: (np.exp(K * x) - math.exp(-K)) / (math.exp(K) - math.exp(-K))
+    assert ss.kstest(c, cdf).pvalue > 1e-3
+    m, se = S.mean_se(c)
+    assert within_4sigma(m, se, langevin(K))
+
+
 def test_proposal_uniform_on_sphere():
     """Proposal of the uniform-sphere reading: |S| = 1, E[S] = 0, E[S_a S_b] = delta_ab/3,
     z uniform on (-1,1), phi uniform on [0, 2 pi). Catches z = u instead of 2u - 1, a
