@@ -299,6 +299,52 @@ int mmc_opbench_copy(const void *src, void *dst, size_t bytes, int reps, int blo
     return mmc_opbench_stream(src, dst, bytes, reps, 0, 0, 256, blocks_per_cu, unroll, ms);
 }
 
+// The update mix alone at full occupancy for iters iterations (two updates per lane each),
+// after one warm-up launch: updates per second, kernel time (HIP events) and the mean shader
+// clock of the run in MHz (s_memtime cycles over s_memrealtime ticks of each workgroup, the
+// latter at the device's wall-clock rate). Returns 0, -1 on bad arguments, -3 on a HIP error.
+int mmc_opbench_update_mix(int iters, double *updates_per_s, double *ms, double *clock_mhz)
+{
+    if (iters < 1 || !updates_per_s || !ms || !clock_mhz) return -1;
+    int dev = 0, cus = 0, wall_khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+        return -3;
+    const int blocks = cus * 8;
+    uint32_t *sink = nullptr;
+    if (hipMalloc(&sink, (size_t)blocks * 256 * sizeof(uint32_t)) != hipSuccess) return -3;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_update_mix, dim3(blocks), dim3(256), 0, 0, sink, 1);  // warm-up
+        (void)hipEventRecord(a, 0);
+        hipLaunchKernelGGL(k_update_mix, dim3(blocks), dim3(256), 0, 0, sink, iters);
+        (void)hipEventRecord(b, 0);
+        e = hipEventSynchronize(b);
+    }
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    double cyc = 0, ticks = 0;
+    if (e == hipSuccess) {
+        uint64_t *h = new uint64_t[(size_t)blocks * 128];
+        e = hipMemcpy(h, sink, (size_t)blocks * 256 * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        for (int i = 0; i < blocks && e == hipSuccess; ++i) {
+            cyc += (double)h[(size_t)i * 128];
+            ticks += (double)h[(size_t)i * 128 + 1];
+        }
+        delete[] h;
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipFree(sink);
+    if (e != hipSuccess || t <= 0 || ticks <= 0) return -3;
+    *ms = t;
+    *updates_per_s = (double)blocks * 256.0 * 2.0 * (double)iters / (t * 1e-3);
+    *clock_mhz = cyc / (ticks / ((double)wall_khz * 1e3)) / 1e6;
+    return 0;
+}
+
 int mmc_opbench_count(void) { return (int)(sizeof(k_ops) / sizeof(k_ops[0])); }
 
 const char *mmc_opbench_name(int i) { return (i >= 0 && i < mmc_opbench_count()) ? k_ops[i].name : nullptr; }

@@ -63,6 +63,16 @@ def test_arguments_validated_without_gpu():
     mmc.mmc_destroy(None)
 
 
+def test_measurement_library_exports_what_bench_calls():
+    """libmmc_opbench.so (the instruction-rate and streaming probes) exports the calls bench.py
+    and opbench.py make: the update-mix ceiling with its clock, and the streaming kernels."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_1305_6758_amd", "libmmc_opbench.so"))
+    for name in ("mmc_opbench_update_mix", "mmc_opbench_stream", "mmc_opbench_copy", "mmc_opbench_run",
+                 "mmc_opbench_count", "mmc_opbench_name"):
+        assert hasattr(lib, name), name
+
+
 def test_load_rejects_missing_or_foreign_files(tmp_path):
     from paper_1305_6758_amd import mmc
     with pytest.raises(mmc.MMCError):
