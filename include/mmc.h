@@ -323,6 +323,35 @@ int mmc_batch_results(const mmc_ctx *ctx, int inst, mmc_path_result *out, int n_
 /* Statistics of instance inst. */
 int mmc_batch_stats(const mmc_ctx *ctx, int inst, mmc_stats_t *out);
 
+/* ---------------------------------------------------------------- allocation-free batch
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the batch of mmc_batch_create + mmc_batch_run +
+ * mmc_batch_results in one call that allocates nothing. Every piece of device memory the run
+ * needs besides the caller's output lives in a static device array of
+ * MMC_STATIC_SCRATCH_BYTES that each GPU the library runs on holds until the process ends.
+ *
+ * inst, n_inst, seed and cfg as for mmc_batch_create (instance i draws Philox instance word
+ * i; cfg may be NULL; cfg->placement AUTO or LDS, the sphere proposal, the Heisenberg model).
+ * Every instance's whole lattice must fit in a workgroup's LDS (L <= 20 in FP32, L <= 16 in
+ * FP64): each side runs on its default LDS batch variant -- the first one compiled for that L,
+ * else the first generic one, the variant mmc_batch_create starts from before its tuner --
+ * so the results equal those of mmc_batch_run with the same variants pinned. At most
+ * MMC_STATIC_MAX_INSTANCES instances and MMC_STATIC_MAX_PATHS paths in all.
+ * out: caller-owned DEVICE memory of sum(n_paths) results, instance 0's paths first, then
+ * instance 1's, and so on. hip_stream: the caller's stream (NULL: the null stream); the call
+ * only enqueues work on it and returns; the results are in out when the stream gets there.
+ * Calls on one GPU share its scratch array: calls whose work overlaps on that GPU (other
+ * streams, other threads) race and must be ordered by the caller. Allocates no device
+ * memory and no host heap memory.
+ * Errors: MMC_EINVAL (null pointers, n_inst or the total path count beyond the limits, an
+ * instance out of range), MMC_EUNSUPPORTED (a lattice that needs device-memory spins, or a
+ * configuration the static batch does not run), MMC_EHIP (no device, launch failure). */
+#define MMC_STATIC_SCRATCH_BYTES ((size_t)18 << 20)
+#define MMC_STATIC_MAX_INSTANCES 256
+#define MMC_STATIC_MAX_PATHS 131072
+int mmc_batch_run_static(const mmc_instance *inst, int n_inst, uint64_t seed, const mmc_config *cfg,
+                         mmc_path_result *out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ ARCH = "gfx950"
 # trajectory); no packed FP32 instructions.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
-SOURCES = ["kernels.hip", "ising.hip", "runtime.cpp", "stats.cpp"]
+SOURCES = ["kernels.hip", "ising.hip", "static_run.hip", "runtime.cpp", "stats.cpp"]
 
 
 def _compile(src, verbose):

@@ -19,6 +19,7 @@ MMC_INIT_SPHERE, MMC_INIT_ANGLES, MMC_INIT_ORDERED, MMC_INIT_MIXED = 0, 1, 2, 3
 MMC_PROPOSAL_SPHERE, MMC_PROPOSAL_ANGLES = 0, 1
 MMC_MODEL_HEISENBERG3D, MMC_MODEL_ISING2D = 0, 1
 MMC_PLACE_AUTO, MMC_PLACE_LDS, MMC_PLACE_HBM, MMC_PLACE_PLAIN, MMC_PLACE_WINDOW = 0, 1, 2, 3, 4
+MMC_STATIC_SCRATCH_BYTES, MMC_STATIC_MAX_INSTANCES, MMC_STATIC_MAX_PATHS = 18 << 20, 256, 131072
 
 
 class mmc_config(C.Structure):
@@ -97,6 +98,7 @@ _SIGNATURES = [
     ("mmc_batch_run", C.c_int, [_P]),
     ("mmc_batch_results", C.c_int, [_P, C.c_int, C.POINTER(mmc_path_result), C.c_int]),
     ("mmc_batch_stats", C.c_int, [_P, C.c_int, C.POINTER(mmc_stats_t)]),
+    ("mmc_batch_run_static", C.c_int, [C.POINTER(mmc_instance), C.c_int, C.c_uint64, C.POINTER(mmc_config), _P, _P]),
 ]
 EXPORTED = [s[0] for s in _SIGNATURES]
 
@@ -350,6 +352,21 @@ def mmc_batch_stats(ctx, inst):
     s = mmc_stats_t()
     _check(lib().mmc_batch_stats(ctx, inst, C.byref(s)))
     return _stats_dict(s)
+
+
+def mmc_batch_run_static(instances, seed, cfg, out_dev, stream):
+    """instances: list of (L, T, J, n_paths, n_therm, n_meas); out_dev: device address of
+    sum(n_paths) mmc_path_result records; stream: HIP stream handle (0: null stream). Enqueues
+    the run and returns."""
+    arr = (mmc_instance * len(instances))(*[mmc_instance(*x) for x in instances])
+    return _check(lib().mmc_batch_run_static(arr, len(instances), seed, C.byref(cfg) if cfg else None, out_dev,
+                                             stream))
+
+
+def path_results_from_bytes(raw, n):
+    """n mmc_path_result records from a bytes-like host copy of device memory -> dict of arrays."""
+    buf = np.frombuffer(bytes(raw[:n * RESULT_DTYPE.itemsize]), dtype=RESULT_DTYPE, count=n)
+    return _results_to_numpy(buf)
 
 
 # ---------------------------------------------------------------- torch-backed workspace
