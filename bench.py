@@ -107,14 +107,16 @@ def measured_traffic(workload, kernel="k_batch_f32"):
 # update, read and written per colour-1 update), 24 for the x/y split (as the colour split,
 # plus colour 0's z: read and written per colour-0 update, read once per colour-1 update);
 # LDS-resident lattices (and windows, whose traffic depends on the pass length) move none here.
-BYTES_PER_UPDATE = {"-hbm-": 36.0, "-split-": 18.0, "-splitxy-": 24.0, "-ring-": None}
-BYTES_PER_UPDATE_BY_KIND = {"device-memory": 36, "split": 18, "splitxy": 24, "ring": "24 + 24/L"}
+BYTES_PER_UPDATE = {"-hbm-": 36.0, "-split-": 18.0, "-splitxy-": 24.0, "-ring-": None, "-hring-": None}
+BYTES_PER_UPDATE_BY_KIND = {"device-memory": 36, "split": 18, "splitxy": 24, "ring": "24 + 24/L",
+                            "half ring": "24 + 12/L"}
 
 
-def ring_bytes_per_update(L):
+def ring_bytes_per_update(L, half=False):
     """The plane ring reads each half-plane once per sweep plus four half-planes twice
-    (12 (2L + 4) / (2L) B per update) and writes every site once (12 B)."""
-    return 12.0 * (2 * L + 4) / (2 * L) + 12.0
+    (12 (2L + 4) / (2L) B per update) and writes every site once (12 B); the half ring reads
+    only colour 0's two planes twice (colour 1 once, from device memory through the L2)."""
+    return 12.0 * (2 * L + (2 if half else 4)) / (2 * L) + 12.0
 
 
 def device_memory_bytes(instances, plan):
@@ -131,8 +133,9 @@ def device_memory_bytes(instances, plan):
             if k in v:
                 upd = p * L ** 3 * (nt + nm)
                 upd_of[k] += upd
-                total += upd * (ring_bytes_per_update(L) if k == "-ring-" else BYTES_PER_UPDATE[k])
-    return total, upd_of["-hbm-"] + upd_of["-ring-"], upd_of["-split-"] + upd_of["-splitxy-"]
+                total += upd * (ring_bytes_per_update(L, k == "-hring-") if k in ("-ring-", "-hring-")
+                                else BYTES_PER_UPDATE[k])
+    return total, upd_of["-hbm-"] + upd_of["-ring-"] + upd_of["-hring-"], upd_of["-split-"] + upd_of["-splitxy-"]
 
 
 def log(*a):
@@ -209,13 +212,14 @@ def four_sigma_vs_oracle(results, golden):
     return ok, out
 
 
-def run_batched(instances, steps, warmup, init="sphere"):
+def run_batched(instances, steps, warmup, init="sphere", batch_launch="auto"):
     import torch
     from paper_1305_6758_amd import mmc
     inits = {"sphere": mmc.MMC_INIT_SPHERE, "angles": mmc.MMC_INIT_ANGLES, "ordered": mmc.MMC_INIT_ORDERED,
              "mixed": mmc.MMC_INIT_MIXED}
+    launch = {"auto": mmc.MMC_BATCH_AUTO, "fused": mmc.MMC_BATCH_FUSED, "per-variant": mmc.MMC_BATCH_PER_VARIANT}
     ctx = mmc.mmc_batch_create([(L, T, 1.0, p, nt, nm) for (L, T, p, nt, nm) in instances], 1234,
-                               mmc.config(precision=mmc.MMC_FP32, init=inits[init]))
+                               mmc.config(precision=mmc.MMC_FP32, init=inits[init], batch_launch=launch[batch_launch]))
     ws = mmc.Workspace(ctx)
     plan = mmc.mmc_plan(ctx)
     log("plan:", plan)
@@ -515,13 +519,15 @@ def measure_workload(name, steps, warmup, mix, a, plain_paths=None, compact=Fals
         wall, kernel_ms, results, stats, plan = run_single(instances[0], steps, warmup, place, a.variant)
     else:
         wall, kernel_ms, results, stats, plan = run_batched(instances, steps, warmup,
-                                                            init=WORKLOADS[name].get("init", "sphere"))
+                                                            init=WORKLOADS[name].get("init", "sphere"),
+                                                            batch_launch=a.batch_launch)
     value = upd_step * steps / wall
     kms = sum(kernel_ms) / len(kernel_ms)
     hbm_bytes, hbm_upd, split_upd = device_memory_bytes(instances, plan)
     # the batch runs one persistent kernel per variant in use: name them by their variants
     launched = re.findall(r"\[(\S+) block=\d+ workgroups=", plan)
-    kernel_name = ("k_batch<float> " + " + ".join(launched)) if not single else (
+    fused = any(x.startswith("fused:") for x in launched)
+    kernel_name = (("k_batch_fused<float> " if fused else "k_batch<float> ") + " + ".join(launched)) if not single else (
         "k_window<float>" if "win-" in plan else "k_resident<float>")
     kernel_family = kernel_name.split()[0].replace("<float>", "_f32")
     traffic = measured_traffic(name, kernel_family)
@@ -542,7 +548,7 @@ def measure_workload(name, steps, warmup, mix, a, plain_paths=None, compact=Fals
               "instances": len(instances),
               "paths": sum(x[2] for x in instances), "n_therm": sorted({x[3] for x in instances}),
               "n_meas": sorted({x[4] for x in instances}), "updates_per_step": upd_step, "seed": 1234,
-              "plan": plan, "engine": "single-instance, tuned" if single else "batch",
+              "plan": plan, "engine": "single-instance, tuned" if single else f"batch ({a.batch_launch} launch)",
               "init": WORKLOADS[name].get("init", "sphere")}
     roof = valu_roofline(upd_step, kms, mix, kernel_name)
     roof["traffic"] = traffic
@@ -610,6 +616,8 @@ def main():
     ap.add_argument("--tune-only", action="store_true",
                     help="run the tuners of the workload's contexts (their choices go to the MMC_TUNE_CACHE "
                          "file when set) and exit, so that a later (profiled) run launches only its steps")
+    ap.add_argument("--batch-launch", default="auto", choices=["auto", "fused", "per-variant"],
+                    help="batch workloads: one fused persistent kernel, or one kernel per variant (auto: the library's rule)")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-largest", action="store_true",

@@ -106,6 +106,18 @@ typedef enum {
     MMC_PLACE_WINDOW = 4
 } mmc_placement;
 
+/* How a batch runs (mmc_config.batch_launch). FUSED: one persistent kernel for the whole batch,
+ * whose workgroups take (instance, path group) items from one queue, largest first, and run
+ * each with the code of the instance's variant (FP32; the variants of L = 8, 12, 16, 20, 24,
+ * 30, 32, 48 the tuner picks by default have a member in it; results as with PER_VARIANT).
+ * PER_VARIANT: one persistent kernel per variant in use, each with its own queue, side by side
+ * in the captured graph. AUTO (default): PER_VARIANT. The fused kernel holds one 1024-lane
+ * workgroup per CU whenever a device-memory member is in the batch (its LDS sets the size), so
+ * the LDS-resident members run at fewer waves per CU than in their own launches; on a batch
+ * mixing L = 8..48 it takes longer than the per-variant launches. An explicit FUSED request
+ * that some variant cannot meet makes the batch's runs fail with MMC_EUNSUPPORTED. */
+typedef enum { MMC_BATCH_AUTO = 0, MMC_BATCH_FUSED = 1, MMC_BATCH_PER_VARIANT = 2 } mmc_batch_launch;
+
 /* Zero-initialised = defaults. */
 typedef struct {
     int precision;      /* mmc_precision, default MMC_FP32 */
@@ -119,6 +131,7 @@ typedef struct {
     int async;          /* nonzero: mmc_run/mmc_batch_run return without waiting */
     int proposal;       /* mmc_proposal, default MMC_PROPOSAL_SPHERE */
     int model;          /* mmc_model, default MMC_MODEL_HEISENBERG3D */
+    int batch_launch;   /* batches: mmc_batch_launch, default MMC_BATCH_AUTO */
 } mmc_config;
 
 /* Per-path output. Means over the n_meas measured sweeps (NaN when n_meas = 0), per site:
@@ -297,7 +310,8 @@ int mmc_proposal_vectors(int precision, int proposal, const uint32_t *words, int
 /* Human-readable description of the chosen kernel variant(s), NUL-terminated: the variant's
  * name for a single instance ("plain-f64" for the plain engine); for a batch
  * "batch launches=N [<variants> block=B workgroups=W items=I] ...; L<side>:<variant> ..."
- * (one bracket per persistent launch, then the variant of each instance in order). */
+ * (one bracket per persistent launch -- "fused:<variants>" for the fused kernel -- then the
+ * variant of each instance in order). */
 int mmc_plan(const mmc_ctx *ctx, char *buf, size_t n);
 
 /* Frees the context and the device memory it allocated. NULL is ignored. */

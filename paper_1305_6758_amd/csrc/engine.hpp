@@ -67,7 +67,8 @@ struct Variant {
     int L;           // compile-time side, 0 = any even L
     int lds;         // 1: spins in LDS, 0: in device memory, 2: colour 0 in LDS, colour 1 in device memory,
                      // 3: colour 0's x and y components in LDS, the rest in device memory,
-                     // 4: in device memory, swept through a ring of z-planes in LDS
+                     // 4: in device memory, swept through a ring of z-planes in LDS,
+                     // 5: in device memory, colour 0 swept through a ring of z-planes in LDS
     int block;       // threads per workgroup
     int lanes;       // threads per path (block % lanes == 0)
     size_t lds_bytes;                 // dynamic LDS per workgroup
@@ -92,6 +93,19 @@ hipError_t launch_batch(const BatchDev &b, int fp64, int variant, int grid, size
 int batch_blocks_per_cu(int fp64, int variant, size_t lds);  // resident workgroups per CU; 0 if unknown
 int batch_paths_per_item(int fp64, int variant);
 size_t batch_slot_bytes(int fp64, int variant, int L);  // HBM slot bytes needed (0 for LDS)
+
+// The fused batch kernel (one launch for a batch mixing lattice sides, FP32): the member that
+// runs a batch variant's paths identically, or -1; per member its dynamic LDS, spin-slot bytes
+// per workgroup and paths per item; resident workgroups per CU at a given LDS size.
+int fused_member(int fp64, const char *batch_variant);
+size_t fused_lds_bytes(int member);
+size_t fused_slot_bytes(int member);
+int fused_paths_per_item(int member);
+int fused_blocks_per_cu(size_t lds);
+int fused_block();  // threads per workgroup of the fused kernel
+const char *fused_member_name(int member);  // the batch variant a member runs like
+int fused_member_like(int fp64, int L, int place);  // a member of that side and placement, or -1
+hipError_t launch_fused(const BatchDev &b, int grid, size_t lds, hipStream_t s);
 
 hipError_t prepare_kernels(int max_lds);  // once per process, before the first launch
 

@@ -18,6 +18,7 @@
 #include "philox.hpp"
 
 #include <algorithm>
+#include <string.h>
 #include <type_traits>
 
 namespace mmc {
@@ -129,7 +130,7 @@ enum Map { COLZ = 0, FLAT = 1 };
 // LDS and colour 1 in device memory (sides whose lattice is too large for LDS but half of it
 // is not: 22 <= L <= 30 in FP32), or only colour 0's x and y components in LDS (a third of
 // the lattice: L = 32 and 34 in FP32).
-enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2, PL_SPLIT_XY = 3, PL_RING = 4 };
+enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2, PL_SPLIT_XY = 3, PL_RING = 4, PL_HRING = 5 };
 
 // Everything a path group needs during its sweeps; path, key and counter word are
 // wave-uniform (each wave belongs to one path group).
@@ -721,12 +722,17 @@ __device__ __attribute__((noinline)) void copy_spins(T *__restrict__ dst, const 
 // when its plane first enters the ring in the pass (colour 0 virtual planes 0 .. L - 1, every
 // colour-1 load) and written back whether or not its move is accepted, which leaves the spins
 // bit-identical to the other kernels'.
+// Half ring (PL_HRING, for sides whose two-colour slots do not fit: L = 64 in FP32): the ring
+// holds colour 0 only (five slots of one half-plane); colour 1 is read and written in place in
+// device memory, where the L2 keeps each colour-1 plane between its first read (colour 0 of
+// the plane below) and its update three steps later. Renormalisation passes normalise colour
+// 1 in place before the pass (the colour-0 rule as above).
 constexpr int RING = 5;
 
 template <typename T>
-__host__ __device__ constexpr size_t ring_lds_bytes(int L, int B)
+__host__ __device__ constexpr size_t ring_lds_bytes(int L, int B, bool half = false)
 {
-    return (size_t)RING * 3 * (size_t)L * L * sizeof(T) + 128 + (size_t)(B / 16) * 4 * sizeof(T);
+    return (size_t)RING * (half ? 3 : 6) * ((size_t)L * L / 2) * sizeof(T) + 128 + (size_t)(B / 16) * 4 * sizeof(T);
 }
 
 // LDS bytes of one workgroup: spins (all of them, or colour 0), accumulators, reduction
@@ -735,6 +741,7 @@ template <typename T>
 __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, int pl)
 {
     if (pl == PL_RING) return ring_lds_bytes<T>(L, B);
+    if (pl == PL_HRING) return ring_lds_bytes<T>(L, B, true);
     const size_t ns = 3 * (size_t)L * L * L * sizeof(T);
     return (size_t)(B / G) * (pl == PL_LDS ? ns : pl == PL_SPLIT ? ns / 2 : pl == PL_SPLIT_XY ? ns / 3 : 0) +
            (size_t)(B / G) * 128 +
@@ -795,14 +802,15 @@ __device__ __forceinline__ void ring_load(RingRegs<T, LC, B> &r, const T *gsp, i
     }
 }
 
-// Stores what ring_load brought in into ring slots s0 / s1 (normalising first where n0 / n1).
-template <typename T, int LC, int B>
+// Stores what ring_load brought in into ring slots s0 / s1 (normalising first where n0 / n1);
+// HR: slots of colour 0 only.
+template <typename T, int LC, int B, bool HR = false>
 __device__ __forceinline__ void ring_store(RingRegs<T, LC, B> &r, T *ring, int c0, int s0, bool h0, bool n0, int c1,
                                            int s1, bool h1, bool n1, int tid)
 {
     using R = RingRegs<T, LC, B>;
     using V = typename R::V;
-    constexpr int PLANE = R::PLANE, NQ = R::NQ, E = R::E, SLOT = 6 * PLANE;
+    constexpr int PLANE = R::PLANE, NQ = R::NQ, E = R::E, SLOT = (HR ? 3 : 6) * PLANE;
 #pragma unroll
     for (int i = 0; i < R::R; ++i) {
         const int q = tid + B * i;
@@ -822,57 +830,99 @@ __device__ __forceinline__ void ring_store(RingRegs<T, LC, B> &r, T *ring, int c
 // (B/2) t, its site id less the x-parity and the z part, the parity of y, and the in-plane
 // neighbour offsets (x-1 when the x-parity is 0, x+1 when it is 1, y-1, y+1).
 struct RingSite {
-    int s, idb, ypar, xm0, xp1, ym, yp;
+    int s, idb, ypar, xm0, xp1, ym, yp, y;
 };
 
-template <typename T, int C, int LC, int B, int K>
+// With (B/2) a multiple of the row length L/2 a lane's sites share their x position and are
+// (B/2)/(L/2) rows apart, so only the first site's geometry is kept (fewer registers).
+template <int LC, int B>
+constexpr bool ring_compact() { return ((B / 2) % (LC / 2)) == 0; }
+
+template <typename T, int C, int LC, int B, int K, bool HR = false>
 __device__ __forceinline__ void ring_stage(const GroupCtx<T> &g, const RingSite (&q)[K], T *ring, T *gsp, int v,
                                            uint32_t k, const Coef<T> &cf, bool rn, T &pe, T &pmx, T &pmy, T &pmz,
                                            unsigned long long &nacc)
 {
-    constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE, SLOT = 6 * PLANE, SL = B / 2;
+    constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE, SLOT = (HR ? 3 : 6) * PLANE, SL = B / 2;
+    // components in device memory: the half ring's colour 1 (own for stage 1, the neighbours of stage 0)
+    constexpr int OWN_DEV = (HR && C == 1) ? 7 : 0, OTH_DEV = (HR && C == 0) ? 7 : 0;
     const int zp = v < LC ? v : v - LC;
     const int sl = v % RING;
-    const int dm = ((v + RING - 1) % RING - sl) * SLOT, dp = ((v + 1) % RING - sl) * SLOT;
-    T *const own = ring + sl * SLOT + C * 3 * PLANE;
-    const T *const oth = ring + sl * SLOT + (1 - C) * 3 * PLANE;
-    const ColourView<T> cv{{own, own + PLANE, own + 2 * PLANE}, {oth, oth + PLANE, oth + 2 * PLANE}};
+    const int rdm = ((v + RING - 1) % RING - sl) * SLOT, rdp = ((v + 1) % RING - sl) * SLOT;
+    // The half ring's colour 1 in device memory: accessed from the start of each component array
+    // with absolute, non-negative site indices (spin_at takes a device index as an unsigned
+    // 32-bit offset). zb: this plane's first index; zbm / zbp: those of the planes below and
+    // above, periodic in z.
+    const int zb = zp * PLANE, zbm = (zp == 0 ? LC - 1 : zp - 1) * PLANE, zbp = (zp == LC - 1 ? 0 : zp + 1) * PLANE;
+    T *const gc1 = gsp + 3 * HALF;  // colour 1 in device memory, component x
+    T *const own = (HR && C == 1) ? gc1 : ring + sl * SLOT + C * 3 * PLANE;
+    const T *const oth = (HR && C == 0) ? gc1 : ring + sl * SLOT + (1 - C) * 3 * PLANE;
+    constexpr int OS = (HR && C == 1) ? HALF : PLANE, TS = (HR && C == 0) ? HALF : PLANE;  // component strides
+    const ColourView<T> cv{{own, own + OS, own + 2 * OS}, {oth, oth + TS, oth + 2 * TS}};
     T *const gx = gsp + C * 3 * HALF + zp * PLANE, *const gy = gx + HALF, *const gz = gx + 2 * HALF;
     const int zpar = zp & 1, idz = LC * LC * zp;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-        if ((PLANE % SL) == 0 || t < K - 1 || q[t].s < PLANE) {
-            const int p = (q[t].ypar + zpar + C) & 1;
-            const int h = q[t].s;
-            Site st;
-            st.h = h;
-            st.id = q[t].idb + p + idz;
-            st.nb[0] = h + (p ? 0 : q[t].xm0);
-            st.nb[1] = h + (p ? q[t].xp1 : 0);
-            st.nb[2] = h + q[t].ym;
-            st.nb[3] = h + q[t].yp;
-            st.nb[4] = h + dm;
-            st.nb[5] = h + dp;
-            update_site_s<T, false, 0, 0>(g, cv, C != 0, st, k, cf, pe, pmx, pmy, pmz, nacc,
-                                          [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
-                                              if (C == 0 && acc) {
-                                                  own[h] = nx;
-                                                  own[PLANE + h] = ny;
-                                                  own[2 * PLANE + h] = nz;
-                                              }
-                                              if (acc || rn) {
-                                                  spin_at<true>(gx, h) = acc ? nx : sx;
-                                                  spin_at<true>(gy, h) = acc ? ny : sy;
-                                                  spin_at<true>(gz, h) = acc ? nz : sz;
-                                              }
-                                          });
+    constexpr bool COMPACT = ring_compact<LC, B>();
+    constexpr int HL = LC / 2, DY = COMPACT ? SL / HL : 0;
+    auto site = [&](int t) {
+        RingSite r;
+        if constexpr (COMPACT) {
+            // sites t of a lane: DY t rows below its first one, same x
+            r.s = q[0].s + SL * t;
+            r.y = q[0].y + DY * t;
+            r.idb = q[0].idb + LC * DY * t;
+            r.ypar = (q[0].ypar + DY * t) & 1;
+            r.xm0 = q[0].xm0;
+            r.xp1 = q[0].xp1;
+            r.ym = (r.y == 0) ? (LC - 1) * HL : -HL;
+            r.yp = (r.y == LC - 1) ? -(LC - 1) * HL : HL;
+        } else {
+            r = q[t];
         }
+        if ((PLANE % SL) == 0 || t < K - 1 || r.s < PLANE) {
+            const int p = (r.ypar + zpar + C) & 1;
+            const int h = r.s;  // in-plane half-index
+            Site st;
+            st.id = r.idb + p + idz;
+            // own site: a ring slot, or (half ring, colour 1) device memory
+            st.h = (HR && C == 1) ? zb + h : h;
+            // neighbours: ring slots (other colour), or (half ring, colour 0) device memory
+            const int nbase = (HR && C == 0) ? zb + h : h;
+            st.nb[0] = nbase + (p ? 0 : r.xm0);
+            st.nb[1] = nbase + (p ? r.xp1 : 0);
+            st.nb[2] = nbase + r.ym;
+            st.nb[3] = nbase + r.yp;
+            st.nb[4] = (HR && C == 0) ? zbm + h : h + rdm;
+            st.nb[5] = (HR && C == 0) ? zbp + h : h + rdp;
+            update_site_s<T, false, OWN_DEV, OTH_DEV>(g, cv, C != 0, st, k, cf, pe, pmx, pmy, pmz, nacc,
+                                                      [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
+                                                          if (C == 0 && acc) {
+                                                              own[h] = nx;
+                                                              own[PLANE + h] = ny;
+                                                              own[2 * PLANE + h] = nz;
+                                                          }
+                                                          // (the half ring's colour 1 was normalised in place)
+                                                          if (acc || (rn && !(HR && C == 1))) {
+                                                              spin_at<true>(gx, h) = acc ? nx : sx;
+                                                              spin_at<true>(gy, h) = acc ? ny : sy;
+                                                              spin_at<true>(gz, h) = acc ? nz : sz;
+                                                          }
+                                                      });
+        }
+    };
+    if constexpr (COMPACT) {
+        // (rolled: the sites' geometry comes from the first one, and one update at a time keeps
+        // the registers of a 1024-lane workgroup within budget)
+#pragma unroll 1
+        for (int t = 0; t < K; ++t) site(t);
+    } else {
+#pragma unroll
+        for (int t = 0; t < K; ++t) site(t);
     }
 }
 
 // Sweeps [k0, k1) of one path (the whole workgroup) through the ring. Waves of even index run
 // stage 0, odd ones stage 1.
-template <typename T, int LC, int B>
+template <typename T, int LC, int B, bool HR = false>
 __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const InstDev &in, int k0, int k1, bool fresh,
                                                  T *ring)
 {
@@ -899,10 +949,11 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
         asm volatile("" : "+v"(lane));  // not hoisted out of a persistent kernel's item loop
         const int rank = (lane >> 6) >> 1, l64 = lane & 63;
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
+        for (int t = 0; t < (ring_compact<LC, B>() ? 1 : K); ++t) {
             const int sidx = rank * 64 + l64 + SL * t;
             const int jx = sidx % HL, y = sidx / HL;
             q[t].s = sidx;
+            q[t].y = y;
             q[t].idb = 2 * jx + L * y;
             q[t].ypar = y & 1;
             q[t].xm0 = (jx == 0) ? HL - 1 : -1;
@@ -914,13 +965,34 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
     __syncthreads();
     for (int ks = k0; ks < k1; ++ks) {
         const bool rn = FP32 && renorm_every > 0 && ks > 0 && ks % renorm_every == 0;
-        // the pass starts with colour 0 of plane 0 and colour 1 of planes -1, 0, 1
-        if (g.active) {
-            RingRegs<T, LC, B> r;
-            ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, L - 1, true, tid);
-            ring_store<T, LC, B>(r, ring, 0, 0, true, rn, 1, RING - 1, true, rn, tid);
-            ring_load<T, LC, B>(r, gsp, 1, 0, true, 1, 1, true, tid);
-            ring_store<T, LC, B>(r, ring, 1, 0, true, rn, 1, 1, true, rn, tid);
+        if constexpr (HR) {
+            // colour 1 stays in device memory: normalised in place before a renormalisation pass
+            if constexpr (FP32) if (rn && g.active) {
+                constexpr int HALF = L * PLANE;
+                T *const c1 = gsp + 3 * HALF;
+                for (int t = tid; t < HALF; t += B) {
+                    const T x = c1[t], y = c1[HALF + t], z = c1[2 * HALF + t];
+                    const float rr = __builtin_amdgcn_rsqf(fmaf(z, z, fmaf(y, y, x * x)));
+                    c1[t] = x * rr;
+                    c1[HALF + t] = y * rr;
+                    c1[2 * HALF + t] = z * rr;
+                }
+            }
+            // the pass starts with colour 0 of plane 0
+            if (g.active) {
+                RingRegs<T, LC, B> r;
+                ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, 0, false, tid);
+                ring_store<T, LC, B, HR>(r, ring, 0, 0, true, rn, 1, 0, false, false, tid);
+            }
+        } else {
+            // the pass starts with colour 0 of plane 0 and colour 1 of planes -1, 0, 1
+            if (g.active) {
+                RingRegs<T, LC, B> r;
+                ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, L - 1, true, tid);
+                ring_store<T, LC, B>(r, ring, 0, 0, true, rn, 1, RING - 1, true, rn, tid);
+                ring_load<T, LC, B>(r, gsp, 1, 0, true, 1, 1, true, tid);
+                ring_store<T, LC, B>(r, ring, 1, 0, true, rn, 1, 1, true, rn, tid);
+            }
         }
         __syncthreads();
         T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);
@@ -928,19 +1000,20 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
         for (int tau = 0; tau <= L + 2; ++tau) {
             // next step's half-planes: colour 0 of plane tau + 1 (virtual planes up to L + 1),
             // colour 1 of plane tau + 2 (up to L)
-            const bool h0 = tau + 1 <= L + 1, h1 = tau + 2 <= L;
+            const bool h0 = tau + 1 <= L + 1, h1 = !HR && tau + 2 <= L;
             const int z0 = tau + 1 < L ? tau + 1 : tau + 1 - L, z1 = tau + 2 < L ? tau + 2 : tau + 2 - L;
             RingRegs<T, LC, B> r;
             if (g.active) ring_load<T, LC, B>(r, gsp, 0, z0, h0, 1, z1, h1, tid);
             if (g.active) {
                 if (odd_wave) {
                     if (tau >= 3)
-                        ring_stage<T, 1, LC, B, K>(g, q, ring, gsp, tau - 2, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
+                        ring_stage<T, 1, LC, B, K, HR>(g, q, ring, gsp, tau - 2, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz,
+                                                       nacc);
                 } else if (tau < L) {
-                    ring_stage<T, 0, LC, B, K>(g, q, ring, gsp, tau, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
+                    ring_stage<T, 0, LC, B, K, HR>(g, q, ring, gsp, tau, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
                 }
-                ring_store<T, LC, B>(r, ring, 0, (tau + 1) % RING, h0, rn && tau + 1 < L, 1, (tau + 2) % RING, h1, rn,
-                                     tid);
+                ring_store<T, LC, B, HR>(r, ring, 0, (tau + 1) % RING, h0, rn && tau + 1 < L, 1, (tau + 2) % RING, h1,
+                                         rn, tid);
             }
             __syncthreads();
         }
@@ -1005,7 +1078,7 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
     __syncthreads();
 }
 
-template <typename T, int LC, int B>
+template <typename T, int LC, int B, bool HR = false>
 __device__ __forceinline__ void wg_run_ring(const InstDev &in, int path, int k0, int k1, bool fresh, char *smem, T *gsp)
 {
     GroupCtx<T> g;
@@ -1017,14 +1090,14 @@ __device__ __forceinline__ void wg_run_ring(const InstDev &in, int path, int k0,
     g.ctr3 = in.ctr3;
     g.active = path < in.n_paths;
     T *ring = reinterpret_cast<T *>(smem);
-    char *p = smem + (size_t)RING * 3 * LC * LC * sizeof(T);
+    char *p = smem + (size_t)RING * (HR ? 3 : 6) * (LC * LC / 2) * sizeof(T);
     g.shacc = reinterpret_cast<double *>(p);
     g.red = reinterpret_cast<T *>(p + 128);
     g.sp = gsp;
     g.sp1 = nullptr;
     g.sp0z = nullptr;
     load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
-    path_sweeps_ring<T, LC, B>(g, in, k0, k1, fresh, ring);
+    path_sweeps_ring<T, LC, B, HR>(g, in, k0, k1, fresh, ring);
     store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
 }
 
@@ -1078,9 +1151,9 @@ template <typename T, int LC, int G, int B, int MAP, int PL>
 __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int k1, bool fresh, char *smem, T *gbase,
                                        bool resident)
 {
-    if constexpr (PL == PL_RING) {
+    if constexpr (PL == PL_RING || PL == PL_HRING) {
         static_assert(G == B, "one path per workgroup");
-        wg_run_ring<T, LC, B>(in, path0, k0, k1, fresh, smem, gbase);
+        wg_run_ring<T, LC, B, PL == PL_HRING>(in, path0, k0, k1, fresh, smem, gbase);
     } else {
         wg_run_groups<T, LC, G, B, MAP, PL>(in, path0, k0, k1, fresh, smem, gbase, resident);
     }
@@ -1096,7 +1169,7 @@ constexpr int target_waves(int L, int B, int G, int pl)
     if (pl == PL_MEM || L == 0) return fp64 ? 2 : 4;
     const int wgs = (int)((size_t)160 * 1024 / lds_layout_bytes<T>(L, B, G, pl));
     // (the plane ring keeps a whole update's worth of geometry and in-flight planes per lane)
-    const int w = wgs * (B / 64) / 4, cap = pl == PL_RING ? (fp64 ? 2 : 4) : (fp64 ? 4 : 8);
+    const int w = wgs * (B / 64) / 4, cap = (pl == PL_RING || pl == PL_HRING) ? (fp64 ? 2 : 4) : (fp64 ? 4 : 8);
     return w < 1 ? 1 : (w > cap ? cap : w);
 }
 
@@ -1657,6 +1730,60 @@ hipError_t launch_batch_mem(const BatchDev &b, int grid, size_t lds, hipStream_t
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ fused batch kernel
+// One persistent kernel of FUSED_B-lane workgroups for a batch that mixes lattice sides: every
+// item of every instance goes into one queue, largest first, and each workgroup runs an item
+// with the code of the instance's member variant (the same lanes per path, site map and
+// placement as the batch variant it is named after, so each path's results are the same bit
+// for bit). Its LDS and spin slots are the largest any member in the batch needs; its
+// registers the largest any member needs (four waves per SIMD).
+constexpr int FUSED_B = 1024;
+
+#define MMC_FUSED_MEMBERS_F32(X)                                   \
+    X(float, 48, 1024, FLAT, PL_RING, "f32-ring-L48-g1024")         \
+    X(float, 32, 1024, COLZ, PL_SPLIT_XY, "f32-splitxy-L32-g1024")  \
+    X(float, 30, 1024, COLZ, PL_SPLIT, "f32-split-L30-g1024")       \
+    X(float, 24, 1024, FLAT, PL_SPLIT, "f32-split-L24-g1024")       \
+    X(float, 20, 1024, COLZ, PL_LDS, "f32-lds-L20-g1024")           \
+    X(float, 16, 512, COLZ, PL_LDS, "f32-lds-L16-g512")             \
+    X(float, 12, 256, FLAT, PL_LDS, "f32-lds-L12-g256")             \
+    X(float, 8, 64, COLZ, PL_LDS, "f32-lds-L8-g64")
+
+// One item of a fused batch with member code (out of line: each member is register-allocated on
+// its own, not as one union of every member's live values).
+template <typename T, int LC, int G, int MAP, int PL>
+__device__ __attribute__((noinline)) void fused_item(const InstDev &in, int path0, int total, char *smem, T *slot)
+{
+    wg_run<T, LC, G, FUSED_B, MAP, PL>(in, path0, 0, total, true, smem, slot, false);
+}
+
+template <typename T>
+__global__ __launch_bounds__(FUSED_B) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_fused(BatchDev bd)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int item_sh;
+    T *slot = reinterpret_cast<T *>(bd.slots + (size_t)blockIdx.x * bd.slot_bytes);
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = (int)atomicAdd(bd.head, 1u);
+        __syncthreads();
+        const int it = item_sh;
+        __syncthreads();
+        if (it >= bd.n_items) break;  // uniform: every wave leaves once the queue is empty
+        const BatchItem item = bd.items[it];
+        const InstDev &in = bd.inst[item.inst];
+        const int total = in.n_therm + in.n_meas;
+        const int m = bd.variant[item.inst];  // the instance's fused member (workgroup-uniform)
+        int idx = 0;
+#define MMC_FUSED_CASE(TT, LC, G, MAP, PL, NAME)                                                          \
+    if constexpr (std::is_same<T, TT>::value) {                                                           \
+        if (m == idx) fused_item<TT, LC, G, MAP, PL>(in, item.path0, total, smem, slot);                  \
+        ++idx;                                                                                            \
+    }
+        MMC_FUSED_MEMBERS_F32(MMC_FUSED_CASE)
+#undef MMC_FUSED_CASE
+    }
+}
+
 // ------------------------------------------------------------------ plain FP64 engine
 // One thread per site of one colour, spins in device memory, one launch per half-sweep;
 // the sweep index lives in device memory so one captured sweep can be replayed.
@@ -1879,6 +2006,11 @@ static const Variant k_variants[] = {
     MMC_RES(float, 48, 768, 768, FLAT, PL_RING, "f32-ring-L48-b768")
     MMC_RES(float, 32, 512, 512, FLAT, PL_RING, "f32-ring-L32-b512")
     MMC_RES(float, 16, 256, 256, FLAT, PL_RING, "f32-ring-L16-b256")
+    // FP32, colour 0 through a ring of z-planes in LDS, colour 1 in place in device memory
+    MMC_RES(float, 64, 1024, 1024, FLAT, PL_HRING, "f32-hring-L64-b1024")
+    MMC_RES(float, 64, 768, 768, FLAT, PL_HRING, "f32-hring-L64-b768")
+    MMC_RES(float, 48, 1024, 1024, FLAT, PL_HRING, "f32-hring-L48-b1024")
+    MMC_RES(float, 16, 256, 256, FLAT, PL_HRING, "f32-hring-L16-b256")
     // FP32, spins in device memory, z-pipelined window in LDS
     MMC_WIN(float, 24, 512, 2, false, "f32-win-L24-d2-b512")
     MMC_WIN(float, 24, 1024, 3, false, "f32-win-L24-d3-b1024")
@@ -1906,6 +2038,7 @@ static const Variant k_variants[] = {
     // FP64, plane ring (small lattices: parity of its schedule with the oracle)
     MMC_RES(double, 12, 256, 256, FLAT, PL_RING, "f64-ring-L12-b256")
     MMC_RES(double, 16, 256, 256, FLAT, PL_RING, "f64-ring-L16-b256")
+    MMC_RES(double, 16, 256, 256, FLAT, PL_HRING, "f64-hring-L16-b256")
     // FP64, window (small lattices: parity of the pipelined schedule with the oracle)
     MMC_WIN(double, 12, 256, 1, false, "f64-win-L12-d1-b256")
     MMC_WIN(double, 16, 256, 2, false, "f64-win-L16-d2-b256")
@@ -1993,6 +2126,66 @@ hipError_t launch_batch(const BatchDev &b, int fp64, int variant, int grid, size
     return v[variant].launch_batch(b, grid, lds, s);
 }
 
+// The fused kernel's members: (name, side, lanes per path, placement) in member order.
+struct FusedMember {
+    const char *name;
+    int L, lanes, place;
+};
+#define MMC_FUSED_ROW(TT, LC, G, MAP, PL, NAME) FusedMember{NAME, LC, G, (int)(PL)},
+static const FusedMember k_fused_f32[] = {MMC_FUSED_MEMBERS_F32(MMC_FUSED_ROW)};
+#undef MMC_FUSED_ROW
+
+int fused_member(int fp64, const char *batch_variant)
+{
+    if (fp64 || !batch_variant) return -1;
+    const int n = (int)(sizeof(k_fused_f32) / sizeof(k_fused_f32[0]));
+    for (int i = 0; i < n; ++i)
+        if (strcmp(k_fused_f32[i].name, batch_variant) == 0) return i;
+    return -1;
+}
+
+size_t fused_lds_bytes(int member)
+{
+    const FusedMember &f = k_fused_f32[member];
+    return lds_layout_bytes<float>(f.L, FUSED_B, f.lanes, f.place);
+}
+
+size_t fused_slot_bytes(int member)
+{
+    const FusedMember &f = k_fused_f32[member];
+    if (f.place == PL_LDS) return 0;
+    return (size_t)(FUSED_B / f.lanes) * 3 * (size_t)f.L * f.L * f.L * sizeof(float);
+}
+
+int fused_paths_per_item(int member) { return FUSED_B / k_fused_f32[member].lanes; }
+
+const char *fused_member_name(int member) { return k_fused_f32[member].name; }
+
+int fused_member_like(int fp64, int L, int place)
+{
+    if (fp64) return -1;
+    const int n = (int)(sizeof(k_fused_f32) / sizeof(k_fused_f32[0]));
+    for (int i = 0; i < n; ++i)
+        if (k_fused_f32[i].L == L && k_fused_f32[i].place == place) return i;
+    return -1;
+}
+
+int fused_block() { return FUSED_B; }
+
+int fused_blocks_per_cu(size_t lds)
+{
+    int blocks = 0;
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)&k_batch_fused<float>, FUSED_B, lds);
+    return e == hipSuccess ? blocks : 0;
+}
+
+hipError_t launch_fused(const BatchDev &b, int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_fused<float>, dim3(grid), dim3(FUSED_B), lds, s, b);
+    return hipGetLastError();
+}
+
 // Raises every sweep kernel's dynamic-LDS limit to what the device allows per workgroup
 // minus the kernel's static LDS (once, before any launch or graph capture). HIP on gfx950
 // accepts dynamic LDS up to the device limit without it, so a refusal is not an error: a
@@ -2020,6 +2213,7 @@ hipError_t prepare_kernels(int max_lds)
         const Variant *bv = batch_variants(fp64, &nb);
         for (int i = 0; i < nb; ++i) raise_lds_limit(bv[i].kernel, max_lds);
     }
+    raise_lds_limit((const void *)&k_batch_fused<float>, max_lds);
     done = 1;
     return hipSuccess;
 }

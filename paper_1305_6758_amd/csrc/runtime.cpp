@@ -88,6 +88,7 @@ struct Instance {
     int variant = -1;  // index into mmc::variants() (single) or mmc::batch_variants() (batch)
     bool plain = false;
     bool pinned = false;  // batch: variant fixed by mmc_set_variant, not tuned
+    int member = -1;      // batch run by the fused kernel: the variant's member in it
     // device views (offsets into the workspace)
     size_t off_spins = 0, off_acc = 0, off_trace = 0;
 };
@@ -133,6 +134,7 @@ struct mmc_ctx {
     // with its own work list, queue head (64 bytes apart), resident workgroups and LDS size;
     // the device-memory variants' launches share one slot area (they run one after another)
     struct Launch {
+        bool fused = false;  // the fused kernel (the whole batch)
         int variant = 0;  // a variant of the launch's kernel (the first; the shared
                           // device-memory kernel serves several)
         std::string name;
@@ -145,6 +147,7 @@ struct mmc_ctx {
     std::vector<Launch> launches;
     size_t off_inst = 0, off_var = 0, off_head = 0, off_slots = 0;
     size_t slot_area = 0;  // bytes of all launches' slots (the launches run side by side)
+    bool fused_refused = false;  // batch_launch FUSED asked for, but a variant has no member
     int n_cu = 0;
     bool tuned = false;
 };
@@ -305,10 +308,11 @@ std::string tune_key(bool batch, int fp64, int L, int n_paths)
 }
 
 // ---------------------------------------------------------------- candidates
-// Variant::lds of the plane-ring variants: their spins live in device memory and stream
-// through LDS, so they count as window placements, not LDS ones.
-constexpr int LDS_RING = 4;
-bool is_ring(const mmc::Variant &v) { return v.lds == LDS_RING; }
+// Variant::lds of the plane-ring variants (both colours, or colour 0 only, in the ring): their
+// spins live in device memory and stream through LDS, so they count as window placements, not
+// LDS ones.
+constexpr int LDS_RING = 4, LDS_HALF_RING = 5;
+bool is_ring(const mmc::Variant &v) { return v.lds == LDS_RING || v.lds == LDS_HALF_RING; }
 bool lds_resident(const mmc::Variant &v) { return v.lds != 0 && !is_ring(v); }
 
 bool variant_fits(const mmc::Variant &v, int fp64, int L, int lds_limit)
@@ -1006,7 +1010,7 @@ int mmc_stats(const mmc_ctx *c, mmc_stats_t *out)
 }
 
 // ---------------------------------------------------------------- checkpoints
-static const char k_magic[8] = {'M', 'M', 'C', 'C', 'K', 'P', 'T', '2'};
+static const char k_magic[8] = {'M', 'M', 'C', 'C', 'K', 'P', 'T', '3'};
 
 int mmc_save(const mmc_ctx *c, const char *file)
 {
@@ -1160,8 +1164,8 @@ int mmc_plan(const mmc_ctx *c, char *buf, size_t n)
         snprintf(b, sizeof b, "batch launches=%zu", c->launches.size());
         s += b;
         for (const auto &l : c->launches) {
-            snprintf(b, sizeof b, " [%s block=%d workgroups=%d items=%zu]", l.name.c_str(), vs[l.variant].block,
-                     l.n_slots, l.items.size());
+            snprintf(b, sizeof b, " [%s block=%d workgroups=%d items=%zu]", l.name.c_str(),
+                     l.fused ? mmc::fused_block() : vs[l.variant].block, l.n_slots, l.items.size());
             s += b;
         }
         s += ";";
@@ -1234,6 +1238,65 @@ static void batch_plan(mmc_ctx *c)
         }
     }
     c->launches.clear();
+    c->fused_refused = false;
+    // the fused kernel, when asked for and every variant has a member in it (a tuned variant
+    // without a member is replaced by the member of the same side and placement, e.g. the
+    // plane ring's 1024-lane form for its 768-lane one; pinned ones stay); AUTO runs
+    // per-variant launches
+    const int mode = c->cfg.batch_launch;
+    bool members = true;
+    std::vector<int> like(c->inst.size(), -1);
+    for (size_t i = 0; i < c->inst.size(); ++i) {
+        Instance &in = c->inst[i];
+        in.member = mmc::fused_member(c->fp64, vs[in.variant].name);
+        if (in.member < 0 && !in.pinned) like[i] = mmc::fused_member_like(c->fp64, in.L, vs[in.variant].lds);
+        members = members && (in.member >= 0 || like[i] >= 0);
+    }
+    if (mode == MMC_BATCH_FUSED && !members) c->fused_refused = true;
+    if (members && mode == MMC_BATCH_FUSED) {
+        for (size_t i = 0; i < c->inst.size(); ++i) {
+            if (like[i] < 0) continue;
+            for (int v = 0; v < nv; ++v)
+                if (strcmp(vs[v].name, mmc::fused_member_name(like[i])) == 0) c->inst[i].variant = v;
+            c->inst[i].member = like[i];
+        }
+        names.clear();
+        for (const Instance &in : c->inst)
+            if (std::find(names.begin(), names.end(), std::string(vs[in.variant].name)) == names.end())
+                names.push_back(vs[in.variant].name);
+        std::vector<Work> all;
+        mmc_ctx::Launch l;
+        l.fused = true;
+        l.variant = c->inst[0].variant;
+        l.name = "fused:";
+        for (size_t g = 0; g < names.size(); ++g) l.name += (g ? "+" : "") + names[g];
+        size_t lds_max = 0, slot_max = 0;
+        for (size_t i = 0; i < c->inst.size(); ++i) {
+            const Instance &in = c->inst[i];
+            const int ppi = mmc::fused_paths_per_item(in.member);
+            lds_max = std::max(lds_max, mmc::fused_lds_bytes(in.member));
+            slot_max = std::max(slot_max, mmc::fused_slot_bytes(in.member));
+            for (int p = 0; p < in.n_paths; p += ppi) {
+                const int np = std::min(ppi, in.n_paths - p);
+                all.push_back({(double)in.L * in.L * in.L * (double)(in.n_therm + in.n_meas) * np, {(int)i, p}});
+            }
+        }
+        std::stable_sort(all.begin(), all.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
+        for (auto &w : all) {
+            l.items.push_back(w.item);
+            l.updates += w.cost;
+        }
+        l.lds = lds_max;
+        const int per_cu = std::max(1, mmc::fused_blocks_per_cu(l.lds));
+        l.n_slots = std::min((int)std::min<size_t>(l.items.size(), 1u << 30), per_cu * std::max(1, c->n_cu));
+        l.slot_bytes = align_up(slot_max);
+        l.off_slots = 0;
+        c->launches.push_back(std::move(l));
+        c->slot_area = c->launches[0].slot_bytes * (size_t)c->launches[0].n_slots;
+        c->ws_bytes = layout_batch(c);
+        c->ready = false;
+        return;
+    }
     for (size_t g = 0; g < kern.size(); ++g) {
         std::stable_sort(work[g].begin(), work[g].end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
         mmc_ctx::Launch l;
@@ -1382,7 +1445,7 @@ mmc_ctx *mmc_batch_create(const mmc_instance *inst, int n_inst, uint64_t seed, c
         return nullptr;
     }
     if (c0.init < MMC_INIT_SPHERE || c0.init > MMC_INIT_MIXED || c0.proposal < MMC_PROPOSAL_SPHERE ||
-        c0.proposal > MMC_PROPOSAL_ANGLES) {
+        c0.proposal > MMC_PROPOSAL_ANGLES || c0.batch_launch < MMC_BATCH_AUTO || c0.batch_launch > MMC_BATCH_PER_VARIANT) {
         fail(MMC_EINVAL, "configuration out of range");
         return nullptr;
     }
@@ -1446,9 +1509,10 @@ static int batch_upload(mmc_ctx *c)
 {
     std::vector<mmc::InstDev> d;
     std::vector<int> var;
+    const bool fused = !c->launches.empty() && c->launches[0].fused;
     for (size_t i = 0; i < c->inst.size(); ++i) {
         d.push_back(inst_dev(c, c->inst[i], (uint32_t)i));
-        var.push_back(c->inst[i].variant);
+        var.push_back(fused ? c->inst[i].member : c->inst[i].variant);
     }
     HIP_TRY(hipMemcpy(c->ws + c->off_inst, d.data(), d.size() * sizeof(mmc::InstDev), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->ws + c->off_var, var.data(), var.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -1492,7 +1556,7 @@ static int batch_enqueue(mmc_ctx *c, hipStream_t s)
         b.slots = c->ws + c->off_slots + l.off_slots;  // all-LDS variants: slot_bytes 0, never touched
         b.slot_bytes = l.slot_bytes;
         b.n_slots = l.n_slots;
-        e = mmc::launch_batch(b, c->fp64, l.variant, l.n_slots, l.lds, sk);
+        e = l.fused ? mmc::launch_fused(b, l.n_slots, l.lds, sk) : mmc::launch_batch(b, c->fp64, l.variant, l.n_slots, l.lds, sk);
         if (e != hipSuccess) return fail(MMC_EHIP, "batch launch %s: %s", l.name.c_str(), hipGetErrorString(e));
     }
     for (size_t k = 1; k < c->launches.size(); ++k) {
@@ -1506,6 +1570,8 @@ int mmc_batch_run(mmc_ctx *c)
 {
     if (!c) return fail(MMC_EINVAL, "null context");
     if (!c->batch) return fail(MMC_EINVAL, "not a batch context");
+    if (c->fused_refused)
+        return fail(MMC_EUNSUPPORTED, "batch_launch FUSED: a variant of this batch has no member in the fused kernel");
     if (!c->ready) {
         int rc = ensure_memory(c);
         if (rc) return rc;

@@ -19,13 +19,15 @@ MMC_INIT_SPHERE, MMC_INIT_ANGLES, MMC_INIT_ORDERED, MMC_INIT_MIXED = 0, 1, 2, 3
 MMC_PROPOSAL_SPHERE, MMC_PROPOSAL_ANGLES = 0, 1
 MMC_MODEL_HEISENBERG3D, MMC_MODEL_ISING2D = 0, 1
 MMC_PLACE_AUTO, MMC_PLACE_LDS, MMC_PLACE_HBM, MMC_PLACE_PLAIN, MMC_PLACE_WINDOW = 0, 1, 2, 3, 4
+MMC_BATCH_AUTO, MMC_BATCH_FUSED, MMC_BATCH_PER_VARIANT = 0, 1, 2
 MMC_STATIC_SCRATCH_BYTES, MMC_STATIC_MAX_INSTANCES, MMC_STATIC_MAX_PATHS = 18 << 20, 256, 131072
 
 
 class mmc_config(C.Structure):
     _fields_ = [("precision", C.c_int), ("init", C.c_int), ("placement", C.c_int), ("block", C.c_int),
                 ("lanes_per_path", C.c_int), ("renorm_every", C.c_int), ("instance_id", C.c_uint32),
-                ("trace_sweeps", C.c_int), ("async_", C.c_int), ("proposal", C.c_int), ("model", C.c_int)]
+                ("trace_sweeps", C.c_int), ("async_", C.c_int), ("proposal", C.c_int), ("model", C.c_int),
+                ("batch_launch", C.c_int)]
 
 
 class mmc_path_result(C.Structure):
@@ -138,9 +140,9 @@ def _ptr(h):
 
 def config(precision=MMC_FP32, init=MMC_INIT_SPHERE, placement=MMC_PLACE_AUTO, block=0, lanes_per_path=0,
            renorm_every=0, instance_id=0, trace_sweeps=0, async_=0, proposal=MMC_PROPOSAL_SPHERE,
-           model=MMC_MODEL_HEISENBERG3D):
+           model=MMC_MODEL_HEISENBERG3D, batch_launch=0):
     return mmc_config(precision, init, placement, block, lanes_per_path, renorm_every, instance_id,
-                      trace_sweeps, async_, proposal, model)
+                      trace_sweeps, async_, proposal, model, batch_launch)
 
 
 # ---------------------------------------------------------------- same names as the C ABI

@@ -39,6 +39,7 @@ SINGLE_VARIANTS = [
     (24, "f32-win-L24-d2-b512"), (24, "f32-win-L24-d3-b1024"), (30, "f32-win-L30-d2-b1024"),
     (32, "f32-win-L32-d2-b1024"), (32, "f32-gwin-L32-d2-b1024"), (48, "f32-gwin-L48-d1-b1024"),
     (16, "f32-ring-L16-b256"), (32, "f32-ring-L32-b512"), (48, "f32-ring-L48-b1024"), (48, "f32-ring-L48-b768"),
+    (16, "f32-hring-L16-b256"), (48, "f32-hring-L48-b1024"), (64, "f32-hring-L64-b1024"), (64, "f32-hring-L64-b768"),
 ]
 
 # the batch variants the uneven batch of lattice sides 8 ... 48 runs on

@@ -1,6 +1,7 @@
-"""Parity of the z-pipelined window kernels (spins in device memory, several sweeps per pass,
-the half-sweeps of a pass pipelined over z-planes), in both forms: planes staged through a
-sliding window in LDS ("win"), and planes left in device memory ("gwin").
+"""Parity of the z-pipelined window kernels (spins in device memory, swept in passes over
+z-planes): the plane rings (one sweep per pass, both colours' planes in LDS, "ring", or colour
+0's only, "hring"), and the multi-sweep windows, with the planes staged through a sliding
+window in LDS ("win") or left in device memory ("gwin").
 
   - FP64 (L = 12, 16, 24): trajectories, traces, accept counts and final spins match the
     oracle to 1e-12 -- odd sweep counts (a last pass shorter than the others), every start,
@@ -25,7 +26,8 @@ def say(*a):
 
 
 FP64_VARIANTS = [(12, "f64-win-L12-d1-b256"), (16, "f64-win-L16-d2-b256"), (16, "f64-gwin-L16-d2-b256"),
-                 (24, "f64-gwin-L24-d3-b512"), (12, "f64-ring-L12-b256"), (16, "f64-ring-L16-b256")]
+                 (24, "f64-gwin-L24-d3-b512"), (12, "f64-ring-L12-b256"), (16, "f64-ring-L16-b256"),
+                 (16, "f64-hring-L16-b256")]
 
 
 @pytest.mark.parametrize("L,variant", FP64_VARIANTS)
@@ -45,7 +47,8 @@ def test_window_fp64_matches_oracle(L, variant):
             assert max_abs_diff(sp[p], ora["spins"][p]) <= TOL64
 
 
-@pytest.mark.parametrize("variant", ["f64-win-L16-d2-b256", "f64-gwin-L16-d2-b256", "f64-ring-L16-b256"])
+@pytest.mark.parametrize("variant", ["f64-win-L16-d2-b256", "f64-gwin-L16-d2-b256", "f64-ring-L16-b256",
+                                     "f64-hring-L16-b256"])
 def test_window_fp64_split_runs(variant):
     """Sweeps run in chunks of 3, 1, 4 and the rest equal one uninterrupted run."""
     from paper_1305_6758_amd import mmc
@@ -71,7 +74,9 @@ def test_window_fp64_split_runs(variant):
 FP32_VARIANTS = [(24, "f32-win-L24-d2-b512"), (24, "f32-win-L24-d3-b1024"), (30, "f32-win-L30-d2-b1024"),
                  (32, "f32-win-L32-d2-b512"), (32, "f32-win-L32-d2-b1024"), (32, "f32-gwin-L32-d2-b1024"),
                  (48, "f32-gwin-L48-d1-b1024"), (64, "f32-gwin-L64-d1-b1024"), (16, "f32-ring-L16-b256"),
-                 (32, "f32-ring-L32-b512"), (48, "f32-ring-L48-b1024"), (48, "f32-ring-L48-b768")]
+                 (32, "f32-ring-L32-b512"), (48, "f32-ring-L48-b1024"), (48, "f32-ring-L48-b768"),
+                 (16, "f32-hring-L16-b256"), (48, "f32-hring-L48-b1024"), (64, "f32-hring-L64-b1024"),
+                 (64, "f32-hring-L64-b768")]
 
 
 @pytest.mark.parametrize("L,variant", FP32_VARIANTS)

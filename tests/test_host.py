@@ -93,7 +93,7 @@ def test_load_rejects_sweep_count_out_of_range(tmp_path, done):
     from paper_1305_6758_amd import mmc
     L, n_paths, n_therm, n_meas = 8, 2, 2, 4
     cfg = mmc.config(trace_sweeps=3)
-    head = (b"MMCCKPT2" + struct.pack("<iddiiiQ", L, 1.5, 1.0, n_paths, n_therm, n_meas, 1234)
+    head = (b"MMCCKPT3" + struct.pack("<iddiiiQ", L, 1.5, 1.0, n_paths, n_therm, n_meas, 1234)
             + bytes(C.string_at(C.addressof(cfg), C.sizeof(cfg))) + struct.pack("<i", done)
             + b"f32-lds-L8-g64-b256".ljust(64, b"\0"))
     body = bytes(n_paths * 3 * L ** 3 * 4 + n_paths * 128 + n_paths * 3 * 4 * 8)
@@ -168,6 +168,8 @@ def test_bench_device_memory_bytes_by_placement():
     # the plane ring: 12 (2L + 4)/(2L) B read + 12 B written per update, 24.5 B at L = 48
     assert bench.device_memory_bytes([(48, 1.4, 2, 3, 3)], "f32-ring-L48-b1024") == (24.5 * 2 * 48 ** 3 * 6,
                                                                                    2 * 48 ** 3 * 6, 0)
+    # the half ring: colour 1 read once from device memory, 24 + 12/L B per update
+    assert bench.device_memory_bytes([(64, 1.4, 2, 3, 3)], "f32-hring-L64-b1024")[0] == (24 + 12 / 64) * 2 * 64 ** 3 * 6
     with pytest.raises(ValueError):
         bench.device_memory_bytes(insts, "batch launches=1 [x]; L48:f32-hbm-L48-g512")
 
