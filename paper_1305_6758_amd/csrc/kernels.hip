@@ -270,6 +270,9 @@ __device__ __forceinline__ void update_site_s(const GroupCtx<T> &g, const Colour
         const float dot = fmaf(dz, hz, fmaf(dy, hy, dx * hx));
         acc = Arith<float>::uni(w.w2) < __builtin_amdgcn_exp2f(cf.q * dot);
     }
+    // (counted before the store: the ballot then reads the compare's mask as it is, instead of
+    // a copy rebuilt after the store's branch)
+    nacc += (unsigned long long)__popcll(__ballot(acc));
     store(acc, nx, ny, nz, sx, sy, sz);
     const T fx = acc ? nx : sx, fy = acc ? ny : sy, fz = acc ? nz : sz;
     pmx += fx;
@@ -279,7 +282,6 @@ __device__ __forceinline__ void update_site_s(const GroupCtx<T> &g, const Colour
         if constexpr (std::is_same<T, double>::value) pe = pe + ((fx * hx + fy * hy) + fz * hz);
         else pe = fmaf(fz, hz, fmaf(fy, hy, fmaf(fx, hx, pe)));
     }
-    nacc += (unsigned long long)__popcll(__ballot(acc));
 }
 
 template <typename T, bool ANG = false, int OWN_DEV = 0, int OTH_DEV = 0>

@@ -119,8 +119,8 @@ struct mmc_ctx {
     bool own_ws = false;
     bool ready = false;  // memory and plan in place
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_in = nullptr, ev_out = nullptr;
-    // batch: a stream and a join event per launch after the first (default priority), so the
-    // captured graph runs the variants' persistent kernels side by side
+    // batch: a stream and a join event per graph branch after the first (default priority), so
+    // the captured graph runs the variants' persistent kernels side by side
     std::vector<hipStream_t> aux;
     std::vector<hipEvent_t> ev_join;
     hipEvent_t ev_fork = nullptr;
@@ -130,9 +130,9 @@ struct mmc_ctx {
     // single-instance extras
     size_t off_kdev = 0;
     // batch
-    // one persistent launch per batch variant in use, in `order` (largest items first), each
-    // with its own work list, queue head (64 bytes apart), resident workgroups and LDS size;
-    // the device-memory variants' launches share one slot area (they run one after another)
+    // one persistent launch per batch variant in use (or one fused launch), largest items
+    // first, each with its own work list, queue head (64 bytes apart), resident workgroups,
+    // LDS size and spin slots (the launches run side by side)
     struct Launch {
         bool fused = false;  // the fused kernel (the whole batch)
         int variant = 0;  // a variant of the launch's kernel (the first; the shared
@@ -1522,13 +1522,29 @@ static int batch_upload(mmc_ctx *c)
     return MMC_OK;
 }
 
-// The launches (largest items first): the first on the context's stream, each further one on
-// a stream of its own forked from it and joined back, so the kernels run side by side and
-// compute-bound LDS work overlaps the memory-bound device-memory kernel. Where the LDS
+// Parallel branches of a batch graph: one per launch, at most as many as the process has
+// hardware queues (GPU_MAX_HW_QUEUES, HIP's default 4). With more branches than queues, some
+// launches wait for a queue until another launch has ended; within the limit the largest
+// launches get a branch each and the smallest run one after another on the last one, beside
+// the others.
+static int batch_branches(const mmc_ctx *c)
+{
+    int q = 4;
+    if (const char *e = getenv("GPU_MAX_HW_QUEUES")) {
+        const int v = atoi(e);
+        if (v >= 1) q = v;
+    }
+    return std::max(1, std::min((int)c->launches.size(), q));
+}
+
+// The launches (largest items first): the first on the context's stream, the others on
+// branches forked from it and joined back (batch_branches), so the kernels run side by side
+// and compute-bound LDS work overlaps the memory-bound device-memory kernels. Where the LDS
 // launches carry under a tenth of the updates they start after the device-memory kernel
 // instead: side by side they would hold CU resources from the kernel on the critical path
 // for longer than their share is worth. The kernels share no data but the read-only
 // instance and variant tables, and each works its own queue to the end.
+
 static int batch_enqueue(mmc_ctx *c, hipStream_t s)
 {
     hipError_t e = mmc::fill_zero(c->ws + c->off_head, 64 * std::max<size_t>(1, c->launches.size()), s);
@@ -1541,12 +1557,14 @@ static int batch_enqueue(mmc_ctx *c, hipStream_t s)
         if (lds_resident(vs[l.variant])) in_lds += l.updates;
     }
     const bool after_memory = !lds_resident(vs[c->launches[0].variant]) && in_lds < 0.1 * total;
+    const int nb = batch_branches(c);
     for (size_t k = 0; k < c->launches.size(); ++k) {
         const auto &l = c->launches[k];
-        hipStream_t sk = k ? c->aux[k - 1] : s;
+        const int br = std::min((int)k, nb - 1);  // launches nb - 1 and later share the last branch
+        hipStream_t sk = br ? c->aux[br - 1] : s;
         // fork point: before the first launch, or after it when the rest waits for it
         if (c->launches.size() > 1 && k == (after_memory ? 1 : 0)) HIP_TRY(hipEventRecord(c->ev_fork, s));
-        if (k) HIP_TRY(hipStreamWaitEvent(sk, c->ev_fork, 0));
+        if (br && (int)k == br) HIP_TRY(hipStreamWaitEvent(sk, c->ev_fork, 0));
         mmc::BatchDev b;
         b.inst = reinterpret_cast<const mmc::InstDev *>(c->ws + c->off_inst);
         b.variant = reinterpret_cast<const int *>(c->ws + c->off_var);
@@ -1559,9 +1577,9 @@ static int batch_enqueue(mmc_ctx *c, hipStream_t s)
         e = l.fused ? mmc::launch_fused(b, l.n_slots, l.lds, sk) : mmc::launch_batch(b, c->fp64, l.variant, l.n_slots, l.lds, sk);
         if (e != hipSuccess) return fail(MMC_EHIP, "batch launch %s: %s", l.name.c_str(), hipGetErrorString(e));
     }
-    for (size_t k = 1; k < c->launches.size(); ++k) {
-        HIP_TRY(hipEventRecord(c->ev_join[k - 1], c->aux[k - 1]));
-        HIP_TRY(hipStreamWaitEvent(s, c->ev_join[k - 1], 0));
+    for (int b = 1; b < nb; ++b) {
+        HIP_TRY(hipEventRecord(c->ev_join[b - 1], c->aux[b - 1]));
+        HIP_TRY(hipStreamWaitEvent(s, c->ev_join[b - 1], 0));
     }
     return MMC_OK;
 }
@@ -1578,7 +1596,7 @@ int mmc_batch_run(mmc_ctx *c)
         rc = batch_upload(c);
         if (rc) return rc;
         if (!c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        while (c->aux.size() + 1 < c->launches.size()) {
+        while ((int)c->aux.size() + 1 < batch_branches(c)) {
             hipStream_t a = nullptr;
             hipEvent_t e = nullptr;
             HIP_TRY(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
