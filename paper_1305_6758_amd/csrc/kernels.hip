@@ -215,42 +215,38 @@ struct ColourView {
     const T *oth[3];
 };
 
-// One Metropolis attempt at site s of colour c, sweep k. Adds the resulting spin (and for the
-// odd colour S . h) to the measurement partials and the accepted count of the wave to nacc.
-// OWN_DEV / OTH_DEV: bit masks of the own / other colour's components in device memory.
-// store(acc, new spin, old spin) writes the outcome (update_site_v: the new spin into the own
-// arrays when accepted).
-template <typename T, bool ANG, int OWN_DEV, int OTH_DEV, typename Store>
-__device__ __forceinline__ void update_site_s(const GroupCtx<T> &g, const ColourView<T> &cv, bool odd, const Site &s,
-                                              uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
-                                              unsigned long long &nacc, Store &&store)
+// One Metropolis attempt at site s of sweep k, with the operand reads given as functors
+// (own(c): component c of the site's spin; nbr(c, n): component c of neighbour n, order -x,
+// +x, -y, +y, -z, +z). Adds the resulting spin (and for the odd colour S . h) to the
+// measurement partials and the accepted count of the wave to nacc. store(acc, new spin, old
+// spin) writes the outcome.
+template <typename T, bool ANG, typename Own, typename Nbr, typename Store>
+__device__ __forceinline__ void update_site_f(const GroupCtx<T> &g, bool odd, const Site &s, uint32_t k,
+                                              const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
+                                              unsigned long long &nacc, Own &&own, Nbr &&nbr, Store &&store)
 {
     const Words w = philox4x32_10((uint32_t)s.id, k, g.path, TAG_MET | g.ctr3, g.key0, g.key1);
-    T *const ox = cv.own[0], *const oy = cv.own[1], *const oz = cv.own[2];
-    const T *const tx = cv.oth[0], *const ty = cv.oth[1], *const tz = cv.oth[2];
-    constexpr bool OX = OWN_DEV & 1, OY = OWN_DEV & 2, OZ = OWN_DEV & 4;
-    constexpr bool TX = OTH_DEV & 1, TY = OTH_DEV & 2, TZ = OTH_DEV & 4;
-    const T sx = spin_at<OX>(ox, s.h), sy = spin_at<OY>(oy, s.h), sz = spin_at<OZ>(oz, s.h);
+    const T sx = own(0), sy = own(1), sz = own(2);
     T hx, hy, hz;
     if constexpr (std::is_same<T, double>::value) {
         // h = ((((S_-x + S_+x) + S_-y) + S_+y) + S_-z) + S_+z, the reference order.
-        hx = spin_at<TX>(tx, s.nb[0]);
-        hy = spin_at<TY>(ty, s.nb[0]);
-        hz = spin_at<TZ>(tz, s.nb[0]);
+        hx = nbr(0, 0);
+        hy = nbr(1, 0);
+        hz = nbr(2, 0);
 #pragma unroll
         for (int n = 1; n < 6; ++n) {
-            hx = hx + spin_at<TX>(tx, s.nb[n]);
-            hy = hy + spin_at<TY>(ty, s.nb[n]);
-            hz = hz + spin_at<TZ>(tz, s.nb[n]);
+            hx = hx + nbr(0, n);
+            hy = hy + nbr(1, n);
+            hz = hz + nbr(2, n);
         }
     } else {
         // FP32: pairwise tree (any order is a valid FP32 rounding of the same sum).
         T ax[6], ay[6], az[6];
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
-            ax[n] = spin_at<TX>(tx, s.nb[n]);
-            ay[n] = spin_at<TY>(ty, s.nb[n]);
-            az[n] = spin_at<TZ>(tz, s.nb[n]);
+            ax[n] = nbr(0, n);
+            ay[n] = nbr(1, n);
+            az[n] = nbr(2, n);
         }
         hx = ((ax[0] + ax[1]) + (ax[2] + ax[3])) + (ax[4] + ax[5]);
         hy = ((ay[0] + ay[1]) + (ay[2] + ay[3])) + (ay[4] + ay[5]);
@@ -282,6 +278,27 @@ __device__ __forceinline__ void update_site_s(const GroupCtx<T> &g, const Colour
         if constexpr (std::is_same<T, double>::value) pe = pe + ((fx * hx + fy * hy) + fz * hz);
         else pe = fmaf(fz, hz, fmaf(fy, hy, fmaf(fx, hx, pe)));
     }
+}
+
+// The same with the operands read from a colour view: OWN_DEV / OTH_DEV are bit masks of the
+// own / other colour's components in device memory (update_site_v's store writes the new spin
+// into the own arrays when accepted).
+template <typename T, bool ANG, int OWN_DEV, int OTH_DEV, typename Store>
+__device__ __forceinline__ void update_site_s(const GroupCtx<T> &g, const ColourView<T> &cv, bool odd, const Site &s,
+                                              uint32_t k, const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
+                                              unsigned long long &nacc, Store &&store)
+{
+    T *const ox = cv.own[0], *const oy = cv.own[1], *const oz = cv.own[2];
+    const T *const tx = cv.oth[0], *const ty = cv.oth[1], *const tz = cv.oth[2];
+    constexpr bool OX = OWN_DEV & 1, OY = OWN_DEV & 2, OZ = OWN_DEV & 4;
+    constexpr bool TX = OTH_DEV & 1, TY = OTH_DEV & 2, TZ = OTH_DEV & 4;
+    update_site_f<T, ANG>(
+        g, odd, s, k, cf, pe, pmx, pmy, pmz, nacc,
+        [&](int c) { return c == 0 ? spin_at<OX>(ox, s.h) : c == 1 ? spin_at<OY>(oy, s.h) : spin_at<OZ>(oz, s.h); },
+        [&](int c, int n) {
+            return c == 0 ? spin_at<TX>(tx, s.nb[n]) : c == 1 ? spin_at<TY>(ty, s.nb[n]) : spin_at<TZ>(tz, s.nb[n]);
+        },
+        store);
 }
 
 template <typename T, bool ANG = false, int OWN_DEV = 0, int OTH_DEV = 0>
@@ -731,10 +748,13 @@ __device__ __attribute__((noinline)) void copy_spins(T *__restrict__ dst, const 
 // 1 in place before the pass (the colour-0 rule as above).
 constexpr int RING = 5;
 
+// LDS of a ring workgroup: RING slots of both colours of a z-plane (half ring: colour 0, plus
+// one buffer for colour 1 of the plane being updated), accumulators, reduction slots.
 template <typename T>
 __host__ __device__ constexpr size_t ring_lds_bytes(int L, int B, bool half = false)
 {
-    return (size_t)RING * (half ? 3 : 6) * ((size_t)L * L / 2) * sizeof(T) + 128 + (size_t)(B / 16) * 4 * sizeof(T);
+    return ((size_t)RING * (half ? 3 : 6) + (half ? 3 : 0)) * ((size_t)L * L / 2) * sizeof(T) + 128 +
+           (size_t)(B / 16) * 4 * sizeof(T);
 }
 
 // LDS bytes of one workgroup: spins (all of them, or colour 0), accumulators, reduction
@@ -804,8 +824,9 @@ __device__ __forceinline__ void ring_load(RingRegs<T, LC, B> &r, const T *gsp, i
     }
 }
 
-// Stores what ring_load brought in into ring slots s0 / s1 (normalising first where n0 / n1);
-// HR: slots of colour 0 only.
+// Stores what ring_load brought in into ring slots s0 / s1 (normalising first where n0 / n1).
+// HR (half ring): the slots hold colour 0 only, and the second half-plane (colour 1) goes to
+// the colour-1 buffer after the slots (s1, c1 unused).
 template <typename T, int LC, int B, bool HR = false>
 __device__ __forceinline__ void ring_store(RingRegs<T, LC, B> &r, T *ring, int c0, int s0, bool h0, bool n0, int c1,
                                            int s1, bool h1, bool n1, int tid)
@@ -820,7 +841,7 @@ __device__ __forceinline__ void ring_store(RingRegs<T, LC, B> &r, T *ring, int c
         if (q < 2 * NQ && (second ? h1 : h0)) {
             const int c = second ? c1 : c0, sl = second ? s1 : s0, rq = q - (second ? NQ : 0);
             if (second ? n1 : n0) normalise_sites(r.x[i], r.y[i], r.z[i]);
-            T *o = ring + sl * SLOT + c * 3 * PLANE + E * rq;
+            T *o = (HR && second) ? ring + RING * SLOT + E * rq : ring + sl * SLOT + c * 3 * PLANE + E * rq;
             *reinterpret_cast<V *>(o) = r.x[i];
             *reinterpret_cast<V *>(o + PLANE) = r.y[i];
             *reinterpret_cast<V *>(o + 2 * PLANE) = r.z[i];
@@ -846,8 +867,10 @@ __device__ __forceinline__ void ring_stage(const GroupCtx<T> &g, const RingSite 
                                            unsigned long long &nacc)
 {
     constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE, SLOT = (HR ? 3 : 6) * PLANE, SL = B / 2;
-    // components in device memory: the half ring's colour 1 (own for stage 1, the neighbours of stage 0)
+    // components in device memory: the half ring's colour 1 (own for stage 1; for stage 0 the
+    // z-neighbours, its in-plane neighbours coming from the colour-1 buffer c1b)
     constexpr int OWN_DEV = (HR && C == 1) ? 7 : 0, OTH_DEV = (HR && C == 0) ? 7 : 0;
+    const T *const c1b = ring + RING * SLOT;  // half ring: colour 1 of plane v, [component][L^2/2]
     const int zp = v < LC ? v : v - LC;
     const int sl = v % RING;
     const int rdm = ((v + RING - 1) % RING - sl) * SLOT, rdp = ((v + 1) % RING - sl) * SLOT;
@@ -887,28 +910,37 @@ __device__ __forceinline__ void ring_stage(const GroupCtx<T> &g, const RingSite 
             st.id = r.idb + p + idz;
             // own site: a ring slot, or (half ring, colour 1) device memory
             st.h = (HR && C == 1) ? zb + h : h;
-            // neighbours: ring slots (other colour), or (half ring, colour 0) device memory
-            const int nbase = (HR && C == 0) ? zb + h : h;
-            st.nb[0] = nbase + (p ? 0 : r.xm0);
-            st.nb[1] = nbase + (p ? r.xp1 : 0);
-            st.nb[2] = nbase + r.ym;
-            st.nb[3] = nbase + r.yp;
+            // in-plane neighbours: ring slot or colour-1 buffer (plane-local indices); z:
+            // ring slots, or (half ring, colour 0) device memory
+            st.nb[0] = h + (p ? 0 : r.xm0);
+            st.nb[1] = h + (p ? r.xp1 : 0);
+            st.nb[2] = h + r.ym;
+            st.nb[3] = h + r.yp;
             st.nb[4] = (HR && C == 0) ? zbm + h : h + rdm;
             st.nb[5] = (HR && C == 0) ? zbp + h : h + rdp;
-            update_site_s<T, false, OWN_DEV, OTH_DEV>(g, cv, C != 0, st, k, cf, pe, pmx, pmy, pmz, nacc,
-                                                      [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
-                                                          if (C == 0 && acc) {
-                                                              own[h] = nx;
-                                                              own[PLANE + h] = ny;
-                                                              own[2 * PLANE + h] = nz;
-                                                          }
-                                                          // (the half ring's colour 1 was normalised in place)
-                                                          if (acc || (rn && !(HR && C == 1))) {
-                                                              spin_at<true>(gx, h) = acc ? nx : sx;
-                                                              spin_at<true>(gy, h) = acc ? ny : sy;
-                                                              spin_at<true>(gz, h) = acc ? nz : sz;
-                                                          }
-                                                      });
+            auto store = [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
+                if (C == 0 && acc) {
+                    own[h] = nx;
+                    own[PLANE + h] = ny;
+                    own[2 * PLANE + h] = nz;
+                }
+                // (the half ring's colour 1 was normalised in place)
+                if (acc || (rn && !(HR && C == 1))) {
+                    spin_at<true>(gx, h) = acc ? nx : sx;
+                    spin_at<true>(gy, h) = acc ? ny : sy;
+                    spin_at<true>(gz, h) = acc ? nz : sz;
+                }
+            };
+            if constexpr (HR && C == 0) {
+                update_site_f<T, false>(
+                    g, false, st, k, cf, pe, pmx, pmy, pmz, nacc, [&](int c) { return own[c * PLANE + h]; },
+                    [&](int c, int n) {
+                        return n < 4 ? c1b[c * PLANE + st.nb[n]] : spin_at<true>(gc1 + c * HALF, st.nb[n]);
+                    },
+                    store);
+            } else {
+                update_site_s<T, false, OWN_DEV, OTH_DEV>(g, cv, C != 0, st, k, cf, pe, pmx, pmy, pmz, nacc, store);
+            }
         }
     };
     if constexpr (COMPACT) {
@@ -980,11 +1012,12 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
                     c1[2 * HALF + t] = z * rr;
                 }
             }
-            // the pass starts with colour 0 of plane 0
+            if (rn) __syncthreads();  // (uniform) normalised before plane 0 is read below
+            // the pass starts with colour 0 of plane 0 in slot 0 and colour 1 of plane 0 in the buffer
             if (g.active) {
                 RingRegs<T, LC, B> r;
-                ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, 0, false, tid);
-                ring_store<T, LC, B, HR>(r, ring, 0, 0, true, rn, 1, 0, false, false, tid);
+                ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, 0, true, tid);
+                ring_store<T, LC, B, HR>(r, ring, 0, 0, true, rn, 1, 0, true, false, tid);
             }
         } else {
             // the pass starts with colour 0 of plane 0 and colour 1 of planes -1, 0, 1
@@ -1001,9 +1034,11 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
 #pragma unroll 1
         for (int tau = 0; tau <= L + 2; ++tau) {
             // next step's half-planes: colour 0 of plane tau + 1 (virtual planes up to L + 1),
-            // colour 1 of plane tau + 2 (up to L)
-            const bool h0 = tau + 1 <= L + 1, h1 = !HR && tau + 2 <= L;
-            const int z0 = tau + 1 < L ? tau + 1 : tau + 1 - L, z1 = tau + 2 < L ? tau + 2 : tau + 2 - L;
+            // colour 1 of plane tau + 2 (up to L); half ring: colour 1 of plane tau + 1 for the
+            // buffer (up to L - 1, not yet updated in this pass: stage 1 reaches it at step tau + 3)
+            const bool h0 = tau + 1 <= L + 1, h1 = HR ? tau + 1 < L : tau + 2 <= L;
+            const int z0 = tau + 1 < L ? tau + 1 : tau + 1 - L;
+            const int z1 = HR ? tau + 1 : (tau + 2 < L ? tau + 2 : tau + 2 - L);
             RingRegs<T, LC, B> r;
             if (g.active) ring_load<T, LC, B>(r, gsp, 0, z0, h0, 1, z1, h1, tid);
             if (g.active) {
@@ -1014,8 +1049,18 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
                 } else if (tau < L) {
                     ring_stage<T, 0, LC, B, K, HR>(g, q, ring, gsp, tau, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
                 }
-                ring_store<T, LC, B, HR>(r, ring, 0, (tau + 1) % RING, h0, rn && tau + 1 < L, 1, (tau + 2) % RING, h1,
+                if constexpr (HR) {
+                    ring_store<T, LC, B, HR>(r, ring, 0, (tau + 1) % RING, h0, rn && tau + 1 < L, 1, 0, false, false, tid);
+                } else {
+                    ring_store<T, LC, B>(r, ring, 0, (tau + 1) % RING, h0, rn && tau + 1 < L, 1, (tau + 2) % RING, h1,
                                          rn, tid);
+                }
+            }
+            if constexpr (HR) {
+                // the buffer still holds plane tau for stage 0: replace it only after every wave
+                // is done with it
+                __syncthreads();
+                if (g.active) ring_store<T, LC, B, HR>(r, ring, 0, 0, false, false, 1, 0, h1, false, tid);
             }
             __syncthreads();
         }
@@ -1092,7 +1137,7 @@ __device__ __forceinline__ void wg_run_ring(const InstDev &in, int path, int k0,
     g.ctr3 = in.ctr3;
     g.active = path < in.n_paths;
     T *ring = reinterpret_cast<T *>(smem);
-    char *p = smem + (size_t)RING * (HR ? 3 : 6) * (LC * LC / 2) * sizeof(T);
+    char *p = smem + ((size_t)RING * (HR ? 3 : 6) + (HR ? 3 : 0)) * (LC * LC / 2) * sizeof(T);
     g.shacc = reinterpret_cast<double *>(p);
     g.red = reinterpret_cast<T *>(p + 128);
     g.sp = gsp;
