@@ -8,14 +8,18 @@ FP64 cross-path statistics -- 5.03e11 spin updates per step, in one persistent h
 Also reported on the same GPU: the plain per-instance FP64 engine on the same workload, the
 4-standard-error agreement of the FP32 results with the FP64 CPU oracle (sampled paths,
 stored by tests/golden/make_oracle_golden.py), the VALU and device-memory rooflines of the
-batch kernels (the one they come closer to as "roofline"), and the oracle itself timed on the
-host cores.
+batch kernels (the one they come closer to as "roofline"; the VALU ceiling is the update's
+instruction mix measured in the same process), and the oracle itself timed on the host cores.
+The default run adds one timed pass each of the largest configuration (the uneven batch of 96
+instances, "largest_config") and of the two device-memory configurations (L = 32 and L = 64,
+"device_memory_configs"), with their rooflines and oracle agreement.
 
 --workload selects another batched FP32 workload of paper_1305_6758_amd/workloads.py (same
 JSON line; the plain FP64 comparison runs only where its resident spins fit). For the
 Binder-cumulant workload the line also carries the cumulants, their ratio and the crossing.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--skip-plain] [--skip-cpu]
+                      [--skip-largest]
 """
 import argparse
 import json
@@ -485,6 +489,9 @@ def run_experiment(name, spec, steps, mix):
 # The largest configuration: the uneven batch of 96 (L, T) instances, measured once per bench
 # run beside the stepped default workload.
 LARGEST = "uneven-batch-96-fp32"
+# the two device-memory configurations: L = 32, 1024 paths, 5000 + 5000 sweeps; L = 64, 256
+# paths, 10000 + 10000 sweeps (one timed pass each in the default run)
+DEVICE_MEMORY_CONFIGS = ("L32-T1.443-p1024", "L64-T1.443-p256-fp32")
 
 
 def parity_summary(rows):
@@ -502,7 +509,7 @@ def parity_summary(rows):
     return {"comparisons": n, "max_diff_over_bound": worst[0], "worst": worst[1]}
 
 
-def measure_workload(name, steps, warmup, mix, a, plain_paths=None, compact=False):
+def measure_workload(name, steps, warmup, mix, a, plain_paths=None, compact=False, cpu=True):
     """One batched (or single-instance) FP32 workload of workloads.WORKLOADS: `steps` timed
     passes after `warmup` untimed ones, parity with the stored oracle sample, the VALU and
     device-memory rooflines, the plain FP64 engine on the same seeds (all paths, or the first
@@ -596,7 +603,7 @@ def measure_workload(name, steps, warmup, mix, a, plain_paths=None, compact=Fals
             out["fp32_vs_fp64"] = {"comparisons": len(within), "within_4sigma": int(sum(within)),
                                    "max_abs_rel_diff": max(abs(row[k]["rel_diff"] or 0.0) for row in cmp
                                                            for k in ("e_mean", "absm_mean"))}
-    if not a.skip_cpu:
+    if cpu and not a.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(instances, init=WORKLOADS[name].get("init", "sphere"),
                                            idx=None if len(instances) <= 16 else
                                            max(range(len(instances)), key=lambda i: instances[i][0]))
@@ -621,7 +628,8 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-largest", action="store_true",
-                    help="default workload only: leave out the one-pass record of the uneven batch")
+                    help="default workload only: leave out the one-pass records of the uneven batch and "
+                         "of the two device-memory configurations")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the engine runs its paths on a single MI355X; several GPUs "
@@ -663,6 +671,16 @@ def main():
         for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
             sub.pop(k, None)
         out["largest_config"] = sub
+    if default and not a.skip_largest:
+        # the device-memory configurations, one timed pass each (the plain FP64 engine on a
+        # sample of their paths; no CPU leg)
+        out["device_memory_configs"] = {}
+        for w in DEVICE_MEMORY_CONFIGS:
+            log(f"device-memory configuration: {w}, one pass")
+            sub, _ = measure_workload(w, 1, 0, mix, a, plain_paths=64, compact=True, cpu=False)
+            for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+                sub.pop(k, None)
+            out["device_memory_configs"][w] = sub
     print(json.dumps(out), flush=True)
 
 
