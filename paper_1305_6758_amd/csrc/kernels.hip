@@ -741,19 +741,26 @@ __device__ __attribute__((noinline)) void copy_spins(T *__restrict__ dst, const 
 // when its plane first enters the ring in the pass (colour 0 virtual planes 0 .. L - 1, every
 // colour-1 load) and written back whether or not its move is accepted, which leaves the spins
 // bit-identical to the other kernels'.
-// Half ring (PL_HRING, for sides whose two-colour slots do not fit: L = 64 in FP32): the ring
-// holds colour 0 only (five slots of one half-plane); colour 1 is read and written in place in
-// device memory, where the L2 keeps each colour-1 plane between its first read (colour 0 of
-// the plane below) and its update three steps later. Renormalisation passes normalise colour
+// Half ring (PL_HRING, for sides whose two-colour slots do not fit: L = 64 in FP32): colour 1
+// is updated in place in device memory; the LDS holds HR_SLOTS = 4 slots of colour 0 and two
+// buffers of colour 1 (the plane being updated and the one below). Each step has two phases,
+// each over every lane (path_sweeps_hring): colour 0 of plane tau reads five of its six
+// neighbours from the buffers and the one above from device memory, then colour 1 of plane
+// tau - 1 reads all its neighbours from the slots. A colour-1 plane is read from device memory
+// twice per pass, one step apart (into its buffer with the plane below, and for its own
+// update), so the L2 still holds it the second time. Renormalisation passes normalise colour
 // 1 in place before the pass (the colour-0 rule as above).
 constexpr int RING = 5;
 
-// LDS of a ring workgroup: RING slots of both colours of a z-plane (half ring: colour 0, plus
-// one buffer for colour 1 of the plane being updated), accumulators, reduction slots.
+// The half ring's LDS: HR_SLOTS slots of colour 0 and two buffers of colour 1.
+constexpr int HR_SLOTS = 4;
+
+// LDS of a ring workgroup: the plane slots (RING of both colours of a z-plane; half ring:
+// HR_SLOTS of colour 0 and two colour-1 buffers), accumulators, reduction slots.
 template <typename T>
 __host__ __device__ constexpr size_t ring_lds_bytes(int L, int B, bool half = false)
 {
-    return ((size_t)RING * (half ? 3 : 6) + (half ? 3 : 0)) * ((size_t)L * L / 2) * sizeof(T) + 128 +
+    return ((size_t)(half ? (HR_SLOTS + 2) * 3 : RING * 6)) * ((size_t)L * L / 2) * sizeof(T) + 128 +
            (size_t)(B / 16) * 4 * sizeof(T);
 }
 
@@ -826,7 +833,7 @@ __device__ __forceinline__ void ring_load(RingRegs<T, LC, B> &r, const T *gsp, i
 
 // Stores what ring_load brought in into ring slots s0 / s1 (normalising first where n0 / n1).
 // HR (half ring): the slots hold colour 0 only, and the second half-plane (colour 1) goes to
-// the colour-1 buffer after the slots (s1, c1 unused).
+// colour-1 buffer s1 after the HR_SLOTS slots (c1 unused).
 template <typename T, int LC, int B, bool HR = false>
 __device__ __forceinline__ void ring_store(RingRegs<T, LC, B> &r, T *ring, int c0, int s0, bool h0, bool n0, int c1,
                                            int s1, bool h1, bool n1, int tid)
@@ -841,7 +848,8 @@ __device__ __forceinline__ void ring_store(RingRegs<T, LC, B> &r, T *ring, int c
         if (q < 2 * NQ && (second ? h1 : h0)) {
             const int c = second ? c1 : c0, sl = second ? s1 : s0, rq = q - (second ? NQ : 0);
             if (second ? n1 : n0) normalise_sites(r.x[i], r.y[i], r.z[i]);
-            T *o = (HR && second) ? ring + RING * SLOT + E * rq : ring + sl * SLOT + c * 3 * PLANE + E * rq;
+            T *o = (HR && second) ? ring + HR_SLOTS * SLOT + sl * 3 * PLANE + E * rq
+                                  : ring + sl * SLOT + c * 3 * PLANE + E * rq;
             *reinterpret_cast<V *>(o) = r.x[i];
             *reinterpret_cast<V *>(o + PLANE) = r.y[i];
             *reinterpret_cast<V *>(o + 2 * PLANE) = r.z[i];
@@ -861,29 +869,18 @@ struct RingSite {
 template <int LC, int B>
 constexpr bool ring_compact() { return ((B / 2) % (LC / 2)) == 0; }
 
-template <typename T, int C, int LC, int B, int K, bool HR = false>
+template <typename T, int C, int LC, int B, int K>
 __device__ __forceinline__ void ring_stage(const GroupCtx<T> &g, const RingSite (&q)[K], T *ring, T *gsp, int v,
                                            uint32_t k, const Coef<T> &cf, bool rn, T &pe, T &pmx, T &pmy, T &pmz,
                                            unsigned long long &nacc)
 {
-    constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE, SLOT = (HR ? 3 : 6) * PLANE, SL = B / 2;
-    // components in device memory: the half ring's colour 1 (own for stage 1; for stage 0 the
-    // z-neighbours, its in-plane neighbours coming from the colour-1 buffer c1b)
-    constexpr int OWN_DEV = (HR && C == 1) ? 7 : 0, OTH_DEV = (HR && C == 0) ? 7 : 0;
-    const T *const c1b = ring + RING * SLOT;  // half ring: colour 1 of plane v, [component][L^2/2]
+    constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE, SLOT = 6 * PLANE, SL = B / 2;
     const int zp = v < LC ? v : v - LC;
     const int sl = v % RING;
     const int rdm = ((v + RING - 1) % RING - sl) * SLOT, rdp = ((v + 1) % RING - sl) * SLOT;
-    // The half ring's colour 1 in device memory: accessed from the start of each component array
-    // with absolute, non-negative site indices (spin_at takes a device index as an unsigned
-    // 32-bit offset). zb: this plane's first index; zbm / zbp: those of the planes below and
-    // above, periodic in z.
-    const int zb = zp * PLANE, zbm = (zp == 0 ? LC - 1 : zp - 1) * PLANE, zbp = (zp == LC - 1 ? 0 : zp + 1) * PLANE;
-    T *const gc1 = gsp + 3 * HALF;  // colour 1 in device memory, component x
-    T *const own = (HR && C == 1) ? gc1 : ring + sl * SLOT + C * 3 * PLANE;
-    const T *const oth = (HR && C == 0) ? gc1 : ring + sl * SLOT + (1 - C) * 3 * PLANE;
-    constexpr int OS = (HR && C == 1) ? HALF : PLANE, TS = (HR && C == 0) ? HALF : PLANE;  // component strides
-    const ColourView<T> cv{{own, own + OS, own + 2 * OS}, {oth, oth + TS, oth + 2 * TS}};
+    T *const own = ring + sl * SLOT + C * 3 * PLANE;
+    const T *const oth = ring + sl * SLOT + (1 - C) * 3 * PLANE;
+    const ColourView<T> cv{{own, own + PLANE, own + 2 * PLANE}, {oth, oth + PLANE, oth + 2 * PLANE}};
     T *const gx = gsp + C * 3 * HALF + zp * PLANE, *const gy = gx + HALF, *const gz = gx + 2 * HALF;
     const int zpar = zp & 1, idz = LC * LC * zp;
     constexpr bool COMPACT = ring_compact<LC, B>();
@@ -907,40 +904,27 @@ __device__ __forceinline__ void ring_stage(const GroupCtx<T> &g, const RingSite 
             const int p = (r.ypar + zpar + C) & 1;
             const int h = r.s;  // in-plane half-index
             Site st;
+            st.h = h;
             st.id = r.idb + p + idz;
-            // own site: a ring slot, or (half ring, colour 1) device memory
-            st.h = (HR && C == 1) ? zb + h : h;
-            // in-plane neighbours: ring slot or colour-1 buffer (plane-local indices); z:
-            // ring slots, or (half ring, colour 0) device memory
             st.nb[0] = h + (p ? 0 : r.xm0);
             st.nb[1] = h + (p ? r.xp1 : 0);
             st.nb[2] = h + r.ym;
             st.nb[3] = h + r.yp;
-            st.nb[4] = (HR && C == 0) ? zbm + h : h + rdm;
-            st.nb[5] = (HR && C == 0) ? zbp + h : h + rdp;
-            auto store = [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
-                if (C == 0 && acc) {
-                    own[h] = nx;
-                    own[PLANE + h] = ny;
-                    own[2 * PLANE + h] = nz;
-                }
-                // (the half ring's colour 1 was normalised in place)
-                if (acc || (rn && !(HR && C == 1))) {
-                    spin_at<true>(gx, h) = acc ? nx : sx;
-                    spin_at<true>(gy, h) = acc ? ny : sy;
-                    spin_at<true>(gz, h) = acc ? nz : sz;
-                }
-            };
-            if constexpr (HR && C == 0) {
-                update_site_f<T, false>(
-                    g, false, st, k, cf, pe, pmx, pmy, pmz, nacc, [&](int c) { return own[c * PLANE + h]; },
-                    [&](int c, int n) {
-                        return n < 4 ? c1b[c * PLANE + st.nb[n]] : spin_at<true>(gc1 + c * HALF, st.nb[n]);
-                    },
-                    store);
-            } else {
-                update_site_s<T, false, OWN_DEV, OTH_DEV>(g, cv, C != 0, st, k, cf, pe, pmx, pmy, pmz, nacc, store);
-            }
+            st.nb[4] = h + rdm;
+            st.nb[5] = h + rdp;
+            update_site_s<T, false, 0, 0>(g, cv, C != 0, st, k, cf, pe, pmx, pmy, pmz, nacc,
+                                          [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
+                                              if (C == 0 && acc) {
+                                                  own[h] = nx;
+                                                  own[PLANE + h] = ny;
+                                                  own[2 * PLANE + h] = nz;
+                                              }
+                                              if (acc || rn) {
+                                                  spin_at<true>(gx, h) = acc ? nx : sx;
+                                                  spin_at<true>(gy, h) = acc ? ny : sy;
+                                                  spin_at<true>(gz, h) = acc ? nz : sz;
+                                              }
+                                          });
         }
     };
     if constexpr (COMPACT) {
@@ -954,9 +938,150 @@ __device__ __forceinline__ void ring_stage(const GroupCtx<T> &g, const RingSite 
     }
 }
 
+// One phase of the half ring: colour C of virtual plane v, every lane of the workgroup with
+// K sites q of the plane. Colour 0 (own in its slot) reads colour 1 in-plane from the buffer of
+// plane v, below from the buffer of plane v - 1 and above from device memory; colour 1 (own in
+// device memory) reads colour 0 of planes v - 1 .. v + 1 from their slots. Outcomes go to
+// device memory (colour 0 also to its slot); colour 1 is normalised in place before a
+// renormalisation pass, colour 0 on its way into the ring.
+template <typename T, int C, int LC, int B, int K>
+__device__ __forceinline__ void hring_stage(const GroupCtx<T> &g, const RingSite (&q)[K], T *ring, T *gsp, int v,
+                                            uint32_t k, const Coef<T> &cf, bool rn, T &pe, T &pmx, T &pmy, T &pmz,
+                                            unsigned long long &nacc)
+{
+    constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE, SLOT = 3 * PLANE;
+    const int zp = v < LC ? v : v - LC;
+    const int zpar = zp & 1, idz = LC * LC * zp;
+    // colour 1 in device memory, indexed from each component's start (non-negative indices):
+    // zb / zbp the first sites of plane zp and of the plane above
+    T *const gc1 = gsp + 3 * HALF;
+    const int zb = zp * PLANE, zbp = (zp == LC - 1 ? 0 : zp + 1) * PLANE;
+    T *const g0 = gsp + zp * PLANE;  // colour 0 of plane zp in device memory (components HALF apart)
+    T *const s0 = ring + (v % HR_SLOTS) * SLOT;  // colour 0 of plane v
+    const T *const sm = ring + ((v + HR_SLOTS - 1) % HR_SLOTS) * SLOT, *const sp = ring + ((v + 1) % HR_SLOTS) * SLOT;
+    const T *const b0 = ring + HR_SLOTS * SLOT + (v & 1) * SLOT;        // colour 1 of plane v
+    const T *const bm = ring + HR_SLOTS * SLOT + ((v + 1) & 1) * SLOT;  // colour 1 of plane v - 1
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const RingSite &r = q[t];
+        if ((PLANE % B) == 0 || t < K - 1 || r.s < PLANE) {
+            const int p = (r.ypar + zpar + C) & 1;
+            const int h = r.s;  // in-plane half-index
+            Site st;
+            st.h = h;
+            st.id = r.idb + p + idz;
+            // in-plane neighbours (plane-local indices); the z-neighbours share h
+            st.nb[0] = h + (p ? 0 : r.xm0);
+            st.nb[1] = h + (p ? r.xp1 : 0);
+            st.nb[2] = h + r.ym;
+            st.nb[3] = h + r.yp;
+            st.nb[4] = st.nb[5] = h;
+            if constexpr (C == 0) {
+                update_site_f<T, false>(
+                    g, false, st, k, cf, pe, pmx, pmy, pmz, nacc, [&](int c) { return s0[c * PLANE + h]; },
+                    [&](int c, int n) {
+                        return n < 4    ? b0[c * PLANE + st.nb[n]]
+                               : n == 4 ? bm[c * PLANE + h]
+                                        : spin_at<true>(gc1 + c * HALF, zbp + h);
+                    },
+                    [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
+                        if (acc) {
+                            s0[h] = nx;
+                            s0[PLANE + h] = ny;
+                            s0[2 * PLANE + h] = nz;
+                        }
+                        if (acc || rn) {
+                            spin_at<true>(g0, h) = acc ? nx : sx;
+                            spin_at<true>(g0 + HALF, h) = acc ? ny : sy;
+                            spin_at<true>(g0 + 2 * HALF, h) = acc ? nz : sz;
+                        }
+                    });
+            } else {
+                update_site_f<T, false>(
+                    g, true, st, k, cf, pe, pmx, pmy, pmz, nacc,
+                    [&](int c) { return spin_at<true>(gc1 + c * HALF, zb + h); },
+                    [&](int c, int n) {
+                        return n < 4 ? s0[c * PLANE + st.nb[n]] : n == 4 ? sm[c * PLANE + h] : sp[c * PLANE + h];
+                    },
+                    [&](bool acc, T nx, T ny, T nz, T, T, T) {
+                        if (acc) {
+                            spin_at<true>(gc1, zb + h) = nx;
+                            spin_at<true>(gc1 + HALF, zb + h) = ny;
+                            spin_at<true>(gc1 + 2 * HALF, zb + h) = nz;
+                        }
+                    });
+            }
+        }
+    }
+}
+
+// Measurement of sweep ks of a ring pass (the state after it; every site was added once to the
+// lane partials pe, pmx, pmy, pmz): 16-lane row sums into the reduction slots, then wave 0 sums
+// them and adds the sweep's e and m to the path's accumulators and trace.
+template <typename T, int W>
+__device__ __forceinline__ void ring_measure(const GroupCtx<T> &g, const InstDev &in, int ks, int k1, double Nd, int tid,
+                                             T &pe, T &pmx, T &pmy, T &pmz)
+{
+    const int n_therm = in.n_therm, trace_sweeps = in.trace_sweeps, wave = tid >> 6, wl = tid & 63;
+    const double J = in.J;
+    const bool meas = ks >= n_therm || ks < trace_sweeps || ks == k1 - 1;
+    if (meas) {
+        pe = row_sum(pe);
+        pmx = row_sum(pmx);
+        pmy = row_sum(pmy);
+        pmz = row_sum(pmz);
+        if ((wl & 15) == 0) {
+            T *slot = g.red + 4 * (tid >> 4);
+            slot[0] = pe;
+            slot[1] = pmx;
+            slot[2] = pmy;
+            slot[3] = pmz;
+        }
+    }
+    __syncthreads();
+    if (meas && g.active && wave == 0) {
+        T se = T(0), sx = T(0), sy = T(0), sz = T(0);
+        if (wl < 4 * W) {
+            se = g.red[4 * wl + 0];
+            sx = g.red[4 * wl + 1];
+            sy = g.red[4 * wl + 2];
+            sz = g.red[4 * wl + 3];
+        }
+        se = wave_sum(se);
+        sx = wave_sum(sx);
+        sy = wave_sum(sy);
+        sz = wave_sum(sz);
+        if (wl == 0) {
+            const double e = -J * (double)se / Nd;
+            const double mx = (double)sx / Nd, my = (double)sy / Nd, mz = (double)sz / Nd;
+            if (ks >= n_therm) {
+                const double m = sqrt(mx * mx + my * my + mz * mz);
+                g.shacc[0] += e;
+                g.shacc[1] += e * e;
+                g.shacc[2] += m;
+                g.shacc[3] += m * m;
+                g.shacc[4] += (m * m) * (m * m);
+            }
+            if (ks < trace_sweeps) {
+                double *tr = in.trace + ((size_t)g.path * trace_sweeps + ks) * 4;
+                tr[0] = e;
+                tr[1] = mx;
+                tr[2] = my;
+                tr[3] = mz;
+            }
+            if (ks == k1 - 1) {
+                g.shacc[5] = e;
+                g.shacc[6] = mx;
+                g.shacc[7] = my;
+                g.shacc[8] = mz;
+            }
+        }
+    }
+}
+
 // Sweeps [k0, k1) of one path (the whole workgroup) through the ring. Waves of even index run
 // stage 0, odd ones stage 1.
-template <typename T, int LC, int B, bool HR = false>
+template <typename T, int LC, int B>
 __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const InstDev &in, int k0, int k1, bool fresh,
                                                  T *ring)
 {
@@ -964,8 +1089,7 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
     static_assert(W % 2 == 0 && (PLANE % RingRegs<T, LC, B>::E) == 0 && L > RING, "ring shape");
     constexpr bool FP32 = std::is_same<T, float>::value;
     const double Nd = (double)L * L * L;
-    const int n_therm = in.n_therm, trace_sweeps = in.trace_sweeps, renorm_every = in.renorm_every;
-    const double J = in.J;
+    const int renorm_every = in.renorm_every;
     Coef<T> cf;
     cf.beta = (T)in.beta;
     cf.J = (T)in.J;
@@ -999,127 +1123,135 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
     __syncthreads();
     for (int ks = k0; ks < k1; ++ks) {
         const bool rn = FP32 && renorm_every > 0 && ks > 0 && ks % renorm_every == 0;
-        if constexpr (HR) {
-            // colour 1 stays in device memory: normalised in place before a renormalisation pass
-            if constexpr (FP32) if (rn && g.active) {
-                constexpr int HALF = L * PLANE;
-                T *const c1 = gsp + 3 * HALF;
-                for (int t = tid; t < HALF; t += B) {
-                    const T x = c1[t], y = c1[HALF + t], z = c1[2 * HALF + t];
-                    const float rr = __builtin_amdgcn_rsqf(fmaf(z, z, fmaf(y, y, x * x)));
-                    c1[t] = x * rr;
-                    c1[HALF + t] = y * rr;
-                    c1[2 * HALF + t] = z * rr;
-                }
-            }
-            if (rn) __syncthreads();  // (uniform) normalised before plane 0 is read below
-            // the pass starts with colour 0 of plane 0 in slot 0 and colour 1 of plane 0 in the buffer
-            if (g.active) {
-                RingRegs<T, LC, B> r;
-                ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, 0, true, tid);
-                ring_store<T, LC, B, HR>(r, ring, 0, 0, true, rn, 1, 0, true, false, tid);
-            }
-        } else {
-            // the pass starts with colour 0 of plane 0 and colour 1 of planes -1, 0, 1
-            if (g.active) {
-                RingRegs<T, LC, B> r;
-                ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, L - 1, true, tid);
-                ring_store<T, LC, B>(r, ring, 0, 0, true, rn, 1, RING - 1, true, rn, tid);
-                ring_load<T, LC, B>(r, gsp, 1, 0, true, 1, 1, true, tid);
-                ring_store<T, LC, B>(r, ring, 1, 0, true, rn, 1, 1, true, rn, tid);
-            }
+        // the pass starts with colour 0 of plane 0 and colour 1 of planes -1, 0, 1
+        if (g.active) {
+            RingRegs<T, LC, B> r;
+            ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, L - 1, true, tid);
+            ring_store<T, LC, B>(r, ring, 0, 0, true, rn, 1, RING - 1, true, rn, tid);
+            ring_load<T, LC, B>(r, gsp, 1, 0, true, 1, 1, true, tid);
+            ring_store<T, LC, B>(r, ring, 1, 0, true, rn, 1, 1, true, rn, tid);
         }
         __syncthreads();
         T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);
 #pragma unroll 1
         for (int tau = 0; tau <= L + 2; ++tau) {
             // next step's half-planes: colour 0 of plane tau + 1 (virtual planes up to L + 1),
-            // colour 1 of plane tau + 2 (up to L); half ring: colour 1 of plane tau + 1 for the
-            // buffer (up to L - 1, not yet updated in this pass: stage 1 reaches it at step tau + 3)
-            const bool h0 = tau + 1 <= L + 1, h1 = HR ? tau + 1 < L : tau + 2 <= L;
-            const int z0 = tau + 1 < L ? tau + 1 : tau + 1 - L;
-            const int z1 = HR ? tau + 1 : (tau + 2 < L ? tau + 2 : tau + 2 - L);
+            // colour 1 of plane tau + 2 (up to L)
+            const bool h0 = tau + 1 <= L + 1, h1 = tau + 2 <= L;
+            const int z0 = tau + 1 < L ? tau + 1 : tau + 1 - L, z1 = tau + 2 < L ? tau + 2 : tau + 2 - L;
             RingRegs<T, LC, B> r;
             if (g.active) ring_load<T, LC, B>(r, gsp, 0, z0, h0, 1, z1, h1, tid);
             if (g.active) {
                 if (odd_wave) {
                     if (tau >= 3)
-                        ring_stage<T, 1, LC, B, K, HR>(g, q, ring, gsp, tau - 2, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz,
-                                                       nacc);
+                        ring_stage<T, 1, LC, B, K>(g, q, ring, gsp, tau - 2, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
                 } else if (tau < L) {
-                    ring_stage<T, 0, LC, B, K, HR>(g, q, ring, gsp, tau, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
+                    ring_stage<T, 0, LC, B, K>(g, q, ring, gsp, tau, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
                 }
-                if constexpr (HR) {
-                    ring_store<T, LC, B, HR>(r, ring, 0, (tau + 1) % RING, h0, rn && tau + 1 < L, 1, 0, false, false, tid);
-                } else {
-                    ring_store<T, LC, B>(r, ring, 0, (tau + 1) % RING, h0, rn && tau + 1 < L, 1, (tau + 2) % RING, h1,
-                                         rn, tid);
-                }
-            }
-            if constexpr (HR) {
-                // the buffer still holds plane tau for stage 0: replace it only after every wave
-                // is done with it
-                __syncthreads();
-                if (g.active) ring_store<T, LC, B, HR>(r, ring, 0, 0, false, false, 1, 0, h1, false, tid);
+                ring_store<T, LC, B>(r, ring, 0, (tau + 1) % RING, h0, rn && tau + 1 < L, 1, (tau + 2) % RING, h1, rn,
+                                     tid);
             }
             __syncthreads();
         }
-        // measurement of sweep ks (the state after it): every site was added once
-        const bool meas = ks >= n_therm || ks < trace_sweeps || ks == k1 - 1;
-        if (meas) {
-            pe = row_sum(pe);
-            pmx = row_sum(pmx);
-            pmy = row_sum(pmy);
-            pmz = row_sum(pmz);
-            if ((wl & 15) == 0) {
-                T *slot = g.red + 4 * (tid >> 4);
-                slot[0] = pe;
-                slot[1] = pmx;
-                slot[2] = pmy;
-                slot[3] = pmz;
-            }
-        }
-        __syncthreads();
-        if (meas && g.active && wave == 0) {
-            T se = T(0), sx = T(0), sy = T(0), sz = T(0);
-            if (wl < 4 * W) {
-                se = g.red[4 * wl + 0];
-                sx = g.red[4 * wl + 1];
-                sy = g.red[4 * wl + 2];
-                sz = g.red[4 * wl + 3];
-            }
-            se = wave_sum(se);
-            sx = wave_sum(sx);
-            sy = wave_sum(sy);
-            sz = wave_sum(sz);
-            if (wl == 0) {
-                const double e = -J * (double)se / Nd;
-                const double mx = (double)sx / Nd, my = (double)sy / Nd, mz = (double)sz / Nd;
-                if (ks >= n_therm) {
-                    const double m = sqrt(mx * mx + my * my + mz * mz);
-                    g.shacc[0] += e;
-                    g.shacc[1] += e * e;
-                    g.shacc[2] += m;
-                    g.shacc[3] += m * m;
-                    g.shacc[4] += (m * m) * (m * m);
-                }
-                if (ks < trace_sweeps) {
-                    double *tr = in.trace + ((size_t)g.path * trace_sweeps + ks) * 4;
-                    tr[0] = e;
-                    tr[1] = mx;
-                    tr[2] = my;
-                    tr[3] = mz;
-                }
-                if (ks == k1 - 1) {
-                    g.shacc[5] = e;
-                    g.shacc[6] = mx;
-                    g.shacc[7] = my;
-                    g.shacc[8] = mz;
-                }
-            }
-        }
+        ring_measure<T, W>(g, in, ks, k1, Nd, tid, pe, pmx, pmy, pmz);
         // (the next pass's first stores go to the ring, not to the partial slots, which are
         // written again only after L + 3 more barriers)
+    }
+    if (g.active && wl == 0) atomicAdd((unsigned long long *)&g.shacc[9], nacc);
+    __syncthreads();
+}
+
+// Sweeps [k0, k1) of one path through the half ring, in two phases per step tau = 0 .. L + 1
+// (every lane in each): phase A updates colour 0 of plane tau (tau < L), phase B colour 1 of
+// virtual plane tau - 1 (tau >= 2: planes 1 .. L - 1, then 0). Colour 1 of a plane is updated
+// only after colour 0 of both its z-neighbours, and colour 0 of a plane reads colour 1 of
+// planes tau - 1 .. tau + 1 before any of them is updated (plane 0's colour 1 last of all), so
+// the order is that of the sequential half-sweeps. Each step loads colour 0 of plane tau + 1
+// (virtual planes up to L + 1) and colour 1 of plane tau + 1 (up to L - 1) into registers and
+// stores them during phase B, into the slot of plane tau - 3 and the buffer of plane tau - 1,
+// which phase B does not read; a barrier separates the phases and ends the step.
+template <typename T, int LC, int B>
+__device__ __forceinline__ void path_sweeps_hring(const GroupCtx<T> &g, const InstDev &in, int k0, int k1,
+                                                  bool fresh, T *ring)
+{
+    constexpr int L = LC, HL = L / 2, PLANE = L * L / 2, HALF = L * PLANE, W = B / 64, K = (PLANE + B - 1) / B;
+    static_assert((PLANE % RingRegs<T, LC, B>::E) == 0 && L > RING, "ring shape");
+    constexpr bool FP32 = std::is_same<T, float>::value;
+    const double Nd = (double)L * L * L;
+    const int renorm_every = in.renorm_every;
+    Coef<T> cf;
+    cf.beta = (T)in.beta;
+    cf.J = (T)in.J;
+    cf.q = (float)(in.beta * in.J * 1.4426950408889634);  // beta J log2(e)
+    const int tid = g.lane, wl = tid & 63;
+    unsigned long long nacc = 0;
+    T *const gsp = g.sp;
+
+    if (g.active && fresh) init_path<T, B>(gsp, nullptr, nullptr, L, tid, g.path, g.key0, g.key1, g.ctr3, in.init);
+    // this lane's sites of a plane's colour (the same in every plane and for both colours)
+    RingSite q[K];
+    {
+        int lane = tid;
+        asm volatile("" : "+v"(lane));  // not hoisted out of a persistent kernel's item loop
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const int sidx = lane + B * t;
+            const int jx = sidx % HL, y = sidx / HL;
+            q[t].s = sidx;
+            q[t].y = y;
+            q[t].idb = 2 * jx + L * y;
+            q[t].ypar = y & 1;
+            q[t].xm0 = (jx == 0) ? HL - 1 : -1;
+            q[t].xp1 = (jx == HL - 1) ? -(HL - 1) : 1;
+            q[t].ym = (y == 0) ? (L - 1) * HL : -HL;
+            q[t].yp = (y == L - 1) ? -(L - 1) * HL : HL;
+        }
+    }
+    __syncthreads();
+    for (int ks = k0; ks < k1; ++ks) {
+        const bool rn = FP32 && renorm_every > 0 && ks > 0 && ks % renorm_every == 0;
+        // colour 1 stays in device memory: normalised in place before a renormalisation pass
+        if constexpr (FP32) if (rn && g.active) {
+            T *const c1 = gsp + 3 * HALF;
+            for (int t = tid; t < HALF; t += B) {
+                const T x = c1[t], y = c1[HALF + t], z = c1[2 * HALF + t];
+                const float rr = __builtin_amdgcn_rsqf(fmaf(z, z, fmaf(y, y, x * x)));
+                c1[t] = x * rr;
+                c1[HALF + t] = y * rr;
+                c1[2 * HALF + t] = z * rr;
+            }
+        }
+        if (rn) __syncthreads();  // (uniform) normalised before planes 0 and L - 1 are read below
+        // the pass starts with colour 0 of plane 0 in slot 0, colour 1 of plane 0 in buffer 0 and
+        // colour 1 of plane L - 1 (below plane 0) in buffer 1
+        if (g.active) {
+            RingRegs<T, LC, B> r;
+            ring_load<T, LC, B>(r, gsp, 0, 0, true, 1, 0, true, tid);
+            ring_store<T, LC, B, true>(r, ring, 0, 0, true, rn, 1, 0, true, false, tid);
+            ring_load<T, LC, B>(r, gsp, 0, 0, false, 1, L - 1, true, tid);
+            ring_store<T, LC, B, true>(r, ring, 0, 0, false, false, 1, 1, true, false, tid);
+        }
+        __syncthreads();
+        T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);
+#pragma unroll 1
+        for (int tau = 0; tau <= L + 1; ++tau) {
+            const bool h0 = tau + 1 <= L + 1, h1 = tau + 1 < L;
+            const int z0 = tau + 1 < L ? tau + 1 : tau + 1 - L, z1 = tau + 1 < L ? tau + 1 : 0;
+            RingRegs<T, LC, B> r;
+            if (g.active) ring_load<T, LC, B>(r, gsp, 0, z0, h0, 1, z1, h1, tid);
+            if (g.active && tau < L)
+                hring_stage<T, 0, LC, B, K>(g, q, ring, gsp, tau, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
+            __syncthreads();
+            if (g.active) {
+                if (tau >= 2)
+                    hring_stage<T, 1, LC, B, K>(g, q, ring, gsp, tau - 1, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz,
+                                                nacc);
+                ring_store<T, LC, B, true>(r, ring, 0, (tau + 1) % HR_SLOTS, h0, rn && tau + 1 < L, 1, (tau + 1) & 1,
+                                           h1, false, tid);
+            }
+            __syncthreads();
+        }
+        ring_measure<T, W>(g, in, ks, k1, Nd, tid, pe, pmx, pmy, pmz);
     }
     if (g.active && wl == 0) atomicAdd((unsigned long long *)&g.shacc[9], nacc);
     __syncthreads();
@@ -1137,14 +1269,15 @@ __device__ __forceinline__ void wg_run_ring(const InstDev &in, int path, int k0,
     g.ctr3 = in.ctr3;
     g.active = path < in.n_paths;
     T *ring = reinterpret_cast<T *>(smem);
-    char *p = smem + ((size_t)RING * (HR ? 3 : 6) + (HR ? 3 : 0)) * (LC * LC / 2) * sizeof(T);
+    char *p = smem + ring_lds_bytes<T>(LC, B, HR) - 128 - (size_t)(B / 16) * 4 * sizeof(T);
     g.shacc = reinterpret_cast<double *>(p);
     g.red = reinterpret_cast<T *>(p + 128);
     g.sp = gsp;
     g.sp1 = nullptr;
     g.sp0z = nullptr;
     load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
-    path_sweeps_ring<T, LC, B, HR>(g, in, k0, k1, fresh, ring);
+    if constexpr (HR) path_sweeps_hring<T, LC, B>(g, in, k0, k1, fresh, ring);
+    else path_sweeps_ring<T, LC, B>(g, in, k0, k1, fresh, ring);
     store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
 }
 
