@@ -72,3 +72,30 @@ def test_fused_batch_refused_without_members():
         mmc.mmc_destroy(ctx)
     plan, _ = run(mmc.MMC_BATCH_AUTO, pins=["f32-lds-L8-g64", "f32-hbm-L48-g512"], insts=insts)
     assert "launches=2" in plan and "fused" not in plan
+
+
+def test_per_variant_launches_on_fewer_graph_branches():
+    """The per-variant launches of a batch run on at most GPU_MAX_HW_QUEUES graph branches (4
+    when unset), the smallest launches one after another on the last branch: with 1, 2 and 4
+    branches the eight launches of the batch give the same per-path results bit for bit."""
+    import os
+    from paper_1305_6758_amd import mmc
+    say("case per-variant launches on 1, 2 and 4 graph branches")
+    old = os.environ.get("GPU_MAX_HW_QUEUES")
+    results = []
+    try:
+        for q in ("1", "2", "4"):
+            os.environ["GPU_MAX_HW_QUEUES"] = q  # read by the library when it captures the batch's graph
+            plan, res = run(mmc.MMC_BATCH_PER_VARIANT)
+            assert "launches=8" in plan
+            results.append(res)
+    finally:
+        if old is None:
+            os.environ.pop("GPU_MAX_HW_QUEUES", None)
+        else:
+            os.environ["GPU_MAX_HW_QUEUES"] = old
+    for res in results[1:]:
+        for i, (g, r) in enumerate(zip(res, results[0])):
+            assert np.array_equal(g["n_accept"], r["n_accept"]), i
+            for k in ("e_mean", "e2_mean", "absm_mean", "m2_mean", "m4_mean", "final_e", "final_m"):
+                assert np.array_equal(g[k], r[k], equal_nan=True), (i, k)
