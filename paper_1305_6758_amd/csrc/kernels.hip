@@ -940,14 +940,15 @@ __device__ __forceinline__ void ring_stage(const GroupCtx<T> &g, const RingSite 
 
 // One phase of the half ring: colour C of virtual plane v, every lane of the workgroup with
 // K sites q of the plane. Colour 0 (own in its slot) reads colour 1 in-plane from the buffer of
-// plane v, below from the buffer of plane v - 1 and above from device memory; colour 1 (own in
-// device memory) reads colour 0 of planes v - 1 .. v + 1 from their slots. Outcomes go to
-// device memory (colour 0 also to its slot); colour 1 is normalised in place before a
-// renormalisation pass, colour 0 on its way into the ring.
+// plane v, below from the buffer of plane v - 1 and above from device memory; colour 1 takes
+// its own spins from own1 (read from the plane's buffer before the phase) and colour 0 of
+// planes v - 1 .. v + 1 from their slots. Outcomes go to device memory (colour 0 also to its
+// slot); colour 1 is normalised in place before a renormalisation pass, colour 0 on its way
+// into the ring.
 template <typename T, int C, int LC, int B, int K>
-__device__ __forceinline__ void hring_stage(const GroupCtx<T> &g, const RingSite (&q)[K], T *ring, T *gsp, int v,
-                                            uint32_t k, const Coef<T> &cf, bool rn, T &pe, T &pmx, T &pmy, T &pmz,
-                                            unsigned long long &nacc)
+__device__ __forceinline__ void hring_stage(const GroupCtx<T> &g, const RingSite (&q)[K], const T (&own1)[K][3], T *ring,
+                                            T *gsp, int v, uint32_t k, const Coef<T> &cf, bool rn, T &pe, T &pmx,
+                                            T &pmy, T &pmz, unsigned long long &nacc)
 {
     constexpr int PLANE = LC * LC / 2, HALF = LC * PLANE, SLOT = 3 * PLANE;
     const int zp = v < LC ? v : v - LC;
@@ -998,8 +999,7 @@ __device__ __forceinline__ void hring_stage(const GroupCtx<T> &g, const RingSite
                     });
             } else {
                 update_site_f<T, false>(
-                    g, true, st, k, cf, pe, pmx, pmy, pmz, nacc,
-                    [&](int c) { return spin_at<true>(gc1 + c * HALF, zb + h); },
+                    g, true, st, k, cf, pe, pmx, pmy, pmz, nacc, [&](int c) { return own1[t][c]; },
                     [&](int c, int n) {
                         return n < 4 ? s0[c * PLANE + st.nb[n]] : n == 4 ? sm[c * PLANE + h] : sp[c * PLANE + h];
                     },
@@ -1167,14 +1167,18 @@ __device__ __forceinline__ void path_sweeps_ring(const GroupCtx<T> &g, const Ins
 // only after colour 0 of both its z-neighbours, and colour 0 of a plane reads colour 1 of
 // planes tau - 1 .. tau + 1 before any of them is updated (plane 0's colour 1 last of all), so
 // the order is that of the sequential half-sweeps. Each step loads colour 0 of plane tau + 1
-// (virtual planes up to L + 1) and colour 1 of plane tau + 1 (up to L - 1) into registers and
-// stores them during phase B, into the slot of plane tau - 3 and the buffer of plane tau - 1,
-// which phase B does not read; a barrier separates the phases and ends the step.
+// (virtual planes up to L + 1) and colour 1 of virtual plane tau + 1 (up to L, plane 0 again
+// for the last phase B) into registers and stores them during phase B, into the slot of plane
+// tau - 3 and the buffer of plane tau - 1. Phase B reads no buffer: before the first barrier
+// each lane copies the spins of its phase-B sites from the buffer of plane tau - 1 into
+// registers. So a colour-1 plane is fetched from device memory once per pass (with the
+// colour-0 plane below it, whose z-neighbour reads of it hit the L2), not again for its update.
 template <typename T, int LC, int B>
 __device__ __forceinline__ void path_sweeps_hring(const GroupCtx<T> &g, const InstDev &in, int k0, int k1,
                                                   bool fresh, T *ring)
 {
-    constexpr int L = LC, HL = L / 2, PLANE = L * L / 2, HALF = L * PLANE, W = B / 64, K = (PLANE + B - 1) / B;
+    constexpr int L = LC, HL = L / 2, PLANE = L * L / 2, HALF = L * PLANE, SLOT = 3 * PLANE, W = B / 64,
+                  K = (PLANE + B - 1) / B;
     static_assert((PLANE % RingRegs<T, LC, B>::E) == 0 && L > RING, "ring shape");
     constexpr bool FP32 = std::is_same<T, float>::value;
     const double Nd = (double)L * L * L;
@@ -1235,16 +1239,28 @@ __device__ __forceinline__ void path_sweeps_hring(const GroupCtx<T> &g, const In
         T pe = T(0), pmx = T(0), pmy = T(0), pmz = T(0);
 #pragma unroll 1
         for (int tau = 0; tau <= L + 1; ++tau) {
-            const bool h0 = tau + 1 <= L + 1, h1 = tau + 1 < L;
+            const bool h0 = tau + 1 <= L + 1, h1 = tau + 1 <= L;
             const int z0 = tau + 1 < L ? tau + 1 : tau + 1 - L, z1 = tau + 1 < L ? tau + 1 : 0;
             RingRegs<T, LC, B> r;
             if (g.active) ring_load<T, LC, B>(r, gsp, 0, z0, h0, 1, z1, h1, tid);
+            // phase B's own spins (colour 1 of plane tau - 1, in the buffer the step replaces)
+            T own1[K][3];
+            if (g.active && tau >= 2) {
+                const T *const b = ring + HR_SLOTS * SLOT + ((tau - 1) & 1) * SLOT;
+#pragma unroll
+                for (int t = 0; t < K; ++t) {
+                    const int h = q[t].s < PLANE ? q[t].s : 0;  // (sites past the plane are not updated)
+                    own1[t][0] = b[h];
+                    own1[t][1] = b[PLANE + h];
+                    own1[t][2] = b[2 * PLANE + h];
+                }
+            }
             if (g.active && tau < L)
-                hring_stage<T, 0, LC, B, K>(g, q, ring, gsp, tau, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
+                hring_stage<T, 0, LC, B, K>(g, q, own1, ring, gsp, tau, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz, nacc);
             __syncthreads();
             if (g.active) {
                 if (tau >= 2)
-                    hring_stage<T, 1, LC, B, K>(g, q, ring, gsp, tau - 1, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz,
+                    hring_stage<T, 1, LC, B, K>(g, q, own1, ring, gsp, tau - 1, (uint32_t)ks, cf, rn, pe, pmx, pmy, pmz,
                                                 nacc);
                 ring_store<T, LC, B, true>(r, ring, 0, (tau + 1) % HR_SLOTS, h0, rn && tau + 1 < L, 1, (tau + 1) & 1,
                                            h1, false, tid);
