@@ -1839,6 +1839,7 @@ constexpr int BATCH_B = 512;
     X(float, 48, 1024, 1024, FLAT, PL_RING, "f32-ring-L48-g1024")     \
     X(float, 48, 768, 768, FLAT, PL_RING, "f32-ring-L48-g768")        \
     X(float, 32, 512, 512, FLAT, PL_RING, "f32-ring-L32-g512")        \
+    X(float, 64, 1024, 1024, FLAT, PL_HRING, "f32-hring-L64-g1024")   \
     X(float, 24, 512, 512, FLAT, PL_MEM, "f32-hbm-L24-g512")          \
     X(float, 32, 512, 512, COLZ, PL_MEM, "f32-hbm-L32-g512")          \
     X(float, 48, 512, 512, FLAT, PL_MEM, "f32-hbm-L48-g512")          \

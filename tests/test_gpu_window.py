@@ -134,3 +134,26 @@ def test_ring_batch_equals_device_memory_batch():
             assert np.array_equal(g[i]["n_accept"], got[0][i]["n_accept"]), i
             for k in ("e_mean", "absm_mean", "final_e"):
                 assert max_abs_diff(g[i][k], got[0][i][k]) < 1e-5, (i, k)
+
+
+def test_half_ring_batch_equals_device_memory_batch():
+    """The half-ring batch kernel (L = 64, 1024 lanes) against the device-memory batch kernel on
+    the same instances, ragged path counts, renormalisation every 3 sweeps: identical accept
+    counts (the spins are identical), energies and magnetisations to FP32 rounding."""
+    from paper_1305_6758_amd import mmc
+    insts = [(64, 1.3, 1.0, 2, 4, 3), (64, 1.45, -1.0, 1, 3, 4)]
+    got = []
+    for pin in ("f32-hbm-L64-g512", "f32-hring-L64-g1024"):
+        say(f"case half-ring batch {pin}")
+        ctx = mmc.mmc_batch_create(insts, 1234, mmc.config(precision=mmc.MMC_FP32, renorm_every=3))
+        try:
+            mmc.mmc_set_variant(ctx, pin)
+            assert pin in mmc.mmc_plan(ctx)
+            mmc.mmc_batch_run(ctx)
+            got.append([mmc.mmc_batch_results(ctx, i, x[3]) for i, x in enumerate(insts)])
+        finally:
+            mmc.mmc_destroy(ctx)
+    for i in range(len(insts)):
+        assert np.array_equal(got[1][i]["n_accept"], got[0][i]["n_accept"]), i
+        for k in ("e_mean", "absm_mean", "final_e"):
+            assert max_abs_diff(got[1][i][k], got[0][i][k]) < 1e-5, (i, k)
