@@ -89,11 +89,16 @@ typedef enum { MMC_MODEL_HEISENBERG3D = 0, MMC_MODEL_ISING2D = 1 } mmc_model;
  * workgroup's LDS, or, where only half of it fits (compiled for L = 24 and 30 in FP32, any L
  * through the generic variants), its even-colour half in LDS and the odd colour in device
  * memory (variants named *-split-*), or, where only a third fits (compiled for L = 32 in FP32),
- * the even colour's x and y components in LDS and the rest in device memory (*-splitxy-*). HBM: spins in device memory, one workgroup per path, sweeps inside
- * one launch. WINDOW: spins in device memory, each workgroup (one path) running its sweeps
- * in passes over z-planes: one sweep per pass through a ring of five z-planes in LDS, colour 1
- * two planes behind colour 0 (*-ring-*, compiled for L = 48 in FP32, single-instance and
- * batch), or several sweeps per pass with the half-sweeps pipelined over the planes, either
+ * the even colour's x and y components in LDS and the rest in device memory (*-splitxy-*).
+ * HBM: spins in device memory, one workgroup per path, sweeps inside one launch. WINDOW: spins
+ * in device memory, each workgroup (one path) running its sweeps in passes over z-planes: one
+ * sweep per pass through a ring of five z-planes of both colours in LDS, colour 1 two planes
+ * behind colour 0 (*-ring-*, compiled for L = 48 and 32 in FP32, single-instance and batch);
+ * where both colours of five planes do not fit (L = 64 in FP32), the half ring (*-hring-*):
+ * four planes of the even colour and two of the odd one in LDS, the odd colour updated in
+ * device memory, each pass step updating the even colour of one plane and then the odd colour
+ * of the plane below (single-instance and batch); or several sweeps per pass with the
+ * half-sweeps pipelined over the planes, either
  * through a sliding window of planes in LDS (compiled for L = 24, 30, 32 in FP32 and 12, 16 in
  * FP64) or with every plane left in device memory and reused through the caches (L = 32, 48,
  * 64 in FP32; 16, 24 in FP64). PLAIN: the plain FP64 engine, one launch per half-sweep and
