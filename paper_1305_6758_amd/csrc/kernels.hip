@@ -1947,11 +1947,18 @@ constexpr int FUSED_B = 1024;
     X(float, 8, 64, COLZ, PL_LDS, "f32-lds-L8-g64")
 
 // One item of a fused batch with member code (out of line: each member is register-allocated on
-// its own, not as one union of every member's live values).
+// its own, not as one union of every member's live values). The LDS base and the spin slot
+// arrive with their address spaces (LDS, global), as does the instance: through generic
+// pointers the member's every access would be a flat one.
+using LdsPtr = __attribute__((address_space(3))) char *;
+template <typename T>
+using GlobalPtr = __attribute__((address_space(1))) T *;
+
 template <typename T, int LC, int G, int MAP, int PL>
-__device__ __attribute__((noinline)) void fused_item(const InstDev &in, int path0, int total, char *smem, T *slot)
+__device__ __attribute__((noinline)) void fused_item(GlobalPtr<const InstDev> in1, int path0, int total, LdsPtr smem3,
+                                                     GlobalPtr<T> slot1)
 {
-    wg_run<T, LC, G, FUSED_B, MAP, PL>(in, path0, 0, total, true, smem, slot, false);
+    wg_run<T, LC, G, FUSED_B, MAP, PL>(*(const InstDev *)in1, path0, 0, total, true, (char *)smem3, (T *)slot1, false);
 }
 
 template <typename T>
@@ -1973,7 +1980,9 @@ __global__ __launch_bounds__(FUSED_B) __attribute__((amdgpu_waves_per_eu(4))) vo
         int idx = 0;
 #define MMC_FUSED_CASE(TT, LC, G, MAP, PL, NAME)                                                          \
     if constexpr (std::is_same<T, TT>::value) {                                                           \
-        if (m == idx) fused_item<TT, LC, G, MAP, PL>(in, item.path0, total, smem, slot);                  \
+        if (m == idx)                                                                                     \
+            fused_item<TT, LC, G, MAP, PL>((GlobalPtr<const InstDev>)&in, item.path0, total, (LdsPtr)smem,     \
+                                           (GlobalPtr<TT>)slot);                                               \
         ++idx;                                                                                            \
     }
         MMC_FUSED_MEMBERS_F32(MMC_FUSED_CASE)
