@@ -89,18 +89,22 @@ def counters_file(workload, kernel="k_batch_f32"):
     return os.path.join(ROOT, "profiles", f"{kernel}_{short}_counters.md")
 
 
-def measured_traffic(workload, kernel="k_batch_f32"):
+def measured_traffic(workload, kernel="k_batch_f32", plan=None):
     """HBM bytes per launch from the committed counter summary of the workload's dominant
-    kernel, or None when there is none or the kernels have changed since those counters were
-    taken."""
+    kernel, or None when there is none, the kernels have changed since those counters were
+    taken, or the counters were taken with another plan (the tuners may pick other variants on
+    another box)."""
     import hashlib
     try:
         text = open(counters_file(workload, kernel)).read()
     except OSError:
         return None
     sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1305_6758_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()[:16]
-    fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("kernels_sha256:", "traffic_bytes_per_launch:")))
+    fields = dict(l.split(": ", 1) for l in text.splitlines()
+                  if l.startswith(("kernels_sha256:", "traffic_bytes_per_launch:", "plan:")))
     if fields.get("kernels_sha256") != sha:
+        return None
+    if plan is not None and fields.get("plan") not in (None, plan):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -541,7 +545,7 @@ def measure_workload(name, steps, warmup, mix, a, plain_paths=None, compact=Fals
     kernel_name = (("k_batch_fused<float> " if fused else "k_batch<float> ") + " + ".join(launched)) if not single else (
         "k_window<float>" if "win-" in plan else "k_resident<float>")
     kernel_family = kernel_name.split()[0].replace("<float>", "_f32")
-    traffic = measured_traffic(name, kernel_family)
+    traffic = measured_traffic(name, kernel_family, plan)
     if mix is None:
         mix = measure_update_mix()
 
