@@ -68,7 +68,8 @@ struct Variant {
     int lds;         // 1: spins in LDS, 0: in device memory, 2: colour 0 in LDS, colour 1 in device memory,
                      // 3: colour 0's x and y components in LDS, the rest in device memory,
                      // 4: in device memory, swept through a ring of z-planes in LDS,
-                     // 5: in device memory, colour 0 swept through a ring of z-planes in LDS
+                     // 5: in device memory, colour 0 swept through a ring of z-planes in LDS,
+                     // 6: as 4, two sweeps per pass
     int block;       // threads per workgroup
     int lanes;       // threads per path (block % lanes == 0)
     size_t lds_bytes;                 // dynamic LDS per workgroup

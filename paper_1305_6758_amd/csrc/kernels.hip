@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <string.h>
 #include <type_traits>
+#include <utility>
 
 namespace mmc {
 namespace {
@@ -130,7 +131,7 @@ enum Map { COLZ = 0, FLAT = 1 };
 // LDS and colour 1 in device memory (sides whose lattice is too large for LDS but half of it
 // is not: 22 <= L <= 30 in FP32), or only colour 0's x and y components in LDS (a third of
 // the lattice: L = 32 and 34 in FP32).
-enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2, PL_SPLIT_XY = 3, PL_RING = 4, PL_HRING = 5 };
+enum Place { PL_MEM = 0, PL_LDS = 1, PL_SPLIT = 2, PL_SPLIT_XY = 3, PL_RING = 4, PL_HRING = 5, PL_RING2 = 6 };
 
 // Everything a path group needs during its sweeps; path, key and counter word are
 // wave-uniform (each wave belongs to one path group).
@@ -750,6 +751,34 @@ __device__ __attribute__((noinline)) void copy_spins(T *__restrict__ dst, const 
 // twice per pass, one step apart (into its buffer with the plane below, and for its own
 // update), so the L2 still holds it the second time. Renormalisation passes normalise colour
 // 1 in place before the pass (the colour-0 rule as above).
+// Two-sweep ring (PL_RING2, L = 32 and 48 in FP32): the same RING slots of both colours carry
+// two sweeps ks, ks + 1 per pass, as four stages: stage 0 (colour 0 of sweep ks) at virtual
+// plane tau, stage 1 (colour 1, ks) at tau - 1, stage 2 (colour 0, ks + 1) at tau - 3, stage 3
+// (colour 1, ks + 1) at tau - 4, stage j over virtual planes j .. j + L - 1 (each starts one
+// plane further round the periodic z-ring, so physical planes 0 .. j - 1 come last for it).
+// A step has two phases with a barrier after each: stages 0 and 2 (colour 0), then stages 1
+// and 3 (colour 1); the stages of a phase touch disjoint planes, and each update sees exactly
+// the neighbour values of the sequential half-sweep order. Both colours of plane v are in slot
+// v mod RING during steps v .. v + 4; around them:
+//   stage 0 takes its own spins from registers (loaded the step before) and colour 1 of plane
+//   v + 1 from device memory (untouched there until step v + 5), and writes every outcome into
+//   the slot, whose previous plane v - 5 was written back a step earlier;
+//   stage 3 takes its own spins from registers (copied from the slot in phase 1, before phase 2
+//   stores colour 1 of plane tau + 1 over them) and colour 0 of plane v - 1 from device
+//   memory, and writes every outcome there;
+//   colour 0 of plane v is written back at step v + 4, after stage 2's update at step v + 3;
+//   colour 1 reaches device memory from stage 3, and from stage 1 for virtual planes 1 and 2,
+//   whose sweep-ks state stage 3 reads again as virtual planes L + 1 and L + 2;
+//   the virtual planes past L - 1 are reloaded from device memory (colour 0 of L .. L + 3,
+//   copied into their slots by the lanes of stage 0; colour 1 of L .. L + 2).
+// Device-memory traffic per update: about 12 (1 + 3/L) B (each colour-plane read and written
+// once per two sweeps, plus the wrap-around reloads): 12.75 B at L = 48 instead of 24.5.
+// A one-sweep pass (the last sweep of an odd count, or a sweep before a renormalisation
+// boundary) runs stages 0 and 1 alone, which then write their outcomes to device memory
+// directly. Renormalisation passes normalise the whole lattice in place first. In a phase,
+// the active stages' sites (a plane of each) are dealt to the lanes as u = lane + B i, stage
+// u / plane, site u mod plane: wave-uniform, since the plane and B are multiples of 64, and
+// a phase with one active stage gives it every lane.
 constexpr int RING = 5;
 
 // The half ring's LDS: HR_SLOTS slots of colour 0 and two buffers of colour 1.
@@ -769,7 +798,7 @@ __host__ __device__ constexpr size_t ring_lds_bytes(int L, int B, bool half = fa
 template <typename T>
 __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, int pl)
 {
-    if (pl == PL_RING) return ring_lds_bytes<T>(L, B);
+    if (pl == PL_RING || pl == PL_RING2) return ring_lds_bytes<T>(L, B);
     if (pl == PL_HRING) return ring_lds_bytes<T>(L, B, true);
     const size_t ns = 3 * (size_t)L * L * L * sizeof(T);
     return (size_t)(B / G) * (pl == PL_LDS ? ns : pl == PL_SPLIT ? ns / 2 : pl == PL_SPLIT_XY ? ns / 3 : 0) +
@@ -1273,7 +1302,306 @@ __device__ __forceinline__ void path_sweeps_hring(const GroupCtx<T> &g, const In
     __syncthreads();
 }
 
-template <typename T, int LC, int B, bool HR = false>
+// ------------------------------------------------------------------ two-sweep plane ring
+// Stage codes of a phase of the two-sweep ring; R2_COPY: copy registers of colour 0 of a
+// reloaded virtual plane (L .. L + 3) into its slot.
+enum { R2_S0 = 0, R2_S1 = 1, R2_S2 = 2, R2_S3 = 3, R2_COPY = 4, R2_NONE = 5 };
+
+constexpr int ring2_gcd(int a, int b) { return b == 0 ? a : ring2_gcd(b, a % b); }
+
+template <typename T, int LC, int B>
+struct Ring2Shape {
+    static constexpr int HL = LC / 2, PLANE = LC * LC / 2, HALF = LC * PLANE;
+    // a lane's sites in any plane are congruent modulo G, i.e. DY whole rows apart
+    static constexpr int G = ring2_gcd(B, PLANE), DY = G / HL;
+    static constexpr int RMAX = (2 * PLANE + B - 1) / B;  // rounds of a phase with two stages
+    static constexpr int KS = (PLANE + B - 1) / B;        // rounds of the first stage of a phase
+    static constexpr int E = 16 / (int)sizeof(T), NQ = PLANE / E, RQ = (NQ + B - 1) / B;  // 16-byte groups
+};
+
+// Geometry of the lane's site r = lane mod G of a plane (row yr, x-pair 2 jx = idx); its
+// site of round i in region a is r + G m with m = q + (B / G) i - (plane / G) a.
+struct Ring2Lane {
+    int r, yr, q, idx, xm0, xp1;
+};
+
+template <int... I, typename F>
+__device__ __forceinline__ void unroll_each(std::integer_sequence<int, I...>, F &&f)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+// One Metropolis attempt of stage ST (colour ST & 1) of the two-sweep ring at the lane's site
+// m of virtual plane v, sweep k. own_r: the spin when stage 0 or 3 takes it from registers;
+// wglob: stage 0 / 1 also writes accepted moves to device memory.
+template <typename T, int ST, int LC, int B>
+__device__ __forceinline__ void ring2_site(const GroupCtx<T> &g, const Ring2Lane &ln, int m, int v, uint32_t k,
+                                           T *ring, T *gsp, const T (&own_r)[3], bool wglob, const Coef<T> &cf,
+                                           T &pe, T &pmx, T &pmy, T &pmz, unsigned long long &nacc)
+{
+    using S = Ring2Shape<T, LC, B>;
+    constexpr int L = LC, HL = S::HL, PLANE = S::PLANE, HALF = S::HALF, SLOT = 6 * PLANE, C = ST & 1;
+    const int s = ln.r + S::G * m, y = ln.yr + S::DY * m;
+    const int zp = v < L ? v : v - L;  // (0 <= v < 2L)
+    const int p = (y + zp + C) & 1;
+    Site st;
+    st.h = s;
+    st.id = ln.idx + p + L * y + L * L * zp;
+    // in-plane neighbours (plane-local indices); the z-neighbours share s
+    st.nb[0] = s + (p ? 0 : ln.xm0);
+    st.nb[1] = s + (p ? ln.xp1 : 0);
+    st.nb[2] = s + ((y == 0) ? (L - 1) * HL : -HL);
+    st.nb[3] = s + ((y == L - 1) ? -(L - 1) * HL : HL);
+    st.nb[4] = st.nb[5] = s;
+    T *const own = ring + (v % RING) * SLOT + C * 3 * PLANE;
+    const T *const oth = ring + (v % RING) * SLOT + (1 - C) * 3 * PLANE;
+    const T *const othm = ring + ((v + RING - 1) % RING) * SLOT + (1 - C) * 3 * PLANE;
+    const T *const othp = ring + ((v + 1) % RING) * SLOT + (1 - C) * 3 * PLANE;
+    // device memory, indexed from each component's start: zb the first site of plane zp
+    T *const gown = gsp + C * 3 * HALF;
+    const T *const goth = gsp + (1 - C) * 3 * HALF;
+    const int zb = zp * PLANE;
+    update_site_f<T, false>(
+        g, C != 0, st, k, cf, pe, pmx, pmy, pmz, nacc,
+        [&](int c) { return (ST == R2_S0 || ST == R2_S3) ? own_r[c] : own[c * PLANE + s]; },
+        [&](int c, int n) -> T {
+            if (n < 4) return oth[c * PLANE + st.nb[n]];
+            if (n == 4) {
+                if constexpr (ST == R2_S3) return spin_at<true>(goth + c * HALF, (zp == 0 ? L - 1 : zp - 1) * PLANE + s);
+                else return othm[c * PLANE + s];
+            }
+            if constexpr (ST == R2_S0) return spin_at<true>(goth + c * HALF, (zp == L - 1 ? 0 : zp + 1) * PLANE + s);
+            else return othp[c * PLANE + s];
+        },
+        [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
+            if constexpr (ST == R2_S0) {
+                own[s] = acc ? nx : sx;
+                own[PLANE + s] = acc ? ny : sy;
+                own[2 * PLANE + s] = acc ? nz : sz;
+            } else if constexpr (ST == R2_S3) {
+                spin_at<true>(gown, zb + s) = acc ? nx : sx;
+                spin_at<true>(gown + HALF, zb + s) = acc ? ny : sy;
+                spin_at<true>(gown + 2 * HALF, zb + s) = acc ? nz : sz;
+            } else {
+                if (acc) {
+                    own[s] = nx;
+                    own[PLANE + s] = ny;
+                    own[2 * PLANE + s] = nz;
+                }
+            }
+            if constexpr (ST == R2_S0 || ST == R2_S1) {
+                if (wglob && acc) {
+                    spin_at<true>(gown, zb + s) = nx;
+                    spin_at<true>(gown + HALF, zb + s) = ny;
+                    spin_at<true>(gown + 2 * HALF, zb + s) = nz;
+                }
+            }
+        });
+}
+
+// Sweeps [k0, k1) of one path (the whole workgroup) through the two-sweep ring: passes of two
+// sweeps, one-sweep passes where two cannot be taken (see the placement notes above).
+template <typename T, int LC, int B>
+__device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const InstDev &in, int k0, int k1, bool fresh,
+                                                  T *ring)
+{
+    using S = Ring2Shape<T, LC, B>;
+    using V = typename std::conditional<std::is_same<T, float>::value, float4, double2>::type;
+    constexpr int L = LC, HL = S::HL, PLANE = S::PLANE, HALF = S::HALF, SLOT = 6 * PLANE, W = B / 64;
+    constexpr int G = S::G, RMAX = S::RMAX, KS = S::KS, E = S::E, NQ = S::NQ, RQ = S::RQ;
+    static_assert(B % 64 == 0 && PLANE % 64 == 0 && G % HL == 0 && PLANE % E == 0 && L > RING, "two-sweep ring shape");
+    constexpr uint32_t CB = HALF * sizeof(T);  // bytes between components
+    constexpr bool FP32 = std::is_same<T, float>::value;
+    const double Nd = (double)L * L * L;
+    const int renorm_every = in.renorm_every;
+    Coef<T> cf;
+    cf.beta = (T)in.beta;
+    cf.J = (T)in.J;
+    cf.q = (float)(in.beta * in.J * 1.4426950408889634);  // beta J log2(e)
+    const int tid = g.lane, wl = tid & 63;
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // the wave's first lane
+    unsigned long long nacc = 0;
+    T *const gsp = g.sp;
+
+    if (g.active && fresh) init_path<T, B>(gsp, nullptr, nullptr, L, tid, g.path, g.key0, g.key1, g.ctr3, in.init);
+    Ring2Lane ln;
+    {
+        int lane = tid;
+        asm volatile("" : "+v"(lane));  // not hoisted out of a persistent kernel's item loop
+        ln.r = lane % G;
+        ln.q = lane / G;
+        const int jx = ln.r % HL;
+        ln.yr = ln.r / HL;
+        ln.idx = 2 * jx;
+        ln.xm0 = (jx == 0) ? HL - 1 : -1;
+        ln.xp1 = (jx == HL - 1) ? -(HL - 1) : 1;
+    }
+    __syncthreads();
+    // colour c of plane zp from device memory into registers, 16-byte groups j = tid + B jj
+    auto load_plane = [&](V (&r)[RQ][3], int c, int zp) {
+#pragma unroll
+        for (int jj = 0; jj < RQ; ++jj) {
+            const int j = tid + B * jj;
+            if ((NQ % B) == 0 || j < NQ) {
+                const uint32_t off = (uint32_t)(c * 3 * HALF + zp * PLANE + E * j) * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) r[jj][cc] = ld16<V>(gsp, off + cc * CB);
+            }
+        }
+    };
+    auto store_half = [&](const V (&r)[RQ][3], T *half) {
+#pragma unroll
+        for (int jj = 0; jj < RQ; ++jj) {
+            const int j = tid + B * jj;
+            if ((NQ % B) == 0 || j < NQ) {
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) *reinterpret_cast<V *>(half + cc * PLANE + E * j) = r[jj][cc];
+            }
+        }
+    };
+    // colour 0 of plane zp at the lane's sites of a phase's first stage (rounds i < KS)
+    auto load_own0 = [&](T (&o)[KS][3], int zp) {
+#pragma unroll
+        for (int i = 0; i < KS; ++i) {
+            const int s = tid + B * i;
+            if ((PLANE % B) == 0 || s < PLANE) {
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) o[i][cc] = spin_at<true>(gsp + cc * HALF, zp * PLANE + s);
+            }
+        }
+    };
+
+    for (int ks = k0; ks < k1;) {
+        const bool rn = FP32 && renorm_every > 0 && ks > 0 && ks % renorm_every == 0;
+        const bool two = ks + 1 < k1 && !(FP32 && renorm_every > 0 && (ks + 1) % renorm_every == 0);
+        if constexpr (FP32) {
+            if (rn && g.active) renorm_path<B>(gsp, nullptr, nullptr, L, tid);
+            if (rn) __syncthreads();  // (uniform) normalised before any plane is read below
+        }
+        // colour 1 of planes -1 and 0 into their slots, colour 0 of plane 0 into registers
+        T own0[KS][3];
+        if (g.active) {
+            V r[RQ][3];
+            load_plane(r, 1, L - 1);
+            store_half(r, ring + (RING - 1) * SLOT + 3 * PLANE);
+            load_plane(r, 1, 0);
+            store_half(r, ring + 3 * PLANE);
+            load_own0(own0, 0);
+        }
+        __syncthreads();
+        const int nsteps = two ? L + 7 : L + 2, c1_last = two ? L + 2 : L, c0_last = two ? L + 3 : L + 1;
+        T pA[4] = {T(0), T(0), T(0), T(0)}, pB[4] = {T(0), T(0), T(0), T(0)};  // partials of sweeps ks, ks + 1
+#pragma unroll 1
+        for (int tau = 0; tau < nsteps; ++tau) {
+            // next step's colour 1 (virtual plane tau + 1, stored in phase 2) and colour 0 (its
+            // first stage's own spins) into registers
+            const bool h1 = tau + 1 <= c1_last, h0 = tau + 1 <= c0_last;
+            const int zn = tau + 1 < L ? tau + 1 : tau + 1 - L;
+            V r1[RQ][3];
+            T own0n[KS][3];
+            if (g.active && h1) load_plane(r1, 1, zn);
+            if (g.active && h0) load_own0(own0n, zn);
+            // phase 1 (colour 0): stage 0 or the copy of a reloaded plane, then stage 2
+            const int f1 = tau < L ? R2_S0 : (tau <= c0_last ? R2_COPY : R2_NONE);
+            const bool s2 = two && tau >= 5 && tau < L + 5, s1 = tau >= 2 && tau < L + 2,
+                       s3 = two && tau >= 7 && tau < L + 7;
+            const int n1 = (f1 != R2_NONE ? 1 : 0) + (s2 ? 1 : 0), first1 = f1 != R2_NONE ? f1 : R2_S2;
+            T own3[RMAX][3];
+            if (g.active) {
+                unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    const int a = (wbase + B * i) / PLANE;  // region (wave-uniform)
+                    if (a < n1) {
+                        const int m = ln.q + (B / G) * i - (PLANE / G) * a;
+                        const int stg = a == 0 ? first1 : R2_S2;
+                        if constexpr (i < KS) {
+                            if (stg == R2_S0) {
+                                ring2_site<T, R2_S0, LC, B>(g, ln, m, tau, (uint32_t)ks, ring, gsp, own0[i], !two, cf,
+                                                            pA[0], pA[1], pA[2], pA[3], nacc);
+                                return;
+                            }
+                            if (stg == R2_COPY) {
+                                T *const o = ring + (tau % RING) * SLOT;
+                                const int s = ln.r + G * m;
+                                o[s] = own0[i][0];
+                                o[PLANE + s] = own0[i][1];
+                                o[2 * PLANE + s] = own0[i][2];
+                                return;
+                            }
+                        }
+                        ring2_site<T, R2_S2, LC, B>(g, ln, m, tau - 3, (uint32_t)(ks + 1), ring, gsp, own0[0], false,
+                                                    cf, pB[0], pB[1], pB[2], pB[3], nacc);
+                    }
+                });
+                if (s3) {
+                    // stage 3's own spins (colour 1 of plane tau - 4), before phase 2 replaces them
+                    const int a3 = s1 ? 1 : 0;
+                    const T *const src = ring + ((tau - 4) % RING) * SLOT + 3 * PLANE;
+                    unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
+                        constexpr int i = decltype(ic)::value;
+                        if ((wbase + B * i) / PLANE == a3) {
+                            const int s = ln.r + G * (ln.q + (B / G) * i - (PLANE / G) * a3);
+                            own3[i][0] = src[s];
+                            own3[i][1] = src[PLANE + s];
+                            own3[i][2] = src[2 * PLANE + s];
+                        }
+                    });
+                }
+                if (two && tau >= 4 && tau <= L + 5) {
+                    // colour 0 of plane tau - 4 back to device memory (final for this pass)
+                    const int v = tau - 4, zp = v < L ? v : v - L;
+                    const T *const src = ring + (v % RING) * SLOT;
+#pragma unroll
+                    for (int jj = 0; jj < RQ; ++jj) {
+                        const int j = tid + B * jj;
+                        if ((NQ % B) == 0 || j < NQ) {
+#pragma unroll
+                            for (int cc = 0; cc < 3; ++cc)
+                                *reinterpret_cast<V *>(gsp + cc * HALF + zp * PLANE + E * j) =
+                                    *reinterpret_cast<const V *>(src + cc * PLANE + E * j);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // phase 2 (colour 1): stage 1, then stage 3
+            if (g.active) {
+                const int n2 = (s1 ? 1 : 0) + (s3 ? 1 : 0), first2 = s1 ? R2_S1 : R2_S3;
+                unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    const int a = (wbase + B * i) / PLANE;
+                    if (a < n2) {
+                        const int m = ln.q + (B / G) * i - (PLANE / G) * a;
+                        if ((a == 0 ? first2 : R2_S3) == R2_S1)
+                            ring2_site<T, R2_S1, LC, B>(g, ln, m, tau - 1, (uint32_t)ks, ring, gsp, own3[i],
+                                                        !two || tau - 1 <= 2, cf, pA[0], pA[1], pA[2], pA[3], nacc);
+                        else
+                            ring2_site<T, R2_S3, LC, B>(g, ln, m, tau - 4, (uint32_t)(ks + 1), ring, gsp, own3[i], false,
+                                                        cf, pB[0], pB[1], pB[2], pB[3], nacc);
+                    }
+                });
+                if (h1) store_half(r1, ring + ((tau + 1) % RING) * SLOT + 3 * PLANE);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < KS; ++i) {
+                own0[i][0] = own0n[i][0];
+                own0[i][1] = own0n[i][1];
+                own0[i][2] = own0n[i][2];
+            }
+        }
+        ring_measure<T, W>(g, in, ks, k1, Nd, tid, pA[0], pA[1], pA[2], pA[3]);
+        if (two) {
+            __syncthreads();  // (wave 0 has read the partials of sweep ks)
+            ring_measure<T, W>(g, in, ks + 1, k1, Nd, tid, pB[0], pB[1], pB[2], pB[3]);
+        }
+        ks += two ? 2 : 1;
+    }
+    if (g.active && wl == 0) atomicAdd((unsigned long long *)&g.shacc[9], nacc);
+    __syncthreads();
+}
+
+template <typename T, int LC, int B, int PL>
 __device__ __forceinline__ void wg_run_ring(const InstDev &in, int path, int k0, int k1, bool fresh, char *smem, T *gsp)
 {
     GroupCtx<T> g;
@@ -1285,14 +1613,15 @@ __device__ __forceinline__ void wg_run_ring(const InstDev &in, int path, int k0,
     g.ctr3 = in.ctr3;
     g.active = path < in.n_paths;
     T *ring = reinterpret_cast<T *>(smem);
-    char *p = smem + ring_lds_bytes<T>(LC, B, HR) - 128 - (size_t)(B / 16) * 4 * sizeof(T);
+    char *p = smem + ring_lds_bytes<T>(LC, B, PL == PL_HRING) - 128 - (size_t)(B / 16) * 4 * sizeof(T);
     g.shacc = reinterpret_cast<double *>(p);
     g.red = reinterpret_cast<T *>(p + 128);
     g.sp = gsp;
     g.sp1 = nullptr;
     g.sp0z = nullptr;
     load_acc(g.shacc, in.acc + g.path, fresh, g.lane, g.active);
-    if constexpr (HR) path_sweeps_hring<T, LC, B>(g, in, k0, k1, fresh, ring);
+    if constexpr (PL == PL_HRING) path_sweeps_hring<T, LC, B>(g, in, k0, k1, fresh, ring);
+    else if constexpr (PL == PL_RING2) path_sweeps_ring2<T, LC, B>(g, in, k0, k1, fresh, ring);
     else path_sweeps_ring<T, LC, B>(g, in, k0, k1, fresh, ring);
     store_acc(g.shacc, in.acc + g.path, g.lane, g.active);
 }
@@ -1347,9 +1676,9 @@ template <typename T, int LC, int G, int B, int MAP, int PL>
 __device__ __forceinline__ void wg_run(const InstDev &in, int path0, int k0, int k1, bool fresh, char *smem, T *gbase,
                                        bool resident)
 {
-    if constexpr (PL == PL_RING || PL == PL_HRING) {
+    if constexpr (PL == PL_RING || PL == PL_HRING || PL == PL_RING2) {
         static_assert(G == B, "one path per workgroup");
-        wg_run_ring<T, LC, B, PL == PL_HRING>(in, path0, k0, k1, fresh, smem, gbase);
+        wg_run_ring<T, LC, B, PL>(in, path0, k0, k1, fresh, smem, gbase);
     } else {
         wg_run_groups<T, LC, G, B, MAP, PL>(in, path0, k0, k1, fresh, smem, gbase, resident);
     }
@@ -1365,7 +1694,8 @@ constexpr int target_waves(int L, int B, int G, int pl)
     if (pl == PL_MEM || L == 0) return fp64 ? 2 : 4;
     const int wgs = (int)((size_t)160 * 1024 / lds_layout_bytes<T>(L, B, G, pl));
     // (the plane ring keeps a whole update's worth of geometry and in-flight planes per lane)
-    const int w = wgs * (B / 64) / 4, cap = (pl == PL_RING || pl == PL_HRING) ? (fp64 ? 2 : 4) : (fp64 ? 4 : 8);
+    const int w = wgs * (B / 64) / 4,
+              cap = (pl == PL_RING || pl == PL_HRING || pl == PL_RING2) ? (fp64 ? 2 : 4) : (fp64 ? 4 : 8);
     return w < 1 ? 1 : (w > cap ? cap : w);
 }
 
@@ -1840,6 +2170,9 @@ constexpr int BATCH_B = 512;
     X(float, 48, 768, 768, FLAT, PL_RING, "f32-ring-L48-g768")        \
     X(float, 32, 512, 512, FLAT, PL_RING, "f32-ring-L32-g512")        \
     X(float, 64, 1024, 1024, FLAT, PL_HRING, "f32-hring-L64-g1024")   \
+    X(float, 48, 768, 768, FLAT, PL_RING2, "f32-ring2-L48-g768")      \
+    X(float, 48, 576, 576, FLAT, PL_RING2, "f32-ring2-L48-g576")      \
+    X(float, 32, 512, 512, FLAT, PL_RING2, "f32-ring2-L32-g512")      \
     X(float, 24, 512, 512, FLAT, PL_MEM, "f32-hbm-L24-g512")          \
     X(float, 32, 512, 512, COLZ, PL_MEM, "f32-hbm-L32-g512")          \
     X(float, 48, 512, 512, FLAT, PL_MEM, "f32-hbm-L48-g512")          \
@@ -2217,6 +2550,11 @@ static const Variant k_variants[] = {
     MMC_RES(float, 64, 768, 768, FLAT, PL_HRING, "f32-hring-L64-b768")
     MMC_RES(float, 48, 1024, 1024, FLAT, PL_HRING, "f32-hring-L48-b1024")
     MMC_RES(float, 16, 256, 256, FLAT, PL_HRING, "f32-hring-L16-b256")
+    // FP32, spins in device memory, two sweeps per pass through a ring of z-planes in LDS
+    MMC_RES(float, 48, 768, 768, FLAT, PL_RING2, "f32-ring2-L48-b768")
+    MMC_RES(float, 48, 576, 576, FLAT, PL_RING2, "f32-ring2-L48-b576")
+    MMC_RES(float, 32, 512, 512, FLAT, PL_RING2, "f32-ring2-L32-b512")
+    MMC_RES(float, 16, 128, 128, FLAT, PL_RING2, "f32-ring2-L16-b128")
     // FP32, spins in device memory, z-pipelined window in LDS
     MMC_WIN(float, 24, 512, 2, false, "f32-win-L24-d2-b512")
     MMC_WIN(float, 24, 1024, 3, false, "f32-win-L24-d3-b1024")
@@ -2245,6 +2583,7 @@ static const Variant k_variants[] = {
     MMC_RES(double, 12, 256, 256, FLAT, PL_RING, "f64-ring-L12-b256")
     MMC_RES(double, 16, 256, 256, FLAT, PL_RING, "f64-ring-L16-b256")
     MMC_RES(double, 16, 256, 256, FLAT, PL_HRING, "f64-hring-L16-b256")
+    MMC_RES(double, 16, 128, 128, FLAT, PL_RING2, "f64-ring2-L16-b128")
     // FP64, window (small lattices: parity of the pipelined schedule with the oracle)
     MMC_WIN(double, 12, 256, 1, false, "f64-win-L12-d1-b256")
     MMC_WIN(double, 16, 256, 2, false, "f64-win-L16-d2-b256")
@@ -2372,7 +2711,9 @@ int fused_member_like(int fp64, int L, int place)
     if (fp64) return -1;
     const int n = (int)(sizeof(k_fused_f32) / sizeof(k_fused_f32[0]));
     for (int i = 0; i < n; ++i)
-        if (k_fused_f32[i].L == L && k_fused_f32[i].place == place) return i;
+        if (k_fused_f32[i].L == L &&
+            (k_fused_f32[i].place == place || (place == PL_RING2 && k_fused_f32[i].place == PL_RING)))
+            return i;  // (the one-sweep ring's spins and accept counts are the two-sweep ring's)
     return -1;
 }
 

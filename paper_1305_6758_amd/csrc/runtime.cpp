@@ -308,11 +308,11 @@ std::string tune_key(bool batch, int fp64, int L, int n_paths)
 }
 
 // ---------------------------------------------------------------- candidates
-// Variant::lds of the plane-ring variants (both colours, or colour 0 only, in the ring): their
-// spins live in device memory and stream through LDS, so they count as window placements, not
-// LDS ones.
-constexpr int LDS_RING = 4, LDS_HALF_RING = 5;
-bool is_ring(const mmc::Variant &v) { return v.lds == LDS_RING || v.lds == LDS_HALF_RING; }
+// Variant::lds of the plane-ring variants (both colours, or colour 0 only, in the ring; one or
+// two sweeps per pass): their spins live in device memory and stream through LDS, so they
+// count as window placements, not LDS ones.
+constexpr int LDS_RING = 4, LDS_HALF_RING = 5, LDS_RING2 = 6;
+bool is_ring(const mmc::Variant &v) { return v.lds == LDS_RING || v.lds == LDS_HALF_RING || v.lds == LDS_RING2; }
 bool lds_resident(const mmc::Variant &v) { return v.lds != 0 && !is_ring(v); }
 
 bool variant_fits(const mmc::Variant &v, int fp64, int L, int lds_limit)

@@ -1,7 +1,7 @@
 """Parity of the z-pipelined window kernels (spins in device memory, swept in passes over
-z-planes): the plane rings (one sweep per pass, both colours' planes in LDS, "ring", or colour
-0's only, "hring"), and the multi-sweep windows, with the planes staged through a sliding
-window in LDS ("win") or left in device memory ("gwin").
+z-planes): the plane rings (both colours' planes in LDS with one sweep per pass, "ring", or two,
+"ring2"; colour 0's only, "hring"), and the multi-sweep windows, with the planes staged through
+a sliding window in LDS ("win") or left in device memory ("gwin").
 
   - FP64 (L = 12, 16, 24): trajectories, traces, accept counts and final spins match the
     oracle to 1e-12 -- odd sweep counts (a last pass shorter than the others), every start,
@@ -27,7 +27,7 @@ def say(*a):
 
 FP64_VARIANTS = [(12, "f64-win-L12-d1-b256"), (16, "f64-win-L16-d2-b256"), (16, "f64-gwin-L16-d2-b256"),
                  (24, "f64-gwin-L24-d3-b512"), (12, "f64-ring-L12-b256"), (16, "f64-ring-L16-b256"),
-                 (16, "f64-hring-L16-b256")]
+                 (16, "f64-hring-L16-b256"), (16, "f64-ring2-L16-b128")]
 
 
 @pytest.mark.parametrize("L,variant", FP64_VARIANTS)
@@ -48,7 +48,7 @@ def test_window_fp64_matches_oracle(L, variant):
 
 
 @pytest.mark.parametrize("variant", ["f64-win-L16-d2-b256", "f64-gwin-L16-d2-b256", "f64-ring-L16-b256",
-                                     "f64-hring-L16-b256"])
+                                     "f64-hring-L16-b256", "f64-ring2-L16-b128"])
 def test_window_fp64_split_runs(variant):
     """Sweeps run in chunks of 3, 1, 4 and the rest equal one uninterrupted run."""
     from paper_1305_6758_amd import mmc
@@ -76,7 +76,8 @@ FP32_VARIANTS = [(24, "f32-win-L24-d2-b512"), (24, "f32-win-L24-d3-b1024"), (30,
                  (48, "f32-gwin-L48-d1-b1024"), (64, "f32-gwin-L64-d1-b1024"), (16, "f32-ring-L16-b256"),
                  (32, "f32-ring-L32-b512"), (48, "f32-ring-L48-b1024"), (48, "f32-ring-L48-b768"),
                  (16, "f32-hring-L16-b256"), (48, "f32-hring-L48-b1024"), (64, "f32-hring-L64-b1024"),
-                 (64, "f32-hring-L64-b768")]
+                 (64, "f32-hring-L64-b768"), (16, "f32-ring2-L16-b128"), (32, "f32-ring2-L32-b512"),
+                 (48, "f32-ring2-L48-b768"), (48, "f32-ring2-L48-b576")]
 
 
 @pytest.mark.parametrize("L,variant", FP32_VARIANTS)
@@ -113,13 +114,15 @@ def test_set_variant_rejects_what_does_not_fit():
 
 
 def test_ring_batch_equals_device_memory_batch():
-    """The plane-ring batch kernels (L = 48, 1024 and 768 lanes) against the device-memory batch
-    kernel on the same instances, ragged path counts, renormalisation every 5 sweeps: identical
+    """The plane-ring batch kernels (L = 48: one sweep per pass with 1024 and 768 lanes, two
+    sweeps per pass with 768 and 576) against the device-memory batch kernel on the same
+    instances, ragged path counts, odd sweep counts, renormalisation every 5 sweeps: identical
     accept counts (the spins are identical), energies and magnetisations to FP32 rounding."""
     from paper_1305_6758_amd import mmc
     insts = [(48, 1.3, 1.0, 3, 6, 5), (48, 1.45, 1.0, 2, 5, 6), (48, 2.0, -1.0, 1, 3, 3)]
     got = []
-    for pin in ("f32-hbm-L48-g512", "f32-ring-L48-g1024", "f32-ring-L48-g768"):
+    for pin in ("f32-hbm-L48-g512", "f32-ring-L48-g1024", "f32-ring-L48-g768", "f32-ring2-L48-g768",
+                "f32-ring2-L48-g576"):
         say(f"case ring batch {pin}")
         ctx = mmc.mmc_batch_create(insts, 1234, mmc.config(precision=mmc.MMC_FP32, renorm_every=5))
         try:
@@ -146,6 +149,30 @@ def test_half_ring_batch_equals_device_memory_batch():
     for pin in ("f32-hbm-L64-g512", "f32-hring-L64-g1024"):
         say(f"case half-ring batch {pin}")
         ctx = mmc.mmc_batch_create(insts, 1234, mmc.config(precision=mmc.MMC_FP32, renorm_every=3))
+        try:
+            mmc.mmc_set_variant(ctx, pin)
+            assert pin in mmc.mmc_plan(ctx)
+            mmc.mmc_batch_run(ctx)
+            got.append([mmc.mmc_batch_results(ctx, i, x[3]) for i, x in enumerate(insts)])
+        finally:
+            mmc.mmc_destroy(ctx)
+    for i in range(len(insts)):
+        assert np.array_equal(got[1][i]["n_accept"], got[0][i]["n_accept"]), i
+        for k in ("e_mean", "absm_mean", "final_e"):
+            assert max_abs_diff(got[1][i][k], got[0][i][k]) < 1e-5, (i, k)
+
+
+def test_two_sweep_ring_batch_L32_equals_device_memory_batch():
+    """The two-sweep ring's L = 32 batch kernel (two workgroups per CU) against the device-memory
+    batch kernel: even and odd sweep counts, renormalisation every 4 sweeps (a one-sweep pass
+    before each boundary), identical accept counts, energies and magnetisations to FP32
+    rounding."""
+    from paper_1305_6758_amd import mmc
+    insts = [(32, 1.44, 1.0, 3, 4, 6), (32, 1.2, 1.0, 2, 3, 4), (32, 3.0, -1.0, 2, 1, 2)]
+    got = []
+    for pin in ("f32-hbm-L32-g512", "f32-ring2-L32-g512"):
+        say(f"case two-sweep ring batch {pin}")
+        ctx = mmc.mmc_batch_create(insts, 77, mmc.config(precision=mmc.MMC_FP32, renorm_every=4))
         try:
             mmc.mmc_set_variant(ctx, pin)
             assert pin in mmc.mmc_plan(ctx)
