@@ -784,13 +784,16 @@ constexpr int RING = 5;
 // The half ring's LDS: HR_SLOTS slots of colour 0 and two buffers of colour 1.
 constexpr int HR_SLOTS = 4;
 
+// The two-sweep ring's LDS: R2_SLOTS0 slots of colour 0, then R2_SLOTS1 of colour 1.
+constexpr int R2_SLOTS0 = 5, R2_SLOTS1 = 6;
+
 // LDS of a ring workgroup: the plane slots (RING of both colours of a z-plane; half ring:
 // HR_SLOTS of colour 0 and two colour-1 buffers), accumulators, reduction slots.
 template <typename T>
-__host__ __device__ constexpr size_t ring_lds_bytes(int L, int B, bool half = false)
+__host__ __device__ constexpr size_t ring_lds_bytes(int L, int B, int pl)
 {
-    return ((size_t)(half ? (HR_SLOTS + 2) * 3 : RING * 6)) * ((size_t)L * L / 2) * sizeof(T) + 128 +
-           (size_t)(B / 16) * 4 * sizeof(T);
+    const int halves = pl == PL_HRING ? HR_SLOTS + 2 : pl == PL_RING2 ? R2_SLOTS0 + R2_SLOTS1 : 2 * RING;
+    return (size_t)halves * 3 * ((size_t)L * L / 2) * sizeof(T) + 128 + (size_t)(B / 16) * 4 * sizeof(T);
 }
 
 // LDS bytes of one workgroup: spins (all of them, or colour 0), accumulators, reduction
@@ -798,8 +801,7 @@ __host__ __device__ constexpr size_t ring_lds_bytes(int L, int B, bool half = fa
 template <typename T>
 __host__ __device__ constexpr size_t lds_layout_bytes(int L, int B, int G, int pl)
 {
-    if (pl == PL_RING || pl == PL_RING2) return ring_lds_bytes<T>(L, B);
-    if (pl == PL_HRING) return ring_lds_bytes<T>(L, B, true);
+    if (pl == PL_RING || pl == PL_HRING || pl == PL_RING2) return ring_lds_bytes<T>(L, B, pl);
     const size_t ns = 3 * (size_t)L * L * L * sizeof(T);
     return (size_t)(B / G) * (pl == PL_LDS ? ns : pl == PL_SPLIT ? ns / 2 : pl == PL_SPLIT_XY ? ns / 3 : 0) +
            (size_t)(B / G) * 128 +
@@ -1316,8 +1318,17 @@ struct Ring2Shape {
     static constexpr int G = ring2_gcd(B, PLANE), DY = G / HL;
     static constexpr int RMAX = (2 * PLANE + B - 1) / B;  // rounds of a phase with two stages
     static constexpr int KS = (PLANE + B - 1) / B;        // rounds of the first stage of a phase
-    static constexpr int E = 16 / (int)sizeof(T), NQ = PLANE / E, RQ = (NQ + B - 1) / B;  // 16-byte groups
+    // a colour-plane component moves between device memory and LDS in groups of E consecutive
+    // sites, as narrow as lets every group have a lane (few registers held per lane)
+    static constexpr int EMAX = 16 / (int)sizeof(T);
+    static constexpr int E = PLANE <= B ? 1 : (PLANE <= 2 * B || EMAX == 2) ? 2 : 4;
+    static constexpr int NQ = PLANE / E, RQ = (NQ + B - 1) / B;
 };
+
+template <typename T, int E> struct R2Vec { using type = T; };
+template <> struct R2Vec<float, 2> { using type = float2; };
+template <> struct R2Vec<float, 4> { using type = float4; };
+template <> struct R2Vec<double, 2> { using type = double2; };
 
 // Geometry of the lane's site r = lane mod G of a plane (row yr, x-pair 2 jx = idx); its
 // site of round i in region a is r + G m with m = q + (B / G) i - (plane / G) a.
@@ -1331,16 +1342,25 @@ __device__ __forceinline__ void unroll_each(std::integer_sequence<int, I...>, F 
     (f(std::integral_constant<int, I>{}), ...);
 }
 
+// Colour c of virtual plane v (v >= -1) in the two-sweep ring's LDS.
+template <int PLANE, typename T>
+__device__ __forceinline__ T *ring2_slot(T *ring, int c, int v)
+{
+    return c ? ring + 3 * PLANE * (R2_SLOTS0 + (v + R2_SLOTS1) % R2_SLOTS1) : ring + 3 * PLANE * ((v + R2_SLOTS0) % R2_SLOTS0);
+}
+
 // One Metropolis attempt of stage ST (colour ST & 1) of the two-sweep ring at the lane's site
 // m of virtual plane v, sweep k. own_r: the spin when stage 0 or 3 takes it from registers;
-// wglob: stage 0 / 1 also writes accepted moves to device memory.
+// zm_r: stage 3's neighbour below (registers); wglob: stage 0 / 1 also writes accepted moves
+// to device memory.
 template <typename T, int ST, int LC, int B>
 __device__ __forceinline__ void ring2_site(const GroupCtx<T> &g, const Ring2Lane &ln, int m, int v, uint32_t k,
-                                           T *ring, T *gsp, const T (&own_r)[3], bool wglob, const Coef<T> &cf,
-                                           T &pe, T &pmx, T &pmy, T &pmz, unsigned long long &nacc)
+                                           T *ring, T *gsp, const T (&own_r)[3], const T (&zm_r)[3], bool wglob,
+                                           const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
+                                           unsigned long long &nacc)
 {
     using S = Ring2Shape<T, LC, B>;
-    constexpr int L = LC, HL = S::HL, PLANE = S::PLANE, HALF = S::HALF, SLOT = 6 * PLANE, C = ST & 1;
+    constexpr int L = LC, HL = S::HL, PLANE = S::PLANE, HALF = S::HALF, C = ST & 1;
     const int s = ln.r + S::G * m, y = ln.yr + S::DY * m;
     const int zp = v < L ? v : v - L;  // (0 <= v < 2L)
     const int p = (y + zp + C) & 1;
@@ -1353,13 +1373,13 @@ __device__ __forceinline__ void ring2_site(const GroupCtx<T> &g, const Ring2Lane
     st.nb[2] = s + ((y == 0) ? (L - 1) * HL : -HL);
     st.nb[3] = s + ((y == L - 1) ? -(L - 1) * HL : HL);
     st.nb[4] = st.nb[5] = s;
-    T *const own = ring + (v % RING) * SLOT + C * 3 * PLANE;
-    const T *const oth = ring + (v % RING) * SLOT + (1 - C) * 3 * PLANE;
-    const T *const othm = ring + ((v + RING - 1) % RING) * SLOT + (1 - C) * 3 * PLANE;
-    const T *const othp = ring + ((v + 1) % RING) * SLOT + (1 - C) * 3 * PLANE;
-    // device memory, indexed from each component's start: zb the first site of plane zp
+    T *const own = ring2_slot<PLANE>(ring, C, v);
+    const T *const oth = ring2_slot<PLANE>(ring, 1 - C, v);
+    const T *const othm = ring2_slot<PLANE>(ring, 1 - C, v - 1);
+    const T *const othp = ring2_slot<PLANE>(ring, 1 - C, v + 1);
+    // this colour in device memory, indexed from each component's start: zb the first site of
+    // plane zp
     T *const gown = gsp + C * 3 * HALF;
-    const T *const goth = gsp + (1 - C) * 3 * HALF;
     const int zb = zp * PLANE;
     update_site_f<T, false>(
         g, C != 0, st, k, cf, pe, pmx, pmy, pmz, nacc,
@@ -1367,11 +1387,10 @@ __device__ __forceinline__ void ring2_site(const GroupCtx<T> &g, const Ring2Lane
         [&](int c, int n) -> T {
             if (n < 4) return oth[c * PLANE + st.nb[n]];
             if (n == 4) {
-                if constexpr (ST == R2_S3) return spin_at<true>(goth + c * HALF, (zp == 0 ? L - 1 : zp - 1) * PLANE + s);
+                if constexpr (ST == R2_S3) return zm_r[c];
                 else return othm[c * PLANE + s];
             }
-            if constexpr (ST == R2_S0) return spin_at<true>(goth + c * HALF, (zp == L - 1 ? 0 : zp + 1) * PLANE + s);
-            else return othp[c * PLANE + s];
+            return othp[c * PLANE + s];
         },
         [&](bool acc, T nx, T ny, T nz, T sx, T sy, T sz) {
             if constexpr (ST == R2_S0) {
@@ -1406,8 +1425,8 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                                                   T *ring)
 {
     using S = Ring2Shape<T, LC, B>;
-    using V = typename std::conditional<std::is_same<T, float>::value, float4, double2>::type;
-    constexpr int L = LC, HL = S::HL, PLANE = S::PLANE, HALF = S::HALF, SLOT = 6 * PLANE, W = B / 64;
+    using V = typename R2Vec<T, S::E>::type;
+    constexpr int L = LC, HL = S::HL, PLANE = S::PLANE, HALF = S::HALF, W = B / 64;
     constexpr int G = S::G, RMAX = S::RMAX, KS = S::KS, E = S::E, NQ = S::NQ, RQ = S::RQ;
     static_assert(B % 64 == 0 && PLANE % 64 == 0 && G % HL == 0 && PLANE % E == 0 && L > RING, "two-sweep ring shape");
     constexpr uint32_t CB = HALF * sizeof(T);  // bytes between components
@@ -1478,35 +1497,37 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
             if (rn && g.active) renorm_path<B>(gsp, nullptr, nullptr, L, tid);
             if (rn) __syncthreads();  // (uniform) normalised before any plane is read below
         }
-        // colour 1 of planes -1 and 0 into their slots, colour 0 of plane 0 into registers
+        // colour 1 of planes -1, 0 and 1 into their slots, colour 0 of plane 0 into registers
         T own0[KS][3];
         if (g.active) {
             V r[RQ][3];
             load_plane(r, 1, L - 1);
-            store_half(r, ring + (RING - 1) * SLOT + 3 * PLANE);
+            store_half(r, ring2_slot<PLANE>(ring, 1, -1));
             load_plane(r, 1, 0);
-            store_half(r, ring + 3 * PLANE);
+            store_half(r, ring2_slot<PLANE>(ring, 1, 0));
+            load_plane(r, 1, 1);
+            store_half(r, ring2_slot<PLANE>(ring, 1, 1));
             load_own0(own0, 0);
         }
         __syncthreads();
         const int nsteps = two ? L + 7 : L + 2, c1_last = two ? L + 2 : L, c0_last = two ? L + 3 : L + 1;
         T pA[4] = {T(0), T(0), T(0), T(0)}, pB[4] = {T(0), T(0), T(0), T(0)};  // partials of sweeps ks, ks + 1
+        T own3[RMAX][3], zm3[RMAX][3];  // stage 3's own spins and neighbours below
 #pragma unroll 1
         for (int tau = 0; tau < nsteps; ++tau) {
-            // next step's colour 1 (virtual plane tau + 1, stored in phase 2) and colour 0 (its
-            // first stage's own spins) into registers
-            const bool h1 = tau + 1 <= c1_last, h0 = tau + 1 <= c0_last;
-            const int zn = tau + 1 < L ? tau + 1 : tau + 1 - L;
+            // colour 1 of virtual plane tau + 2 (stored in phase 2) and colour 0 of plane tau + 1
+            // (the next step's first stage's own spins) into registers
+            const bool h1 = tau + 2 <= c1_last, h0 = tau + 1 <= c0_last;
+            const int z1 = tau + 2 < L ? tau + 2 : tau + 2 - L, z0 = tau + 1 < L ? tau + 1 : tau + 1 - L;
             V r1[RQ][3];
             T own0n[KS][3];
-            if (g.active && h1) load_plane(r1, 1, zn);
-            if (g.active && h0) load_own0(own0n, zn);
+            if (g.active && h1) load_plane(r1, 1, z1);
+            if (g.active && h0) load_own0(own0n, z0);
             // phase 1 (colour 0): stage 0 or the copy of a reloaded plane, then stage 2
             const int f1 = tau < L ? R2_S0 : (tau <= c0_last ? R2_COPY : R2_NONE);
             const bool s2 = two && tau >= 5 && tau < L + 5, s1 = tau >= 2 && tau < L + 2,
                        s3 = two && tau >= 7 && tau < L + 7;
             const int n1 = (f1 != R2_NONE ? 1 : 0) + (s2 ? 1 : 0), first1 = f1 != R2_NONE ? f1 : R2_S2;
-            T own3[RMAX][3];
             if (g.active) {
                 unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
                     constexpr int i = decltype(ic)::value;
@@ -1516,12 +1537,12 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                         const int stg = a == 0 ? first1 : R2_S2;
                         if constexpr (i < KS) {
                             if (stg == R2_S0) {
-                                ring2_site<T, R2_S0, LC, B>(g, ln, m, tau, (uint32_t)ks, ring, gsp, own0[i], !two, cf,
-                                                            pA[0], pA[1], pA[2], pA[3], nacc);
+                                ring2_site<T, R2_S0, LC, B>(g, ln, m, tau, (uint32_t)ks, ring, gsp, own0[i], own0[i],
+                                                            !two, cf, pA[0], pA[1], pA[2], pA[3], nacc);
                                 return;
                             }
                             if (stg == R2_COPY) {
-                                T *const o = ring + (tau % RING) * SLOT;
+                                T *const o = ring2_slot<PLANE>(ring, 0, tau);
                                 const int s = ln.r + G * m;
                                 o[s] = own0[i][0];
                                 o[PLANE + s] = own0[i][1];
@@ -1529,14 +1550,14 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                                 return;
                             }
                         }
-                        ring2_site<T, R2_S2, LC, B>(g, ln, m, tau - 3, (uint32_t)(ks + 1), ring, gsp, own0[0], false,
-                                                    cf, pB[0], pB[1], pB[2], pB[3], nacc);
+                        ring2_site<T, R2_S2, LC, B>(g, ln, m, tau - 3, (uint32_t)(ks + 1), ring, gsp, own0[0],
+                                                    own0[0], false, cf, pB[0], pB[1], pB[2], pB[3], nacc);
                     }
                 });
                 if (s3) {
                     // stage 3's own spins (colour 1 of plane tau - 4), before phase 2 replaces them
                     const int a3 = s1 ? 1 : 0;
-                    const T *const src = ring + ((tau - 4) % RING) * SLOT + 3 * PLANE;
+                    const T *const src = ring2_slot<PLANE>(ring, 1, tau - 4);
                     unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
                         constexpr int i = decltype(ic)::value;
                         if ((wbase + B * i) / PLANE == a3) {
@@ -1550,7 +1571,7 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                 if (two && tau >= 4 && tau <= L + 5) {
                     // colour 0 of plane tau - 4 back to device memory (final for this pass)
                     const int v = tau - 4, zp = v < L ? v : v - L;
-                    const T *const src = ring + (v % RING) * SLOT;
+                    const T *const src = ring2_slot<PLANE>(ring, 0, v);
 #pragma unroll
                     for (int jj = 0; jj < RQ; ++jj) {
                         const int j = tid + B * jj;
@@ -1573,14 +1594,29 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                     if (a < n2) {
                         const int m = ln.q + (B / G) * i - (PLANE / G) * a;
                         if ((a == 0 ? first2 : R2_S3) == R2_S1)
-                            ring2_site<T, R2_S1, LC, B>(g, ln, m, tau - 1, (uint32_t)ks, ring, gsp, own3[i],
+                            ring2_site<T, R2_S1, LC, B>(g, ln, m, tau - 1, (uint32_t)ks, ring, gsp, own3[i], zm3[i],
                                                         !two || tau - 1 <= 2, cf, pA[0], pA[1], pA[2], pA[3], nacc);
                         else
-                            ring2_site<T, R2_S3, LC, B>(g, ln, m, tau - 4, (uint32_t)(ks + 1), ring, gsp, own3[i], false,
-                                                        cf, pB[0], pB[1], pB[2], pB[3], nacc);
+                            ring2_site<T, R2_S3, LC, B>(g, ln, m, tau - 4, (uint32_t)(ks + 1), ring, gsp, own3[i],
+                                                        zm3[i], false, cf, pB[0], pB[1], pB[2], pB[3], nacc);
                     }
                 });
-                if (h1) store_half(r1, ring + ((tau + 1) % RING) * SLOT + 3 * PLANE);
+                if (h1) store_half(r1, ring2_slot<PLANE>(ring, 1, tau + 2));
+                // the next step's stage 3 neighbours below: colour 0 of plane tau - 4, in its slot
+                // until phase 1 of the next step (this lane's stage-3 updates above have read zm3)
+                if (two && tau + 1 >= 7 && tau + 1 < L + 7) {
+                    const int a3 = (tau + 1 >= 2 && tau + 1 < L + 2) ? 1 : 0;
+                    const T *const src = ring2_slot<PLANE>(ring, 0, tau - 4);
+                    unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
+                        constexpr int i = decltype(ic)::value;
+                        if ((wbase + B * i) / PLANE == a3) {
+                            const int s = ln.r + G * (ln.q + (B / G) * i - (PLANE / G) * a3);
+                            zm3[i][0] = src[s];
+                            zm3[i][1] = src[PLANE + s];
+                            zm3[i][2] = src[2 * PLANE + s];
+                        }
+                    });
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -1613,7 +1649,7 @@ __device__ __forceinline__ void wg_run_ring(const InstDev &in, int path, int k0,
     g.ctr3 = in.ctr3;
     g.active = path < in.n_paths;
     T *ring = reinterpret_cast<T *>(smem);
-    char *p = smem + ring_lds_bytes<T>(LC, B, PL == PL_HRING) - 128 - (size_t)(B / 16) * 4 * sizeof(T);
+    char *p = smem + ring_lds_bytes<T>(LC, B, PL) - 128 - (size_t)(B / 16) * 4 * sizeof(T);
     g.shacc = reinterpret_cast<double *>(p);
     g.red = reinterpret_cast<T *>(p + 128);
     g.sp = gsp;
@@ -2171,6 +2207,7 @@ constexpr int BATCH_B = 512;
     X(float, 32, 512, 512, FLAT, PL_RING, "f32-ring-L32-g512")        \
     X(float, 64, 1024, 1024, FLAT, PL_HRING, "f32-hring-L64-g1024")   \
     X(float, 48, 768, 768, FLAT, PL_RING2, "f32-ring2-L48-g768")      \
+    X(float, 48, 960, 960, FLAT, PL_RING2, "f32-ring2-L48-g960")      \
     X(float, 48, 576, 576, FLAT, PL_RING2, "f32-ring2-L48-g576")      \
     X(float, 32, 512, 512, FLAT, PL_RING2, "f32-ring2-L32-g512")      \
     X(float, 24, 512, 512, FLAT, PL_MEM, "f32-hbm-L24-g512")          \
@@ -2552,6 +2589,7 @@ static const Variant k_variants[] = {
     MMC_RES(float, 16, 256, 256, FLAT, PL_HRING, "f32-hring-L16-b256")
     // FP32, spins in device memory, two sweeps per pass through a ring of z-planes in LDS
     MMC_RES(float, 48, 768, 768, FLAT, PL_RING2, "f32-ring2-L48-b768")
+    MMC_RES(float, 48, 960, 960, FLAT, PL_RING2, "f32-ring2-L48-b960")
     MMC_RES(float, 48, 576, 576, FLAT, PL_RING2, "f32-ring2-L48-b576")
     MMC_RES(float, 32, 512, 512, FLAT, PL_RING2, "f32-ring2-L32-b512")
     MMC_RES(float, 16, 128, 128, FLAT, PL_RING2, "f32-ring2-L16-b128")
