@@ -94,6 +94,9 @@ typedef enum { MMC_MODEL_HEISENBERG3D = 0, MMC_MODEL_ISING2D = 1 } mmc_model;
  * in device memory, each workgroup (one path) running its sweeps in passes over z-planes: one
  * sweep per pass through a ring of five z-planes of both colours in LDS, colour 1 two planes
  * behind colour 0 (*-ring-*, compiled for L = 48 and 32 in FP32, single-instance and batch);
+ * two sweeps per pass through five even-colour and six odd-colour planes in LDS, the four
+ * half-sweeps one to four planes apart, which halves the device-memory traffic (*-ring2-*,
+ * compiled for L = 48 and 32 in FP32 and 16 in FP32 and FP64, single-instance and batch);
  * where both colours of five planes do not fit (L = 64 in FP32), the half ring (*-hring-*):
  * four planes of the even colour and two of the odd one in LDS, the odd colour updated in
  * device memory, each pass step updating the even colour of one plane and then the odd colour

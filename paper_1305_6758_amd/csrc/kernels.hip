@@ -751,21 +751,23 @@ __device__ __attribute__((noinline)) void copy_spins(T *__restrict__ dst, const 
 // twice per pass, one step apart (into its buffer with the plane below, and for its own
 // update), so the L2 still holds it the second time. Renormalisation passes normalise colour
 // 1 in place before the pass (the colour-0 rule as above).
-// Two-sweep ring (PL_RING2, L = 32 and 48 in FP32): the same RING slots of both colours carry
-// two sweeps ks, ks + 1 per pass, as four stages: stage 0 (colour 0 of sweep ks) at virtual
-// plane tau, stage 1 (colour 1, ks) at tau - 1, stage 2 (colour 0, ks + 1) at tau - 3, stage 3
-// (colour 1, ks + 1) at tau - 4, stage j over virtual planes j .. j + L - 1 (each starts one
-// plane further round the periodic z-ring, so physical planes 0 .. j - 1 come last for it).
-// A step has two phases with a barrier after each: stages 0 and 2 (colour 0), then stages 1
-// and 3 (colour 1); the stages of a phase touch disjoint planes, and each update sees exactly
-// the neighbour values of the sequential half-sweep order. Both colours of plane v are in slot
-// v mod RING during steps v .. v + 4; around them:
-//   stage 0 takes its own spins from registers (loaded the step before) and colour 1 of plane
-//   v + 1 from device memory (untouched there until step v + 5), and writes every outcome into
-//   the slot, whose previous plane v - 5 was written back a step earlier;
-//   stage 3 takes its own spins from registers (copied from the slot in phase 1, before phase 2
-//   stores colour 1 of plane tau + 1 over them) and colour 0 of plane v - 1 from device
-//   memory, and writes every outcome there;
+// Two-sweep ring (PL_RING2, L = 32 and 48 in FP32): two sweeps ks, ks + 1 per pass, as four
+// stages: stage 0 (colour 0 of sweep ks) at virtual plane tau, stage 1 (colour 1, ks) at
+// tau - 1, stage 2 (colour 0, ks + 1) at tau - 3, stage 3 (colour 1, ks + 1) at tau - 4, stage
+// j over virtual planes j .. j + L - 1 (each starts one plane further round the periodic
+// z-ring, so physical planes 0 .. j - 1 come last for it). A step has two phases with a barrier
+// after each: stages 0 and 2 (colour 0), then stages 1 and 3 (colour 1); the stages of a phase
+// touch disjoint planes, and each update sees exactly the neighbour values of the sequential
+// half-sweep order. The LDS holds R2_SLOTS0 = 5 colour-0 slots (plane v in slot v mod 5 during
+// steps v .. v + 4) and R2_SLOTS1 = 6 colour-1 slots (plane v in slot v mod 6 during steps
+// v - 1 .. v + 4), 152 KB at L = 48; every neighbour comes from LDS or registers:
+//   stage 0 takes its own spins from registers (loaded from device memory the step before)
+//   and writes every outcome into its slot, whose previous plane v - 5 was written back to
+//   device memory a step earlier;
+//   stage 3 takes its own spins from registers, copied from their slot in phase 1 (before
+//   phase 2 stores colour 1 of plane tau + 2 over them), and its neighbours below (colour 0 of
+//   plane v - 1) from registers copied from their slot in phase 2 of the step before (that
+//   slot takes colour 0 of plane tau in phase 1), and writes every outcome to device memory;
 //   colour 0 of plane v is written back at step v + 4, after stage 2's update at step v + 3;
 //   colour 1 reaches device memory from stage 3, and from stage 1 for virtual planes 1 and 2,
 //   whose sweep-ks state stage 3 reads again as virtual planes L + 1 and L + 2;
@@ -1314,8 +1316,10 @@ constexpr int ring2_gcd(int a, int b) { return b == 0 ? a : ring2_gcd(b, a % b);
 template <typename T, int LC, int B>
 struct Ring2Shape {
     static constexpr int HL = LC / 2, PLANE = LC * LC / 2, HALF = LC * PLANE;
-    // a lane's sites in any plane are congruent modulo G, i.e. DY whole rows apart
+    // a lane's sites in any plane are congruent modulo G; COMPACT: G is whole rows (DY of them),
+    // so they share their x position and one site's geometry serves all
     static constexpr int G = ring2_gcd(B, PLANE), DY = G / HL;
+    static constexpr bool COMPACT = G % HL == 0;
     static constexpr int RMAX = (2 * PLANE + B - 1) / B;  // rounds of a phase with two stages
     static constexpr int KS = (PLANE + B - 1) / B;        // rounds of the first stage of a phase
     // a colour-plane component moves between device memory and LDS in groups of E consecutive
@@ -1331,9 +1335,12 @@ template <> struct R2Vec<float, 4> { using type = float4; };
 template <> struct R2Vec<double, 2> { using type = double2; };
 
 // Geometry of the lane's site r = lane mod G of a plane (row yr, x-pair 2 jx = idx); its
-// site of round i in region a is r + G m with m = q + (B / G) i - (plane / G) a.
+// site of round i in region a is r + G m with m = q + (B / G) i - (plane / G) a (compact
+// shapes; otherwise (lane + B i) mod plane, kept per round with its row in s, y).
+template <int RMAX>
 struct Ring2Lane {
     int r, yr, q, idx, xm0, xp1;
+    int s[RMAX], y[RMAX];
 };
 
 template <int... I, typename F>
@@ -1353,23 +1360,33 @@ __device__ __forceinline__ T *ring2_slot(T *ring, int c, int v)
 // m of virtual plane v, sweep k. own_r: the spin when stage 0 or 3 takes it from registers;
 // zm_r: stage 3's neighbour below (registers); wglob: stage 0 / 1 also writes accepted moves
 // to device memory.
-template <typename T, int ST, int LC, int B>
-__device__ __forceinline__ void ring2_site(const GroupCtx<T> &g, const Ring2Lane &ln, int m, int v, uint32_t k,
+template <typename T, int ST, int LC, int B, typename Lane>
+__device__ __forceinline__ void ring2_site(const GroupCtx<T> &g, const Lane &ln, int s, int y, int v, uint32_t k,
                                            T *ring, T *gsp, const T (&own_r)[3], const T (&zm_r)[3], bool wglob,
                                            const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
                                            unsigned long long &nacc)
 {
     using S = Ring2Shape<T, LC, B>;
     constexpr int L = LC, HL = S::HL, PLANE = S::PLANE, HALF = S::HALF, C = ST & 1;
-    const int s = ln.r + S::G * m, y = ln.yr + S::DY * m;
+    int idx, xm0, xp1;
+    if constexpr (S::COMPACT) {
+        idx = ln.idx;
+        xm0 = ln.xm0;
+        xp1 = ln.xp1;
+    } else {
+        const int jx = s - HL * y;
+        idx = 2 * jx;
+        xm0 = (jx == 0) ? HL - 1 : -1;
+        xp1 = (jx == HL - 1) ? -(HL - 1) : 1;
+    }
     const int zp = v < L ? v : v - L;  // (0 <= v < 2L)
     const int p = (y + zp + C) & 1;
     Site st;
     st.h = s;
-    st.id = ln.idx + p + L * y + L * L * zp;
+    st.id = idx + p + L * y + L * L * zp;
     // in-plane neighbours (plane-local indices); the z-neighbours share s
-    st.nb[0] = s + (p ? 0 : ln.xm0);
-    st.nb[1] = s + (p ? ln.xp1 : 0);
+    st.nb[0] = s + (p ? 0 : xm0);
+    st.nb[1] = s + (p ? xp1 : 0);
     st.nb[2] = s + ((y == 0) ? (L - 1) * HL : -HL);
     st.nb[3] = s + ((y == L - 1) ? -(L - 1) * HL : HL);
     st.nb[4] = st.nb[5] = s;
@@ -1428,7 +1445,7 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
     using V = typename R2Vec<T, S::E>::type;
     constexpr int L = LC, HL = S::HL, PLANE = S::PLANE, HALF = S::HALF, W = B / 64;
     constexpr int G = S::G, RMAX = S::RMAX, KS = S::KS, E = S::E, NQ = S::NQ, RQ = S::RQ;
-    static_assert(B % 64 == 0 && PLANE % 64 == 0 && G % HL == 0 && PLANE % E == 0 && L > RING, "two-sweep ring shape");
+    static_assert(B % 64 == 0 && PLANE % 64 == 0 && PLANE % E == 0 && L > RING, "two-sweep ring shape");
     constexpr uint32_t CB = HALF * sizeof(T);  // bytes between components
     constexpr bool FP32 = std::is_same<T, float>::value;
     const double Nd = (double)L * L * L;
@@ -1443,18 +1460,38 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
     T *const gsp = g.sp;
 
     if (g.active && fresh) init_path<T, B>(gsp, nullptr, nullptr, L, tid, g.path, g.key0, g.key1, g.ctr3, in.init);
-    Ring2Lane ln;
+    Ring2Lane<RMAX> ln;
     {
         int lane = tid;
         asm volatile("" : "+v"(lane));  // not hoisted out of a persistent kernel's item loop
-        ln.r = lane % G;
-        ln.q = lane / G;
-        const int jx = ln.r % HL;
-        ln.yr = ln.r / HL;
-        ln.idx = 2 * jx;
-        ln.xm0 = (jx == 0) ? HL - 1 : -1;
-        ln.xp1 = (jx == HL - 1) ? -(HL - 1) : 1;
+        if constexpr (S::COMPACT) {
+            ln.r = lane % G;
+            ln.q = lane / G;
+            const int jx = ln.r % HL;
+            ln.yr = ln.r / HL;
+            ln.idx = 2 * jx;
+            ln.xm0 = (jx == 0) ? HL - 1 : -1;
+            ln.xp1 = (jx == HL - 1) ? -(HL - 1) : 1;
+        } else {
+#pragma unroll
+            for (int i = 0; i < RMAX; ++i) {
+                const int u = lane + B * i;
+                ln.s[i] = u - (u / PLANE) * PLANE;
+                ln.y[i] = ln.s[i] / HL;
+            }
+        }
     }
+    // the lane's site of round i in region a (a = (lane + B i) / plane)
+    auto site_of = [&](int i, int a, int &s, int &y) {
+        if constexpr (S::COMPACT) {
+            const int m = ln.q + (B / G) * i - (PLANE / G) * a;
+            s = ln.r + G * m;
+            y = ln.yr + S::DY * m;
+        } else {
+            s = ln.s[i];
+            y = ln.y[i];
+        }
+    };
     __syncthreads();
     // colour c of plane zp from device memory into registers, 16-byte groups j = tid + B jj
     auto load_plane = [&](V (&r)[RQ][3], int c, int zp) {
@@ -1533,24 +1570,24 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                     constexpr int i = decltype(ic)::value;
                     const int a = (wbase + B * i) / PLANE;  // region (wave-uniform)
                     if (a < n1) {
-                        const int m = ln.q + (B / G) * i - (PLANE / G) * a;
+                        int s, y;
+                        site_of(i, a, s, y);
                         const int stg = a == 0 ? first1 : R2_S2;
                         if constexpr (i < KS) {
                             if (stg == R2_S0) {
-                                ring2_site<T, R2_S0, LC, B>(g, ln, m, tau, (uint32_t)ks, ring, gsp, own0[i], own0[i],
+                                ring2_site<T, R2_S0, LC, B>(g, ln, s, y, tau, (uint32_t)ks, ring, gsp, own0[i], own0[i],
                                                             !two, cf, pA[0], pA[1], pA[2], pA[3], nacc);
                                 return;
                             }
                             if (stg == R2_COPY) {
                                 T *const o = ring2_slot<PLANE>(ring, 0, tau);
-                                const int s = ln.r + G * m;
                                 o[s] = own0[i][0];
                                 o[PLANE + s] = own0[i][1];
                                 o[2 * PLANE + s] = own0[i][2];
                                 return;
                             }
                         }
-                        ring2_site<T, R2_S2, LC, B>(g, ln, m, tau - 3, (uint32_t)(ks + 1), ring, gsp, own0[0],
+                        ring2_site<T, R2_S2, LC, B>(g, ln, s, y, tau - 3, (uint32_t)(ks + 1), ring, gsp, own0[0],
                                                     own0[0], false, cf, pB[0], pB[1], pB[2], pB[3], nacc);
                     }
                 });
@@ -1561,7 +1598,8 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                     unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
                         constexpr int i = decltype(ic)::value;
                         if ((wbase + B * i) / PLANE == a3) {
-                            const int s = ln.r + G * (ln.q + (B / G) * i - (PLANE / G) * a3);
+                            int s, y;
+                            site_of(i, a3, s, y);
                             own3[i][0] = src[s];
                             own3[i][1] = src[PLANE + s];
                             own3[i][2] = src[2 * PLANE + s];
@@ -1592,12 +1630,13 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                     constexpr int i = decltype(ic)::value;
                     const int a = (wbase + B * i) / PLANE;
                     if (a < n2) {
-                        const int m = ln.q + (B / G) * i - (PLANE / G) * a;
+                        int s, y;
+                        site_of(i, a, s, y);
                         if ((a == 0 ? first2 : R2_S3) == R2_S1)
-                            ring2_site<T, R2_S1, LC, B>(g, ln, m, tau - 1, (uint32_t)ks, ring, gsp, own3[i], zm3[i],
+                            ring2_site<T, R2_S1, LC, B>(g, ln, s, y, tau - 1, (uint32_t)ks, ring, gsp, own3[i], zm3[i],
                                                         !two || tau - 1 <= 2, cf, pA[0], pA[1], pA[2], pA[3], nacc);
                         else
-                            ring2_site<T, R2_S3, LC, B>(g, ln, m, tau - 4, (uint32_t)(ks + 1), ring, gsp, own3[i],
+                            ring2_site<T, R2_S3, LC, B>(g, ln, s, y, tau - 4, (uint32_t)(ks + 1), ring, gsp, own3[i],
                                                         zm3[i], false, cf, pB[0], pB[1], pB[2], pB[3], nacc);
                     }
                 });
@@ -1610,7 +1649,8 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                     unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
                         constexpr int i = decltype(ic)::value;
                         if ((wbase + B * i) / PLANE == a3) {
-                            const int s = ln.r + G * (ln.q + (B / G) * i - (PLANE / G) * a3);
+                            int s, y;
+                            site_of(i, a3, s, y);
                             zm3[i][0] = src[s];
                             zm3[i][1] = src[PLANE + s];
                             zm3[i][2] = src[2 * PLANE + s];
@@ -2207,8 +2247,7 @@ constexpr int BATCH_B = 512;
     X(float, 32, 512, 512, FLAT, PL_RING, "f32-ring-L32-g512")        \
     X(float, 64, 1024, 1024, FLAT, PL_HRING, "f32-hring-L64-g1024")   \
     X(float, 48, 768, 768, FLAT, PL_RING2, "f32-ring2-L48-g768")      \
-    X(float, 48, 960, 960, FLAT, PL_RING2, "f32-ring2-L48-g960")      \
-    X(float, 48, 576, 576, FLAT, PL_RING2, "f32-ring2-L48-g576")      \
+    X(float, 48, 1024, 1024, FLAT, PL_RING2, "f32-ring2-L48-g1024")   \
     X(float, 32, 512, 512, FLAT, PL_RING2, "f32-ring2-L32-g512")      \
     X(float, 24, 512, 512, FLAT, PL_MEM, "f32-hbm-L24-g512")          \
     X(float, 32, 512, 512, COLZ, PL_MEM, "f32-hbm-L32-g512")          \
@@ -2589,8 +2628,7 @@ static const Variant k_variants[] = {
     MMC_RES(float, 16, 256, 256, FLAT, PL_HRING, "f32-hring-L16-b256")
     // FP32, spins in device memory, two sweeps per pass through a ring of z-planes in LDS
     MMC_RES(float, 48, 768, 768, FLAT, PL_RING2, "f32-ring2-L48-b768")
-    MMC_RES(float, 48, 960, 960, FLAT, PL_RING2, "f32-ring2-L48-b960")
-    MMC_RES(float, 48, 576, 576, FLAT, PL_RING2, "f32-ring2-L48-b576")
+    MMC_RES(float, 48, 1024, 1024, FLAT, PL_RING2, "f32-ring2-L48-b1024")
     MMC_RES(float, 32, 512, 512, FLAT, PL_RING2, "f32-ring2-L32-b512")
     MMC_RES(float, 16, 128, 128, FLAT, PL_RING2, "f32-ring2-L16-b128")
     // FP32, spins in device memory, z-pipelined window in LDS

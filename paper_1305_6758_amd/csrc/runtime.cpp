@@ -729,10 +729,11 @@ int mmc_tune(mmc_ctx *c)
                 }
     }
     if (c->sweeps_done) return fail(MMC_ESTATE, "tuning needs a context that has not run yet");
-    // ~0.2 G updates per candidate, in whole passes of every window depth (1, 2, 3 sweeps): a
-    // short last pass would charge a window variant a pipeline fill the long run does not pay
+    // ~1 G updates per candidate (a few ms: shorter trials were swayed by clock ramps), in whole
+    // passes of every window depth (1, 2, 3 sweeps): a short last pass would charge a window
+    // variant a pipeline fill the long run does not pay
     const double per_sweep = (double)in.L * in.L * in.L * in.n_paths;
-    const int sweeps = 6 * (int)ceil(std::min(64.0, std::max(2.0, 2e8 / per_sweep)) / 6.0);
+    const int sweeps = 6 * (int)ceil(std::min(64.0, std::max(2.0, 1e9 / per_sweep)) / 6.0);
     int best = cand[0];
     double best_ms = 1e30;
     // the candidates write the workspace: with caller memory bound, they wait for the work
@@ -741,7 +742,7 @@ int mmc_tune(mmc_ctx *c)
     if (rc_order) return rc_order;
     for (int i : cand) {
         time_single_candidate(c, i, 1);  // warm-up (code load)
-        const double ms = time_single_candidate(c, i, sweeps);
+        const double ms = std::min(time_single_candidate(c, i, sweeps), time_single_candidate(c, i, sweeps));
         if (ms < best_ms) {
             best_ms = ms;
             best = i;
@@ -1330,7 +1331,7 @@ static void batch_plan(mmc_ctx *c)
     c->ready = false;
 }
 
-// Kernel time (ms, best of two graph launches) of batch variant var on a trial batch: one
+// Kernel time (ms, best of three graph launches) of batch variant var on a trial batch: one
 // instance like proto with n_trial paths and `sweeps` measured sweeps, in a context of its own.
 static double batch_time_candidate(const mmc_ctx *c, const Instance &proto, int var, int n_trial, int sweeps)
 {
@@ -1351,7 +1352,7 @@ static double batch_time_candidate(const mmc_ctx *c, const Instance &proto, int 
     double best = 1e30;
     if (ensure_device(t) == MMC_OK) {
         batch_plan(t);
-        for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < 3; ++rep) {
             if (mmc_batch_run(t) != MMC_OK) {
                 best = 1e30;
                 break;
@@ -1365,7 +1366,8 @@ static double batch_time_candidate(const mmc_ctx *c, const Instance &proto, int 
 
 // The batch's autotuner: for each L among the instances that are not pinned, every batch
 // variant that fits (placement, LDS budget; specific and generic site maps) runs a trial
-// batch of about 2e8 updates at that L and the fastest is taken for all of them. Choices are
+// batch of about 1e9 updates at that L (best of three runs) and the fastest is taken for all
+// of them. Choices are
 // cached per (device, precision, L, path count) like the single-instance tuner's.
 static int batch_tune(mmc_ctx *c)
 {
@@ -1400,7 +1402,7 @@ static int batch_tune(mmc_ctx *c)
             }
             const int n_trial = (int)std::min<long long>(paths, most);
             const double per_sweep = (double)L * L * L * n_trial;
-            const int sweeps = 6 * (int)ceil(std::min(64.0, std::max(6.0, 2e8 / per_sweep)) / 6.0);
+            const int sweeps = 6 * (int)ceil(std::min(64.0, std::max(6.0, 1e9 / per_sweep)) / 6.0);
             double best_ms = 1e30;
             for (int v : cand) {
                 const double ms = batch_time_candidate(c, c->inst[kv.second[0]], v, n_trial, sweeps);
