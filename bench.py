@@ -115,9 +115,10 @@ def measured_traffic(workload, kernel="k_batch_f32", plan=None):
 # update, read and written per colour-1 update), 24 for the x/y split (as the colour split,
 # plus colour 0's z: read and written per colour-0 update, read once per colour-1 update);
 # LDS-resident lattices (and windows, whose traffic depends on the pass length) move none here.
-BYTES_PER_UPDATE = {"-hbm-": 36.0, "-split-": 18.0, "-splitxy-": 24.0, "-ring-": None, "-hring-": None}
+BYTES_PER_UPDATE = {"-hbm-": 36.0, "-split-": 18.0, "-splitxy-": 24.0, "-ring-": None, "-hring-": None,
+                    "-ring2-": None}
 BYTES_PER_UPDATE_BY_KIND = {"device-memory": 36, "split": 18, "splitxy": 24, "ring": "24 + 24/L",
-                            "half ring": "24 + 12/L"}
+                            "half ring": "24 + 12/L", "two-sweep ring": "12 + 36/L + 24/64"}
 
 
 def ring_bytes_per_update(L, half=False):
@@ -125,6 +126,14 @@ def ring_bytes_per_update(L, half=False):
     (12 (2L + 4) / (2L) B per update) and writes every site once (12 B); the half ring reads
     only colour 0's two planes twice (colour 1 once, from device memory through the L2)."""
     return 12.0 * (2 * L + (2 if half else 4)) / (2 * L) + 12.0
+
+
+def ring2_bytes_per_update(L, renorm_every=64):
+    """The two-sweep ring, per pass of two sweeps (2 L^3 updates): reads 2L + 8 half-planes
+    (each once, plus the wrap-around reloads) and writes 2L + 4, 12 L^2 / 2 B each, i.e.
+    12 (1 + 3/L) B per update; plus the in-place renormalisation (every site read and written
+    once every renorm_every sweeps)."""
+    return 12.0 * (1.0 + 3.0 / L) + 24.0 / renorm_every
 
 
 def device_memory_bytes(instances, plan):
@@ -142,8 +151,9 @@ def device_memory_bytes(instances, plan):
                 upd = p * L ** 3 * (nt + nm)
                 upd_of[k] += upd
                 total += upd * (ring_bytes_per_update(L, k == "-hring-") if k in ("-ring-", "-hring-")
-                                else BYTES_PER_UPDATE[k])
-    return total, upd_of["-hbm-"] + upd_of["-ring-"] + upd_of["-hring-"], upd_of["-split-"] + upd_of["-splitxy-"]
+                                else ring2_bytes_per_update(L) if k == "-ring2-" else BYTES_PER_UPDATE[k])
+    return (total, upd_of["-hbm-"] + upd_of["-ring-"] + upd_of["-hring-"] + upd_of["-ring2-"],
+            upd_of["-split-"] + upd_of["-splitxy-"])
 
 
 def log(*a):
