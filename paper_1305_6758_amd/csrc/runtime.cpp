@@ -1242,7 +1242,8 @@ static void batch_plan(mmc_ctx *c)
     c->fused_refused = false;
     // the fused kernel, when asked for and every variant has a member in it (a tuned variant
     // without a member is replaced by the member of the same side and placement, e.g. the
-    // plane ring's 1024-lane form for its 768-lane one; pinned ones stay); AUTO runs
+    // plane ring's 1024-lane form for its 768-lane one, else by any member of the same side:
+    // every variant leaves the same spins and accept counts; pinned ones stay); AUTO runs
     // per-variant launches
     const int mode = c->cfg.batch_launch;
     bool members = true;
@@ -1250,7 +1251,10 @@ static void batch_plan(mmc_ctx *c)
     for (size_t i = 0; i < c->inst.size(); ++i) {
         Instance &in = c->inst[i];
         in.member = mmc::fused_member(c->fp64, vs[in.variant].name);
-        if (in.member < 0 && !in.pinned) like[i] = mmc::fused_member_like(c->fp64, in.L, vs[in.variant].lds);
+        if (in.member < 0 && !in.pinned) {
+            like[i] = mmc::fused_member_like(c->fp64, in.L, vs[in.variant].lds);
+            for (int pl = 0; like[i] < 0 && pl <= LDS_RING2; ++pl) like[i] = mmc::fused_member_like(c->fp64, in.L, pl);
+        }
         members = members && (in.member >= 0 || like[i] >= 0);
     }
     if (mode == MMC_BATCH_FUSED && !members) c->fused_refused = true;
