@@ -116,8 +116,10 @@ typedef enum {
 
 /* How a batch runs (mmc_config.batch_launch). FUSED: one persistent kernel for the whole batch,
  * whose workgroups take (instance, path group) items from one queue, largest first, and run
- * each with the code of the instance's variant (FP32; the variants of L = 8, 12, 16, 20, 24,
- * 30, 32, 48 the tuner picks by default have a member in it; results as with PER_VARIANT).
+ * each with the code of the instance's variant (FP32; L = 8, 12, 16, 20, 24, 30, 32, 48 have a
+ * member in it; a tuned variant without one runs as a member of its side, which leaves the
+ * same spins and accept counts, e.g. the two-sweep rings as the L = 32 x/y split and the
+ * L = 48 plane ring; otherwise results as with PER_VARIANT).
  * PER_VARIANT: one persistent kernel per variant in use, each with its own queue, side by side
  * in the captured graph. AUTO (default): PER_VARIANT. The fused kernel holds one 1024-lane
  * workgroup per CU whenever a device-memory member is in the batch (its LDS sets the size), so
