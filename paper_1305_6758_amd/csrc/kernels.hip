@@ -1356,13 +1356,16 @@ __device__ __forceinline__ T *ring2_slot(T *ring, int c, int v)
     return c ? ring + 3 * PLANE * (R2_SLOTS0 + (v + R2_SLOTS1) % R2_SLOTS1) : ring + 3 * PLANE * ((v + R2_SLOTS0) % R2_SLOTS0);
 }
 
-// One Metropolis attempt of stage ST (colour ST & 1) of the two-sweep ring at the lane's site
-// m of virtual plane v, sweep k. own_r: the spin when stage 0 or 3 takes it from registers;
-// zm_r: stage 3's neighbour below (registers); wglob: stage 0 / 1 also writes accepted moves
-// to device memory.
+// One Metropolis attempt of stage ST (colour ST & 1) of the two-sweep ring at the lane's site s
+// (row y) of virtual plane v, sweep k. own, oth, othm, othp: the LDS slots of the stage's
+// colour in plane v and of the other colour in planes v, v - 1, v + 1 (the caller's per-step
+// slot pointers); own_r: the spin when stage 0 or 3 takes it from registers; zm_r: stage 3's
+// neighbour below (registers; its othm is not read); wglob: stage 0 / 1 also writes accepted
+// moves to device memory.
 template <typename T, int ST, int LC, int B, typename Lane>
 __device__ __forceinline__ void ring2_site(const GroupCtx<T> &g, const Lane &ln, int s, int y, int v, uint32_t k,
-                                           T *ring, T *gsp, const T (&own_r)[3], const T (&zm_r)[3], bool wglob,
+                                           T *own, const T *oth, const T *othm, const T *othp, T *gsp,
+                                           const T (&own_r)[3], const T (&zm_r)[3], bool wglob,
                                            const Coef<T> &cf, T &pe, T &pmx, T &pmy, T &pmz,
                                            unsigned long long &nacc)
 {
@@ -1390,10 +1393,6 @@ __device__ __forceinline__ void ring2_site(const GroupCtx<T> &g, const Lane &ln,
     st.nb[2] = s + ((y == 0) ? (L - 1) * HL : -HL);
     st.nb[3] = s + ((y == L - 1) ? -(L - 1) * HL : HL);
     st.nb[4] = st.nb[5] = s;
-    T *const own = ring2_slot<PLANE>(ring, C, v);
-    const T *const oth = ring2_slot<PLANE>(ring, 1 - C, v);
-    const T *const othm = ring2_slot<PLANE>(ring, 1 - C, v - 1);
-    const T *const othp = ring2_slot<PLANE>(ring, 1 - C, v + 1);
     // this colour in device memory, indexed from each component's start: zb the first site of
     // plane zp
     T *const gown = gsp + C * 3 * HALF;
@@ -1550,8 +1549,21 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
         const int nsteps = two ? L + 7 : L + 2, c1_last = two ? L + 2 : L, c0_last = two ? L + 3 : L + 1;
         T pA[4] = {T(0), T(0), T(0), T(0)}, pB[4] = {T(0), T(0), T(0), T(0)};  // partials of sweeps ks, ks + 1
         T own3[RMAX][3], zm3[RMAX][3];  // stage 3's own spins and neighbours below
+        int i0 = 0, i1 = 0;  // tau mod R2_SLOTS0, tau mod R2_SLOTS1
 #pragma unroll 1
         for (int tau = 0; tau < nsteps; ++tau) {
+            // the step's slots, from the running indices (no division per update): colour 0 of
+            // plane tau - d (d = 0 .. 4), colour 1 of plane tau - d (d = -1 .. 4)
+            auto c0s = [&](int d) { int j = i0 - d; j += j < 0 ? R2_SLOTS0 : 0; return ring + 3 * PLANE * j; };
+            auto c1s = [&](int d) {
+                int j = i1 - d;
+                j += j < 0 ? R2_SLOTS1 : 0;
+                j -= j >= R2_SLOTS1 ? R2_SLOTS1 : 0;
+                return ring + 3 * PLANE * (R2_SLOTS0 + j);
+            };
+            T *const c0_0 = c0s(0), *const c0_1 = c0s(1), *const c0_2 = c0s(2), *const c0_3 = c0s(3), *const c0_4 = c0s(4);
+            T *const c1_p1 = c1s(-1), *const c1_0 = c1s(0), *const c1_1 = c1s(1), *const c1_2 = c1s(2),
+                     *const c1_3 = c1s(3), *const c1_4 = c1s(4);
             // colour 1 of virtual plane tau + 2 (stored in phase 2) and colour 0 of plane tau + 1
             // (the next step's first stage's own spins) into registers
             const bool h1 = tau + 2 <= c1_last, h0 = tau + 1 <= c0_last;
@@ -1575,26 +1587,26 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                         const int stg = a == 0 ? first1 : R2_S2;
                         if constexpr (i < KS) {
                             if (stg == R2_S0) {
-                                ring2_site<T, R2_S0, LC, B>(g, ln, s, y, tau, (uint32_t)ks, ring, gsp, own0[i], own0[i],
-                                                            !two, cf, pA[0], pA[1], pA[2], pA[3], nacc);
+                                ring2_site<T, R2_S0, LC, B>(g, ln, s, y, tau, (uint32_t)ks, c0_0, c1_0, c1_1, c1_p1, gsp,
+                                                            own0[i], own0[i], !two, cf, pA[0], pA[1], pA[2], pA[3], nacc);
                                 return;
                             }
                             if (stg == R2_COPY) {
-                                T *const o = ring2_slot<PLANE>(ring, 0, tau);
+                                T *const o = c0_0;
                                 o[s] = own0[i][0];
                                 o[PLANE + s] = own0[i][1];
                                 o[2 * PLANE + s] = own0[i][2];
                                 return;
                             }
                         }
-                        ring2_site<T, R2_S2, LC, B>(g, ln, s, y, tau - 3, (uint32_t)(ks + 1), ring, gsp, own0[0],
-                                                    own0[0], false, cf, pB[0], pB[1], pB[2], pB[3], nacc);
+                        ring2_site<T, R2_S2, LC, B>(g, ln, s, y, tau - 3, (uint32_t)(ks + 1), c0_3, c1_3, c1_4, c1_2,
+                                                    gsp, own0[0], own0[0], false, cf, pB[0], pB[1], pB[2], pB[3], nacc);
                     }
                 });
                 if (s3) {
                     // stage 3's own spins (colour 1 of plane tau - 4), before phase 2 replaces them
                     const int a3 = s1 ? 1 : 0;
-                    const T *const src = ring2_slot<PLANE>(ring, 1, tau - 4);
+                    const T *const src = c1_4;
                     unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
                         constexpr int i = decltype(ic)::value;
                         if ((wbase + B * i) / PLANE == a3) {
@@ -1609,7 +1621,7 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                 if (two && tau >= 4 && tau <= L + 5) {
                     // colour 0 of plane tau - 4 back to device memory (final for this pass)
                     const int v = tau - 4, zp = v < L ? v : v - L;
-                    const T *const src = ring2_slot<PLANE>(ring, 0, v);
+                    const T *const src = c0_4;
 #pragma unroll
                     for (int jj = 0; jj < RQ; ++jj) {
                         const int j = tid + B * jj;
@@ -1633,19 +1645,21 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                         int s, y;
                         site_of(i, a, s, y);
                         if ((a == 0 ? first2 : R2_S3) == R2_S1)
-                            ring2_site<T, R2_S1, LC, B>(g, ln, s, y, tau - 1, (uint32_t)ks, ring, gsp, own3[i], zm3[i],
-                                                        !two || tau - 1 <= 2, cf, pA[0], pA[1], pA[2], pA[3], nacc);
+                            ring2_site<T, R2_S1, LC, B>(g, ln, s, y, tau - 1, (uint32_t)ks, c1_1, c0_1, c0_2, c0_0, gsp,
+                                                        own3[i], zm3[i], !two || tau - 1 <= 2, cf, pA[0], pA[1], pA[2],
+                                                        pA[3], nacc);
                         else
-                            ring2_site<T, R2_S3, LC, B>(g, ln, s, y, tau - 4, (uint32_t)(ks + 1), ring, gsp, own3[i],
-                                                        zm3[i], false, cf, pB[0], pB[1], pB[2], pB[3], nacc);
+                            ring2_site<T, R2_S3, LC, B>(g, ln, s, y, tau - 4, (uint32_t)(ks + 1), c1_4, c0_4, c0_4, c0_3,
+                                                        gsp, own3[i], zm3[i], false, cf, pB[0], pB[1], pB[2], pB[3],
+                                                        nacc);
                     }
                 });
-                if (h1) store_half(r1, ring2_slot<PLANE>(ring, 1, tau + 2));
+                if (h1) store_half(r1, c1_4);  // (plane tau + 2 takes the slot of tau - 4)
                 // the next step's stage 3 neighbours below: colour 0 of plane tau - 4, in its slot
                 // until phase 1 of the next step (this lane's stage-3 updates above have read zm3)
                 if (two && tau + 1 >= 7 && tau + 1 < L + 7) {
                     const int a3 = (tau + 1 >= 2 && tau + 1 < L + 2) ? 1 : 0;
-                    const T *const src = ring2_slot<PLANE>(ring, 0, tau - 4);
+                    const T *const src = c0_4;
                     unroll_each(std::make_integer_sequence<int, RMAX>{}, [&](auto ic) {
                         constexpr int i = decltype(ic)::value;
                         if ((wbase + B * i) / PLANE == a3) {
@@ -1665,6 +1679,8 @@ __device__ __forceinline__ void path_sweeps_ring2(const GroupCtx<T> &g, const In
                 own0[i][1] = own0n[i][1];
                 own0[i][2] = own0n[i][2];
             }
+            i0 = i0 == R2_SLOTS0 - 1 ? 0 : i0 + 1;
+            i1 = i1 == R2_SLOTS1 - 1 ? 0 : i1 + 1;
         }
         ring_measure<T, W>(g, in, ks, k1, Nd, tid, pA[0], pA[1], pA[2], pA[3]);
         if (two) {
