@@ -26,7 +26,8 @@ U32 = 2.0 ** -24
 TOL_PROP = 8 * U32  # absolute error bound of an FP32 proposal's x and y components
 
 # FP32 single-instance variants by lattice side (every compiled FP32 kernel form: LDS,
-# colour split, x/y split, device memory, LDS window, device-memory window, generic maps)
+# colour split, x/y split, device memory, LDS window, device-memory window, plane rings of
+# one and two sweeps per pass, half ring, generic maps)
 SINGLE_VARIANTS = [
     (8, "f32-lds-L8-g64-b256"), (8, "f32-lds-L8-g128-b256"), (8, "f32-lds-L8-g256-b256"),
     (10, "f32-lds-L10-g256-b256"), (12, "f32-lds-L12-g128-b256"), (12, "f32-lds-L12-g256-b256"),
@@ -40,12 +41,14 @@ SINGLE_VARIANTS = [
     (32, "f32-win-L32-d2-b1024"), (32, "f32-gwin-L32-d2-b1024"), (48, "f32-gwin-L48-d1-b1024"),
     (16, "f32-ring-L16-b256"), (32, "f32-ring-L32-b512"), (48, "f32-ring-L48-b1024"), (48, "f32-ring-L48-b768"),
     (16, "f32-hring-L16-b256"), (48, "f32-hring-L48-b1024"), (64, "f32-hring-L64-b1024"), (64, "f32-hring-L64-b768"),
+    (16, "f32-ring2-L16-b128"), (32, "f32-ring2-L32-b512"), (48, "f32-ring2-L48-b768"), (48, "f32-ring2-L48-b1024"),
 ]
 
 # the batch variants the uneven batch of lattice sides 8 ... 48 runs on
 BATCH_VARIANTS = {8: "f32-lds-L8-g64", 12: "f32-lds-L12-g256", 16: "f32-lds-L16-g512",
                   24: "f32-split-L24-g1024", 32: "f32-splitxy-L32-g1024", 48: "f32-hbm-L48-g512"}
-BATCH_SETS = [BATCH_VARIANTS, {**BATCH_VARIANTS, 48: "f32-ring-L48-g1024"}, {**BATCH_VARIANTS, 48: "f32-ring-L48-g768"}]
+BATCH_SETS = [BATCH_VARIANTS, {**BATCH_VARIANTS, 48: "f32-ring-L48-g1024"}, {**BATCH_VARIANTS, 48: "f32-ring-L48-g768"},
+              {**BATCH_VARIANTS, 32: "f32-ring2-L32-g512", 48: "f32-ring2-L48-g1024"}]
 
 
 def lanes_of(name):
@@ -122,10 +125,11 @@ def test_infinite_temperature_spins_elementwise(L, variant):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("variants", BATCH_SETS, ids=["hbm48", "ring48-g1024", "ring48-g768"])
+@pytest.mark.parametrize("variants", BATCH_SETS, ids=["hbm48", "ring48-g1024", "ring48-g768", "ring2-32-48"])
 def test_infinite_temperature_batch_elementwise(variants):
     """The batch kernels of the uneven batch's lattice sides (8, 12, 16 in LDS, 24 colour
-    split, 32 x/y split, 48 device memory or plane ring), pinned by name: at T = inf after one
+    split, 32 x/y split or two-sweep ring, 48 device memory, plane ring or two-sweep ring),
+    pinned by name: at T = inf after one
     and three sweeps the accept counts are exact and every path's final magnetisation and
     energy equal the oracle's (same instance ids) within the FP32 summation bounds."""
     from paper_1305_6758_amd import mmc
@@ -154,7 +158,8 @@ def test_infinite_temperature_batch_elementwise(variants):
 # variants of the uneven batch's sides with a single-instance form whose spins can be read
 FLIP_VARIANTS = [(8, "f32-lds-L8-g64-b256", 48), (12, "f32-lds-L12-g256-b256", 16), (16, "f32-lds-L16-g512-b512", 8),
                  (24, "f32-split-L24-g1024-b1024", 4), (32, "f32-splitxy-L32-g1024-b1024", 2),
-                 (48, "f32-hbm-L48-g512-b512", 1), (48, "f32-ring-L48-b1024", 1)]
+                 (48, "f32-hbm-L48-g512-b512", 1), (48, "f32-ring-L48-b1024", 1), (32, "f32-ring2-L32-b512", 2),
+                 (48, "f32-ring2-L48-b1024", 1)]
 
 
 @pytest.mark.gpu
