@@ -1,11 +1,11 @@
 """Checkpoint and resume on the engines beyond the default ones (2-D Ising, LDS and
-device-memory windows, the split placement): a run of a few sweeps, saved
+device-memory windows, the split placement, the two-sweep ring): a run of a few sweeps, saved
 to a file, loaded into a new context and finished equals an uninterrupted run with the same
 kernel variant (the checkpoint records the variant's name). Spins and accept counts are
 exact everywhere; per-path sums are exact where the reduction order does not depend on where
 a run is split (the 2-D Ising model's integer sums; the split placement's per-sweep sums),
-else equal to rounding (the window kernels sum a pass's partials in an order set by the pass
-length)."""
+else equal to rounding (the window kernels and the rings sum a pass's partials in an order set
+by the pass length)."""
 import numpy as np
 import pytest
 
@@ -28,6 +28,10 @@ CASES = [
     ("split-fp32", 24, 1.2, 2, 5, 6, "fp32", 0, "f32-split-L24-g1024-b1024", 5, 7, 0.0),
     ("split-fp64", 10, 1.3, 3, 4, 5, "fp64", 0, "f64-split-any-g512-b512", 0, 3, 0.0),
     ("splitxy-fp32", 32, 1.4, 2, 3, 4, "fp32", 0, "f32-splitxy-L32-g1024-b1024", 3, 4, 0.0),
+    # the two-sweep ring, resumed at an odd sweep (its passes pair other sweeps than the
+    # uninterrupted run's)
+    ("ring2-fp32", 32, 1.4, 2, 4, 5, "fp32", 0, "f32-ring2-L32-b512", 4, 3, 1e-5),
+    ("ring2-fp64", 16, 1.3, 3, 4, 5, "fp64", 0, "f64-ring2-L16-b128", 0, 5, 1e-14),
 ]
 
 
