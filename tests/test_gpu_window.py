@@ -184,3 +184,31 @@ def test_two_sweep_ring_batch_L32_equals_device_memory_batch():
         assert np.array_equal(got[1][i]["n_accept"], got[0][i]["n_accept"]), i
         for k in ("e_mean", "absm_mean", "final_e"):
             assert max_abs_diff(got[1][i][k], got[0][i][k]) < 1e-5, (i, k)
+
+
+def test_two_sweep_ring_fp64_edge_cases():
+    """The FP64 two-sweep ring at the edges, against the oracle to 1e-12: negative J, infinite
+    temperature (every move accepted), no measured sweeps (NaN means), a nonzero instance id
+    with a 64-bit seed; odd and even sweep counts (a last one-sweep pass or none)."""
+    import math
+    v = "f64-ring2-L16-b128"
+    say("case two-sweep ring edges J<0")
+    ora = oracle_run(16, 0.9, 3, 4, 4, J=-1.0)
+    eng, _, _, plan, _ = engine_run(16, 0.9, 3, 4, 4, J=-1.0, placement=PLACE_WINDOW, variant=v)
+    assert plan.startswith(v), plan
+    assert_results_close(eng, ora, TOL64)
+    say("case two-sweep ring edges T=inf")
+    ora = oracle_run(16, math.inf, 3, 2, 3)
+    eng, *_ = engine_run(16, math.inf, 3, 2, 3, placement=PLACE_WINDOW, variant=v)
+    assert_results_close(eng, ora, TOL64)
+    assert np.all(eng["n_accept"] == 16 ** 3 * 5)
+    say("case two-sweep ring edges n_meas=0")
+    ora = oracle_run(16, 1.1, 3, 5, 0)
+    eng, *_ = engine_run(16, 1.1, 3, 5, 0, placement=PLACE_WINDOW, variant=v)
+    assert np.all(np.isnan(eng["e_mean"]))
+    assert_results_close(eng, ora, TOL64)
+    say("case two-sweep ring edges instance/seed")
+    ora = oracle_run(16, 1.4, 3, 2, 2, seed=0xDEADBEEF12345, instance_id=77)
+    eng, *_ = engine_run(16, 1.4, 3, 2, 2, seed=0xDEADBEEF12345, instance_id=77, placement=PLACE_WINDOW,
+                         variant=v)
+    assert_results_close(eng, ora, TOL64)
